@@ -1,0 +1,228 @@
+"""Pins of the FP64 oracle's DCFR, average strategy and best response.
+
+The CFR pins are: a tiny game whose first three DCFR iterations were worked
+out by hand from the paper's equations (DFCR_REG, RM, DFCR_AVG); brute-force
+best responses over all pure strategies; the minimax bound and shrinking
+exploitability that the convergence theorems guarantee; and structural
+invariants (simplex, forced moves, the inherited point difference not
+entering the utility).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def padded_tree(fanouts_l1, leaves):
+    """Alex picks among len(fanouts_l1) actions at level 0, Bob then picks
+    among fanouts_l1[i]; levels 2..8 are forced single-child chains so the
+    tree has the 8-ply shape of a round."""
+    n1 = len(fanouts_l1)
+    n2 = sum(fanouts_l1)
+    n = [1, n1] + [n2] * 7
+    cb = [np.array([0, n1], np.int32),
+          np.concatenate([[0], np.cumsum(fanouts_l1)]).astype(np.int32)]
+    cb += [np.arange(n2 + 1, dtype=np.int32)] * 6
+    return n, cb, np.asarray(leaves, np.float64)
+
+
+def test_dcfr_three_iterations_by_hand():
+    # Alex: a1, a2; Bob after a1: b1 -> 3, b2 -> -1; after a2: b1 -> 0, b2 -> 2.
+    # Textbook regret matching (positive part, uniform when none is positive),
+    # DCFR alpha=1.5, beta=0, gamma=2.  Hand computation (t = 1, 2, 3):
+    #   t=1: u(a1)=1, u(a2)=1, u=1.  R(a1:b)=(-1,1), R(a2:b)=(1/2,-1/2), R(root)=(0,0)
+    #   t=2: sigma(a1:b)=(0,1), sigma(a2:b)=(1,0), sigma(root)=(1/2,1/2);
+    #        u(a1)=-1, u(a2)=0, u=-1/2; every discount is 1/2 at t=2;
+    #        R(a1:b)=(-5/2,1/2), R(a2:b)=(1/4,-5/4), R(root)=(-1/2,1/2)
+    #   t=3: sigma(root)=(0,1); u=0; with c = 2^1.5/(2^1.5+1):
+    #        R(a1:b)=(-5/4, c/2), R(a2:b)=(c/4, -21/8), R(root)=(-5/4, c/2)
+    #   Sbar(root)=(5/18, 23/18) -> avg (5/28, 23/28); Sbar(a1:b)=(1/18, 3/2)
+    #   -> (1/28, 27/28); Sbar(a2:b)=(3/2, 1/18) -> (27/28, 1/28); vacc = 1/2.
+    n, cb, leaves = padded_tree([2, 2], [3, -1, 0, 2])
+    c = oracle.CFR(n, cb, leaves)
+    c.run(3, oracle.Params(rm_mode=oracle.RM_POSITIVE))
+    cc = 2 ** 1.5 / (2 ** 1.5 + 1)
+    np.testing.assert_allclose(c.get(oracle.CF_R, 1), [-1.25, cc / 2], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_R, 2), [-1.25, cc / 2, cc / 4, -2.625], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SBAR, 1), [5 / 18, 23 / 18], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SBAR, 2), [1 / 18, 1.5, 1.5, 1 / 18], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA_BAR, 1), [5 / 28, 23 / 28], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA_BAR, 2),
+                               [1 / 28, 27 / 28, 27 / 28, 1 / 28], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA, 1), [0, 1], atol=0)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA, 2), [0, 1, 1, 0], atol=0)
+    np.testing.assert_allclose(c.get(oracle.CF_VACC), [0.5], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_U, 0), [0.0], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_U, 1), [-1.0, 0.0], atol=1e-14)
+
+
+def test_floor_rule_matches_textbook_when_regrets_are_large():
+    # The executed rule max(R, 1e-8)/sum differs from the positive-part rule
+    # only by terms of order 1e-8.
+    n, cb, leaves = padded_tree([2, 2], [3, -1, 0, 2])
+    a = oracle.CFR(n, cb, leaves)
+    b = oracle.CFR(n, cb, leaves)
+    a.run(3, oracle.Params(rm_mode=oracle.RM_POSITIVE))
+    b.run(3, oracle.Params(rm_mode=oracle.RM_FLOOR))
+    for l in (1, 2):
+        np.testing.assert_allclose(a.get(oracle.CF_SIGMA_BAR, l), b.get(oracle.CF_SIGMA_BAR, l),
+                                   atol=1e-7)
+
+
+def random_tree(rng, fan):
+    """Random 8-level tree with the given max fan-out per level."""
+    n = [1]
+    cb = []
+    for l in range(8):
+        k = rng.integers(1, fan[l] + 1, size=n[-1])
+        cb.append(np.concatenate([[0], np.cumsum(k)]).astype(np.int32))
+        n.append(int(k.sum()))
+    leaves = rng.integers(-6, 7, size=n[8]).astype(np.float64)
+    return n, cb, leaves
+
+
+def brute_force_br(n, cb, leaves, sigma, player):
+    """Enumerate every pure strategy of ``player`` (0 Alex maximises, 1 Bob
+    minimises) and evaluate it against ``sigma`` by plain recursion."""
+    dec = [(l, h) for l in range(8) if l % 2 == player for h in range(n[l])
+           if cb[l][h + 1] - cb[l][h] > 1]
+    choices = [range(cb[l][h + 1] - cb[l][h]) for l, h in dec]
+    best = None
+    for pick in itertools.product(*choices):
+        pure = dict(zip(dec, pick))
+
+        def val(l, h):
+            if l == 8:
+                return leaves[h]
+            b, e = cb[l][h], cb[l][h + 1]
+            if l % 2 == player:
+                j = pure.get((l, h), 0)
+                return val(l + 1, b + j)
+            return sum(sigma[l + 1][q] * val(l + 1, q) for q in range(b, e))
+
+        v = val(0, 0)
+        if best is None or (v > best if player == 0 else v < best):
+            best = v
+    return best
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_best_response_equals_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n, cb, leaves = random_tree(rng, [3, 2, 2, 2, 1, 2, 1, 1])
+    sigma = [np.ones(1)]
+    for l in range(8):
+        s = np.zeros(n[l + 1])
+        for h in range(n[l]):
+            b, e = cb[l][h], cb[l][h + 1]
+            s[b:e] = rng.dirichlet(np.ones(e - b))
+        sigma.append(s)
+    for player, mode in ((0, oracle.TV_BR_A), (1, oracle.TV_BR_B)):
+        got = oracle.tree_values(n, cb, leaves, sigma, mode)[0]
+        assert got == pytest.approx(brute_force_br(n, cb, leaves, sigma, player), abs=1e-12)
+
+
+def exploitability(n, cb, leaves, sbar):
+    br_a = oracle.tree_values(n, cb, leaves, sbar, oracle.TV_BR_A)
+    br_b = oracle.tree_values(n, cb, leaves, sbar, oracle.TV_BR_B)
+    return br_a, br_b, (br_a - br_b) / 2
+
+
+def last_round_problem(seed):
+    deck, roots = synth.last_round_roots(seed)
+    gt = oracle.GT(deck, 5, sorted({r.pool for r in roots}))
+    f = oracle.FGT(gt, roots)
+    return gt, f, f.leaf_utilities()
+
+
+@pytest.mark.parametrize("seed", [3, 11])
+def test_dcfr_converges_to_minimax(seed):
+    gt, f, leaves = last_round_problem(seed)
+    cb = f.child_begin()
+    M = oracle.tree_values(f.n, cb, leaves, None, oracle.TV_MINIMAX)
+    c = oracle.CFR(f.n, cb, leaves)
+    prev = None
+    for T in (10, 90, 900):
+        c.run(T)
+        sbar = c.sigma_bar()
+        br_a, br_b, ex = exploitability(f.n, cb, leaves, sbar)
+        v = oracle.tree_values(f.n, cb, leaves, sbar, oracle.TV_EXPECT)
+        assert np.all(ex >= -1e-12)
+        assert np.all(br_b - 1e-9 <= M) and np.all(M <= br_a + 1e-9)
+        assert np.all(np.abs(v - M) <= 2 * ex + 1e-9)
+        if prev is not None:
+            assert ex.max() <= prev + 1e-12
+        prev = ex.max()
+    assert prev < 0.05
+
+
+def test_invariants_and_inherited_difference():
+    gt, f, leaves = last_round_problem(3)
+    cb = f.child_begin()
+    c = oracle.CFR(f.n, cb, leaves)
+    c.run(50)
+    for l in range(1, 9):
+        s = c.get(oracle.CF_SIGMA, l)
+        sb = c.get(oracle.CF_SIGMA_BAR, l)
+        R = c.get(oracle.CF_R, l)
+        assert np.all(s >= 0) and np.all(sb >= 0)
+        k = np.diff(cb[l - 1])
+        par = np.repeat(np.arange(f.n[l - 1]), k)
+        np.testing.assert_allclose(np.bincount(par, s, f.n[l - 1]), 1.0, atol=1e-12)
+        np.testing.assert_allclose(np.bincount(par, sb, f.n[l - 1]), 1.0, atol=1e-12)
+        forced = (k[par] == 1)
+        assert np.all(s[forced] == 1.0) and np.all(R[forced] == 0.0)
+    # reach: full reach pi_A * pi_B sums to 1 over each level per root
+    for l in range(1, 8):
+        ra, rb = c.get(oracle.CF_REACHA, l), c.get(oracle.CF_REACHB, l)
+        root = np.arange(f.n[l])
+        for up in range(l, 0, -1):
+            root = f.get(oracle.FGT_PARENT, up)[root]
+        np.testing.assert_allclose(np.bincount(root, ra * rb, f.n[0]), 1.0, atol=1e-12)
+    # the seven roots differ only in the inherited point difference, which
+    # does not enter the utility: identical subgames, identical results
+    sizes = [f.n[l] // f.n[0] for l in range(9)]
+    for l in range(1, 9):
+        sb = c.get(oracle.CF_SIGMA_BAR, l).reshape(f.n[0], sizes[l])
+        assert np.all(sb == sb[0])
+    vacc = c.get(oracle.CF_VACC)
+    assert np.all(vacc == vacc[0])
+
+
+def test_two_round_composition():
+    # Backward round propagation (CodeSnippet CFR, equation passuputil):
+    # solve the last round, pass its root values to the previous round's
+    # leaves, solve that round; composed best responses bracket the minimax.
+    deck, roots = synth.two_round_root(3)
+    gt4 = oracle.GT(deck, 4, [roots[0].pool])
+    f4 = oracle.FGT(gt4, roots)
+    nxt = f4.get(oracle.FGT_NEXT_ROOTS)
+    roots5 = [synth.Root(int(x["pool"]), int(x["ca"]), int(x["cb"]), int(x["d"]), int(x["bonus"]))
+              for x in nxt]
+    gt5 = oracle.GT(deck, 5, sorted({r.pool for r in roots5}))
+    f5 = oracle.FGT(gt5, roots5)
+    cb5, cb4 = f5.child_begin(), f4.child_begin()
+    leaf5 = f5.leaf_utilities()
+    M5 = oracle.tree_values(f5.n, cb5, leaf5, None, oracle.TV_MINIMAX)
+    M4 = oracle.tree_values(f4.n, cb4, f4.leaf_utilities(M5), None, oracle.TV_MINIMAX)
+    prev = None
+    c5 = oracle.CFR(f5.n, cb5, leaf5)
+    for T in (20, 180):
+        c5.run(T)
+        V5 = c5.get(oracle.CF_VACC) / (c5.t - 1)
+        c4 = oracle.CFR(f4.n, cb4, f4.leaf_utilities(V5))
+        c4.run(c5.t - 1)
+        s5, s4 = c5.sigma_bar(), c4.sigma_bar()
+        bra5 = oracle.tree_values(f5.n, cb5, leaf5, s5, oracle.TV_BR_A)
+        brb5 = oracle.tree_values(f5.n, cb5, leaf5, s5, oracle.TV_BR_B)
+        bra4 = oracle.tree_values(f4.n, cb4, f4.leaf_utilities(bra5), s4, oracle.TV_BR_A)
+        brb4 = oracle.tree_values(f4.n, cb4, f4.leaf_utilities(brb5), s4, oracle.TV_BR_B)
+        assert brb4[0] - 1e-9 <= M4[0] <= bra4[0] + 1e-9
+        ex = (bra4[0] - brb4[0]) / 2
+        if prev is not None:
+            assert ex <= prev + 1e-12
+        prev = ex
+    assert prev < 0.1
