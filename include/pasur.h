@@ -1,0 +1,224 @@
+/*
+ * pasur.h -- C ABI of the MI355X (gfx950) Pasur round solver.
+ *
+ * Scope: the data-parallel hot path of "Solving Pasur Using GPU-Accelerated
+ * Counterfactual Regret Minimization" (arXiv 2508.06559): the round game
+ * tree of card states, the Unfolding Process that pairs it with inherited
+ * scores, the Between-Hand linkage to next-round roots, full-width DCFR on
+ * one round's unfolded tree, and the backward round-value propagation, plus
+ * exact best-response values used to measure exploitability.
+ *
+ * Conventions
+ *  - Every function returns 0 (PASUR_OK) or a negative pasur_status; nothing
+ *    aborts.  pasur_last_error() returns a message for the calling thread.
+ *  - "device" pointers are HIP device memory on the current device;
+ *    "host" pointers are ordinary CPU memory.  `stream` is a hipStream_t
+ *    (NULL = the null stream).  Calls that take a stream enqueue work on it
+ *    and return without waiting unless stated otherwise.
+ *  - Tree handles (pasur_gt, pasur_fgt) own their device memory; free them
+ *    with the matching *_free.  Build and unfold calls synchronise `stream`
+ *    (they read level sizes back to allocate the next level).
+ *  - Solver state (pasur_cfr_state) and output arrays are owned by the
+ *    caller.
+ *  - Results are deterministic: identical inputs give bit-identical outputs
+ *    (no floating-point atomics).
+ *
+ * Cards: index = 4*rank + suit, rank A,2..10,J,Q,K = 0..12, suit clubs,
+ * diamonds, hearts, spades = 0..3 (the paper's fixed 52-slot layout).
+ * Deck layout: deck[0..3] is the initial pool; round r (0-based) deals
+ * deck[4+8r..7+8r] to Alex and deck[8+8r..11+8r] to Bob.  A round has 8
+ * plies (levels 0..8 of its tree); Alex moves at even plies.
+ *
+ * Canonical order (the paper's unique() order is unspecified): roots
+ * ascending by (pool, bonus, ca, cb, d); level l+1 parent-major, siblings by
+ * (played card, captured-card mask); score table ascending by
+ * (bonus, ca, cb, d).
+ */
+#ifndef PASUR_H
+#define PASUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PASUR_OK = 0,
+  PASUR_E_INVAL = -1,    /* null or inconsistent argument, bad deck or roots */
+  PASUR_E_RANGE = -2,    /* round outside 0..5, t0 < 1, unknown enum value */
+  PASUR_E_OVERFLOW = -3, /* a tree level would exceed INT32_MAX nodes */
+  PASUR_E_HIP = -4,      /* HIP runtime error (text in pasur_last_error) */
+  PASUR_E_NOMEM = -5     /* device allocation failed */
+} pasur_status;
+
+typedef enum { PASUR_F32 = 0, PASUR_F64 = 1 } pasur_dtype;
+
+/* A round root: the pool at the round start and the score inherited from
+ * earlier rounds (paper tensor t_scr: Alex clubs, Bob clubs, point
+ * difference, 7-club bonus 0/1 Alex/2 Bob).  Once the bonus is decided both
+ * club counts are 0; an undecided bonus has ca, cb in 0..6. */
+typedef struct {
+  uint64_t pool;
+  int8_t ca, cb, d, bonus;
+  int32_t pad; /* must be 0 */
+} pasur_root;
+
+typedef struct pasur_gt pasur_gt;   /* round game tree of card states */
+typedef struct pasur_fgt pasur_fgt; /* unfolded (full) game tree of a round */
+
+const char *pasur_last_error(void);
+int pasur_version(void);
+
+/* ---- a1: round game tree --------------------------------------------------
+ * Section "Actions" and the capture/scoring tables of section "Pasur".
+ * Builds the game tree of round `round` from the distinct pools of
+ * `d_roots` (device, n_roots entries, strictly ascending in canonical root
+ * order; every pool a subset of the cards dealt before the round).  Level 0
+ * holds the distinct pools ascending; every node's children are its legal
+ * moves: a numeric card captures every set of pool numerics completing 11
+ * (one child each) or is laid; a Jack captures all pool cards but Queens and
+ * Kings or is laid; a Queen/King captures one same-rank pool card (one child
+ * each) or is laid.  The must-capture duty is per card.  A capture that
+ * empties the pool scores a Sur unless made with a Jack or in round 5.  In
+ * round 5 the last ply's children include the clean-up by that round's last
+ * picker.  `deck` is host memory (a permutation of 0..51).  On success
+ * *out_gt receives a new handle.  Synchronises `stream`. */
+int pasur_build_round_tree(const uint8_t deck[52], int round,
+                           const pasur_root *d_roots, int64_t n_roots,
+                           pasur_gt **out_gt, void *stream);
+int pasur_gt_sizes(const pasur_gt *gt, int64_t n[9]);
+
+typedef enum {
+  PASUR_GT_POOL = 0,        /* uint64 per node */
+  PASUR_GT_HANDS = 1,       /* uint8: bit i = Alex holds his i-th dealt card, bit 4+i Bob */
+  PASUR_GT_RS = 2,          /* int8[8]: Acl, Bcl, last picker (0/1/2), Apt, Asr, Bpt, Bsr, 0 */
+  PASUR_GT_PARENT = 3,      /* int32, levels 1..8 */
+  PASUR_GT_CHILD_BEGIN = 4, /* int32, n+1 entries, levels 0..7 */
+  PASUR_GT_ACT_CARD = 5,    /* uint8 played card, levels 1..8 */
+  PASUR_GT_ACT_CAP = 6      /* uint64 captured cards (0 = lay), levels 1..8 */
+} pasur_gt_field;
+/* Synchronous copy of one GT array of one level into host memory. */
+int pasur_gt_read(const pasur_gt *gt, int field, int level, void *host_dst);
+void pasur_gt_free(pasur_gt *gt);
+
+/* ---- a2 + a3: unfolding and between-round linkage -------------------------
+ * Sections "In-Hand Updates" (figure "Unfolding Process") and "Between-Hand
+ * Updates" (CodeSnippet BetweenHands).  FGT level 0 are the roots `d_roots`
+ * (the same device array given to pasur_build_round_tree for `gt`); the
+ * children of FGT node (g, s) are the GT children of g tagged with the same
+ * score id s, parent-major.  For rounds 0..4 every FGT leaf (t, s) links to
+ * the next-round root (pool of t, normalise(s + running score of t)); the
+ * distinct such roots, ascending, form the next round's root list.  The
+ * handle keeps per-leaf base utilities so that `gt` may be freed afterwards.
+ * Synchronises `stream`. */
+int pasur_unfold_scores(const pasur_gt *gt, const pasur_root *d_roots,
+                        int64_t n_roots, pasur_fgt **out_fgt, void *stream);
+int pasur_fgt_sizes(const pasur_fgt *fgt, int64_t n[9], int64_t *n_scores,
+                    int64_t *n_next);
+typedef enum {
+  PASUR_FGT_GT = 0,          /* int32 GT node per FGT node */
+  PASUR_FGT_SID = 1,         /* int32 score id per FGT node */
+  PASUR_FGT_PARENT = 2,      /* int32, levels 1..8 */
+  PASUR_FGT_CHILD_BEGIN = 3, /* int32, n+1 entries, levels 0..7 */
+  PASUR_FGT_SCORE_TAB = 4,   /* int8[4] per score: ca, cb, d, bonus (level ignored) */
+  PASUR_FGT_NEXT_ROOTS = 5,  /* pasur_root per next-round root (level ignored) */
+  PASUR_FGT_LINK = 6,        /* int32 per leaf: next-round root index (level ignored) */
+  PASUR_FGT_LEAF_BASE = 7    /* int16 per leaf: round points (+ bonus in round 5) */
+} pasur_fgt_field;
+int pasur_fgt_read(const pasur_fgt *fgt, int field, int level, void *host_dst);
+/* Device pointer to the next-round roots (owned by the handle, n_next
+ * entries, canonical order); NULL for round 5. */
+const pasur_root *pasur_fgt_next_roots(const pasur_fgt *fgt);
+void pasur_fgt_free(pasur_fgt *fgt);
+
+/* ---- a4: leaf utilities -----------------------------------------------------
+ * Equations final_util and passuputil: Alex's point difference at every FGT
+ * leaf.  Round 5: bonus (+7 Alex, -7 Bob, 0 none) of the combined score plus
+ * the round's points (Apt + 5 Asr) - (Bpt + 5 Bsr).  Rounds 0..4:
+ * d_V_next[link] + the round's points, with d_V_next (device, double, one
+ * value per next-round root) the next round's root values.  Writes n[8]
+ * values of type `dtype` to d_leaf (device). */
+int pasur_leaf_utilities(const pasur_fgt *fgt, const double *d_V_next,
+                         int dtype, void *d_leaf, void *stream);
+
+/* ---- a5..a10: DCFR on one round ---------------------------------------------
+ * Section "CFR Algorithm" (CodeSnippets CFR, FindReachProbability,
+ * FindUtility) with equations DFCR_REG, RM and DFCR_AVG.  Caller-owned
+ * device arrays, all of element type `dtype` except vacc:
+ *   sigma[l], R[l], Sbar[l]  levels 1..8, n[l] each (per edge);
+ *   reachA[l], reachB[l]     levels 0..7, n[l] each (pi_Alex, pi_Bob);
+ *   u[l]                     levels 0..8, n[l] each; u[8] = leaf utilities;
+ *   vacc                     double, n[0]: sum of root utilities.
+ * Arithmetic is FP64 in registers whatever `dtype` is. */
+typedef struct {
+  int dtype;
+  void *sigma[9], *R[9], *Sbar[9];
+  void *reachA[9], *reachB[9];
+  void *u[9];
+  double *vacc;
+} pasur_cfr_state;
+
+typedef enum { PASUR_DCFR = 0, PASUR_CFR_PLUS = 1, PASUR_CFR_VANILLA = 2 } pasur_variant;
+typedef enum { PASUR_RM_FLOOR = 0, PASUR_RM_POSITIVE = 1 } pasur_rm_mode;
+typedef struct {
+  int variant;  /* pasur_variant */
+  int rm_mode;  /* PASUR_RM_FLOOR: max(R, eps)/sum (the paper's executed rule);
+                   PASUR_RM_POSITIVE: R+/sum, uniform if no R > 0 */
+  double alpha; /* DCFR positive-regret exponent (paper: 1.5) */
+  double beta;  /* DCFR negative-regret exponent (paper: 0) */
+  double gamma; /* DCFR average-strategy exponent (paper: 2) */
+  double eps;   /* regret floor (paper's executed rule: 1e-8) */
+} pasur_cfr_params;
+
+/* R = 0, Sbar = 0, sigma uniform over every node's children, vacc = 0. */
+int pasur_cfr_init(const pasur_fgt *fgt, const pasur_cfr_state *st, void *stream);
+/* Iterations t0 .. t0+n_iters-1 (1-based t).  Each: reach down levels
+ * 1..7; then levels 8..1: u(h) = sum sigma*u, regret
+ * r = s_p pi_{-p}(h) (u(q) - u(h)), discounted regret update, regret
+ * matching, discounted average-strategy accumulation with pi_p(h); then
+ * vacc += u(root).  u[8] must hold the leaf utilities. */
+int pasur_cfr_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st,
+                      const pasur_cfr_params *p, int64_t t0, int n_iters,
+                      void *stream);
+/* Normalise (CodeSnippet CFR): sigma_bar = Sbar / sum over siblings, uniform
+ * where that sum is 0.  sigma_bar[l] (device, `st->dtype`, levels 1..8). */
+int pasur_average_strategy(const pasur_fgt *fgt, const pasur_cfr_state *st,
+                           void *const sigma_bar[9], void *stream);
+
+typedef enum { PASUR_V_ITERATE_MEAN = 0, PASUR_V_SIGMA_BAR = 1 } pasur_value_mode;
+/* Root values passed to the previous round (d_V, device double, n[0]).
+ * ITERATE_MEAN: vacc / T (the paper's g_UTL / NUM_ITER).  SIGMA_BAR: the
+ * expected value under sigma_bar (needs sigma_bar, else may be NULL). */
+int pasur_round_values(const pasur_fgt *fgt, const pasur_cfr_state *st,
+                       int value_mode, int64_t T, void *const sigma_bar[9],
+                       double *d_V, void *stream);
+
+/* ---- a11: exact values for exploitability ----------------------------------
+ * Not in the paper (exploitability is its future work).  Up-sweep of
+ * d_leaf (device double, n[8]) to the roots (d_out, device double, n[0]):
+ * EXPECT: sum sigma * value; BR_A: max at Alex's nodes, expectation at Bob's;
+ * BR_B: min at Bob's nodes, expectation at Alex's; MINIMAX: max/min.
+ * sigma (type `dtype`, levels 1..8) may be NULL for MINIMAX.  Uses
+ * stream-ordered scratch memory. */
+typedef enum { PASUR_TV_EXPECT = 0, PASUR_TV_BR_A = 1, PASUR_TV_BR_B = 2,
+               PASUR_TV_MINIMAX = 3 } pasur_tv_mode;
+int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
+                      void *const sigma[9], int mode, double *d_out,
+                      void *stream);
+
+/* ---- tracing ----------------------------------------------------------------
+ * Per-launch timing of the sweep kernels with HIP events recorded on the
+ * launch stream around every launch made by pasur_cfr_iterate.  Enabling
+ * (or disabling) clears earlier records.  pasur_profile_read waits for the
+ * events and copies up to `cap` records (kernel 0 = reach down-sweep,
+ * 1 = fused up-sweep; level = child level) into host arrays; *n_out gets
+ * the number recorded.  Not thread-safe against concurrent iterate calls. */
+int pasur_profile_enable(int on);
+int pasur_profile_read(int64_t cap, int32_t *kernel, int32_t *level, float *ms,
+                       int64_t *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,327 @@
+"""Python binding of libpasur (the MI355X Pasur round solver, include/pasur.h).
+
+Argument marshalling only: every step runs in the HIP kernels of libpasur.so.
+PyTorch provides device memory and the stream.  Importing this module on a
+machine without the built library or without a GPU raises; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpasur.so")
+
+PASUR_F32, PASUR_F64 = 0, 1
+DCFR, CFR_PLUS, CFR_VANILLA = 0, 1, 2
+RM_FLOOR, RM_POSITIVE = 0, 1
+V_ITERATE_MEAN, V_SIGMA_BAR = 0, 1
+TV_EXPECT, TV_BR_A, TV_BR_B, TV_MINIMAX = 0, 1, 2, 3
+GT_POOL, GT_HANDS, GT_RS, GT_PARENT, GT_CHILD_BEGIN, GT_ACT_CARD, GT_ACT_CAP = range(7)
+(FGT_GT, FGT_SID, FGT_PARENT, FGT_CHILD_BEGIN, FGT_SCORE_TAB, FGT_NEXT_ROOTS, FGT_LINK,
+ FGT_LEAF_BASE) = range(8)
+
+ROOT_DTYPE = np.dtype([("pool", "<u8"), ("ca", "i1"), ("cb", "i1"), ("d", "i1"),
+                       ("bonus", "i1"), ("pad", "<i4")])
+
+
+class PasurError(RuntimeError):
+    pass
+
+
+class CfrParams(C.Structure):
+    _fields_ = [("variant", C.c_int), ("rm_mode", C.c_int), ("alpha", C.c_double),
+                ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double)]
+
+
+def paper_params() -> CfrParams:
+    """DCFR with the paper's constants (alpha 1.5, beta 0, gamma 2) and its
+    regret-matching floor (1e-8)."""
+    return CfrParams(DCFR, RM_FLOOR, 1.5, 0.0, 2.0, 1e-8)
+
+
+class _State(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("sigma", C.c_void_p * 9), ("R", C.c_void_p * 9),
+                ("Sbar", C.c_void_p * 9), ("reachA", C.c_void_p * 9),
+                ("reachB", C.c_void_p * 9), ("u", C.c_void_p * 9), ("vacc", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpasur.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PasurError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
+        L.pasur_last_error.restype = C.c_char_p
+        L.pasur_build_round_tree.argtypes = [vp, i32, vp, i64, C.POINTER(vp), vp]
+        L.pasur_gt_sizes.argtypes = [vp, vp]
+        L.pasur_gt_read.argtypes = [vp, i32, i32, vp]
+        L.pasur_gt_free.argtypes = [vp]
+        L.pasur_gt_free.restype = None
+        L.pasur_unfold_scores.argtypes = [vp, vp, i64, C.POINTER(vp), vp]
+        L.pasur_fgt_sizes.argtypes = [vp, vp, vp, vp]
+        L.pasur_fgt_read.argtypes = [vp, i32, i32, vp]
+        L.pasur_fgt_next_roots.argtypes = [vp]
+        L.pasur_fgt_next_roots.restype = vp
+        L.pasur_fgt_free.argtypes = [vp]
+        L.pasur_fgt_free.restype = None
+        L.pasur_leaf_utilities.argtypes = [vp, vp, i32, vp, vp]
+        L.pasur_cfr_init.argtypes = [vp, vp, vp]
+        L.pasur_cfr_iterate.argtypes = [vp, vp, vp, i64, i32, vp]
+        L.pasur_average_strategy.argtypes = [vp, vp, vp, vp]
+        L.pasur_round_values.argtypes = [vp, vp, i32, i64, vp, vp, vp]
+        L.pasur_tree_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+        L.pasur_profile_enable.argtypes = [i32]
+        L.pasur_profile_read.argtypes = [i64, vp, vp, vp, C.POINTER(C.c_int64)]
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = lib().pasur_last_error().decode(errors="replace")
+        raise PasurError(f"{what} failed ({status}): {msg}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise PasurError("no GPU: libpasur runs on an MI355X (gfx950) only")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def roots_to_device(roots) -> "torch.Tensor":
+    """Roots (objects with pool, ca, cb, d, bonus, or a ROOT_DTYPE array) ->
+    device byte tensor laid out as pasur_root[]."""
+    torch = _torch()
+    if isinstance(roots, np.ndarray) and roots.dtype == ROOT_DTYPE:
+        a = roots
+    else:
+        a = np.zeros(len(roots), ROOT_DTYPE)
+        for i, r in enumerate(roots):
+            a[i] = (r.pool, r.ca, r.cb, r.d, r.bonus, 0)
+    return torch.from_numpy(a.view(np.uint8).copy()).cuda()
+
+
+class GameTree:
+    """Handle of a round game tree (pasur_gt)."""
+
+    def __init__(self, handle, rnd: int):
+        self.h = handle
+        self.round = rnd
+        n = (C.c_int64 * 9)()
+        _check(lib().pasur_gt_sizes(self.h, n), "pasur_gt_sizes")
+        self.n = list(n)
+
+    def free(self):
+        if self.h:
+            lib().pasur_gt_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def read(self, field: int, level: int) -> np.ndarray:
+        n = self.n[level]
+        dt, size = {GT_POOL: (np.uint64, n), GT_HANDS: (np.uint8, n), GT_RS: (np.int8, 8 * n),
+                    GT_PARENT: (np.int32, n), GT_CHILD_BEGIN: (np.int32, n + 1),
+                    GT_ACT_CARD: (np.uint8, n), GT_ACT_CAP: (np.uint64, n)}[field]
+        out = np.zeros(max(size, 1), dt)
+        _check(lib().pasur_gt_read(self.h, field, level, out.ctypes.data_as(C.c_void_p)),
+               "pasur_gt_read")
+        out = out[:size]
+        return out.reshape(n, 8) if field == GT_RS else out
+
+
+class UnfoldedTree:
+    """Handle of a round's unfolded tree (pasur_fgt)."""
+
+    def __init__(self, handle, rnd: int):
+        self.h = handle
+        self.round = rnd
+        n = (C.c_int64 * 9)()
+        ns, nn = C.c_int64(), C.c_int64()
+        _check(lib().pasur_fgt_sizes(self.h, n, C.byref(ns), C.byref(nn)), "pasur_fgt_sizes")
+        self.n = list(n)
+        self.n_scores = ns.value
+        self.n_next = nn.value
+
+    def free(self):
+        if self.h:
+            lib().pasur_fgt_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def read(self, field: int, level: int = 0) -> np.ndarray:
+        if field == FGT_SCORE_TAB:
+            out = np.zeros(max(4 * self.n_scores, 1), np.int8)
+        elif field == FGT_NEXT_ROOTS:
+            out = np.zeros(max(self.n_next, 1), ROOT_DTYPE)
+        elif field == FGT_LEAF_BASE:
+            out = np.zeros(max(self.n[8], 1), np.int16)
+        else:
+            n = self.n[8] if field == FGT_LINK else self.n[level]
+            out = np.zeros(max(n + 1 if field == FGT_CHILD_BEGIN else n, 1), np.int32)
+        _check(lib().pasur_fgt_read(self.h, field, level, out.ctypes.data_as(C.c_void_p)),
+               "pasur_fgt_read")
+        if field == FGT_SCORE_TAB:
+            return out[: 4 * self.n_scores].reshape(-1, 4)
+        if field == FGT_NEXT_ROOTS:
+            return out[: self.n_next]
+        if field == FGT_LEAF_BASE or field == FGT_LINK:
+            return out[: self.n[8]]
+        n = self.n[level]
+        return out[: n + 1 if field == FGT_CHILD_BEGIN else n]
+
+    def next_roots_device(self):
+        """(device pointer, count) of the next-round roots owned by this handle."""
+        return lib().pasur_fgt_next_roots(self.h), self.n_next
+
+    def edges(self) -> int:
+        """Non-root nodes: one per action edge, updated once per iteration."""
+        return int(sum(self.n[1:]))
+
+
+def build_round_tree(deck: Sequence[int], rnd: int, d_roots, n_roots: int, stream=None) -> GameTree:
+    """pasur_build_round_tree: ``d_roots`` is a device tensor (or int device
+    pointer) of pasur_root in canonical order."""
+    dk = (C.c_uint8 * 52)(*[int(c) for c in deck])
+    h = C.c_void_p()
+    ptr = C.c_void_p(d_roots if isinstance(d_roots, int) else d_roots.data_ptr())
+    _check(lib().pasur_build_round_tree(dk, rnd, ptr, n_roots, C.byref(h), _stream(stream)),
+           "pasur_build_round_tree")
+    return GameTree(h, rnd)
+
+
+def unfold_scores(gt: GameTree, d_roots, n_roots: int, stream=None) -> UnfoldedTree:
+    h = C.c_void_p()
+    ptr = C.c_void_p(d_roots if isinstance(d_roots, int) else d_roots.data_ptr())
+    _check(lib().pasur_unfold_scores(gt.h, ptr, n_roots, C.byref(h), _stream(stream)),
+           "pasur_unfold_scores")
+    return UnfoldedTree(h, gt.round)
+
+
+class CfrState:
+    """Caller-owned solver state of one round (torch device tensors)."""
+
+    def __init__(self, fgt: UnfoldedTree, dtype: int = PASUR_F32):
+        torch = _torch()
+        self.fgt = fgt
+        self.dtype = dtype
+        tdt = torch.float32 if dtype == PASUR_F32 else torch.float64
+        n = fgt.n
+        dev = torch.device("cuda")
+        self.sigma = [None] + [torch.empty(n[l], dtype=tdt, device=dev) for l in range(1, 9)]
+        self.R = [None] + [torch.empty(n[l], dtype=tdt, device=dev) for l in range(1, 9)]
+        self.Sbar = [None] + [torch.empty(n[l], dtype=tdt, device=dev) for l in range(1, 9)]
+        self.reachA = [torch.empty(n[l], dtype=tdt, device=dev) for l in range(8)] + [None]
+        self.reachB = [torch.empty(n[l], dtype=tdt, device=dev) for l in range(8)] + [None]
+        self.u = [torch.empty(n[l], dtype=tdt, device=dev) for l in range(9)]
+        self.vacc = torch.zeros(n[0], dtype=torch.float64, device=dev)
+        self.sigma_bar = [None] + [torch.empty(n[l], dtype=tdt, device=dev) for l in range(1, 9)]
+        st = _State()
+        st.dtype = dtype
+        for name in ("sigma", "R", "Sbar", "reachA", "reachB", "u"):
+            arr = getattr(st, name)
+            for l, t in enumerate(getattr(self, name)):
+                arr[l] = t.data_ptr() if t is not None else None
+        st.vacc = self.vacc.data_ptr()
+        self.c = st
+        self.sb_ptrs = (C.c_void_p * 9)(*([None] + [t.data_ptr() for t in self.sigma_bar[1:]]))
+        self.t = 1
+
+    def bytes(self) -> int:
+        ts = [*self.sigma[1:], *self.R[1:], *self.Sbar[1:], *self.reachA[:8], *self.reachB[:8],
+              *self.u, self.vacc]
+        return int(sum(t.numel() * t.element_size() for t in ts))
+
+
+def leaf_utilities(fgt: UnfoldedTree, d_V_next, dtype: int, d_out, stream=None):
+    vp = None if d_V_next is None else _dptr(d_V_next)
+    _check(lib().pasur_leaf_utilities(fgt.h, vp, dtype, _dptr(d_out), _stream(stream)),
+           "pasur_leaf_utilities")
+
+
+def cfr_init(st: CfrState, stream=None):
+    _check(lib().pasur_cfr_init(st.fgt.h, C.byref(st.c), _stream(stream)), "pasur_cfr_init")
+    st.t = 1
+
+
+def cfr_iterate(st: CfrState, n_iters: int, params: Optional[CfrParams] = None, t0: Optional[int] = None,
+                stream=None):
+    p = params if params is not None else paper_params()
+    t = st.t if t0 is None else t0
+    _check(lib().pasur_cfr_iterate(st.fgt.h, C.byref(st.c), C.byref(p), t, n_iters,
+                                   _stream(stream)), "pasur_cfr_iterate")
+    st.t = t + n_iters
+
+
+def average_strategy(st: CfrState, stream=None):
+    _check(lib().pasur_average_strategy(st.fgt.h, C.byref(st.c), st.sb_ptrs, _stream(stream)),
+           "pasur_average_strategy")
+    return st.sigma_bar
+
+
+def round_values(st: CfrState, value_mode: int, d_V, stream=None):
+    T = st.t - 1
+    _check(lib().pasur_round_values(st.fgt.h, C.byref(st.c), value_mode, T, st.sb_ptrs, _dptr(d_V),
+                                    _stream(stream)), "pasur_round_values")
+    return d_V
+
+
+def tree_values(fgt: UnfoldedTree, d_leaf, dtype: int, sigma: Optional[List], mode: int, d_out,
+                stream=None):
+    if sigma is None:
+        sp = None
+    else:
+        sp = (C.c_void_p * 9)(*([None] + [t.data_ptr() for t in sigma[1:]]))
+    _check(lib().pasur_tree_values(fgt.h, _dptr(d_leaf), dtype, sp, mode, _dptr(d_out),
+                                   _stream(stream)), "pasur_tree_values")
+    return d_out
+
+
+def profile_enable(on: bool):
+    _check(lib().pasur_profile_enable(1 if on else 0), "pasur_profile_enable")
+
+
+def profile_read():
+    """Recorded sweep launches: arrays (kernel, level, milliseconds)."""
+    n = C.c_int64()
+    _check(lib().pasur_profile_read(0, None, None, None, C.byref(n)), "pasur_profile_read")
+    k = np.zeros(max(n.value, 1), np.int32)
+    lv = np.zeros(max(n.value, 1), np.int32)
+    ms = np.zeros(max(n.value, 1), np.float32)
+    _check(lib().pasur_profile_read(n.value, k.ctypes.data_as(C.c_void_p),
+                                    lv.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p),
+                                    C.byref(n)), "pasur_profile_read")
+    return k[: n.value], lv[: n.value], ms[: n.value]
+
+
+from .solver import SubgameSolver, RoundResult  # noqa: E402  (driver over the calls above)

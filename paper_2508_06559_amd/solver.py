@@ -1,0 +1,95 @@
+"""Round-by-round driver over the libpasur calls (CodeSnippet CFR, runcfr).
+
+Forward: build and unfold every round from the start round to round 5,
+chaining each round's next-round roots (device memory) into the next build.
+Backward: solve round 5 first; each solved round passes its root values to
+the previous round's leaves (equation passuputil).  Exploitability composes
+best responses across rounds the same way.  Control flow only: every step is
+a libpasur kernel.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional
+
+from . import (PASUR_F32, PASUR_F64, TV_BR_A, TV_BR_B, TV_EXPECT, V_ITERATE_MEAN, CfrState,
+               UnfoldedTree, average_strategy, build_round_tree, cfr_init, cfr_iterate,
+               leaf_utilities, paper_params, round_values, roots_to_device, tree_values,
+               unfold_scores, _torch)
+
+
+@dataclass
+class RoundResult:
+    round: int
+    fgt: UnfoldedTree
+    state: Optional[CfrState] = None
+    V: Optional[object] = None  # device double tensor, one value per root
+
+
+class SubgameSolver:
+    """All rounds from ``start_round`` to 5 of one deal."""
+
+    def __init__(self, deck, start_round: int, roots, dtype: int = PASUR_F32, stream=None):
+        torch = _torch()
+        self.deck = list(int(c) for c in deck)
+        self.start = start_round
+        self.dtype = dtype
+        self.stream = stream
+        self.rounds: List[RoundResult] = []
+        d_roots = roots_to_device(roots)
+        self._root_tensor = d_roots
+        ptr, n = d_roots.data_ptr(), len(roots)
+        for r in range(start_round, 6):
+            gt = build_round_tree(self.deck, r, ptr, n, stream)
+            fgt = unfold_scores(gt, ptr, n, stream)
+            gt.free()
+            self.rounds.append(RoundResult(r, fgt))
+            if r < 5:
+                ptr, n = fgt.next_roots_device()
+        self.torch = torch
+
+    def sizes(self):
+        return [rr.fgt.n for rr in self.rounds]
+
+    def edges(self) -> int:
+        return sum(rr.fgt.edges() for rr in self.rounds)
+
+    def solve(self, iters: int, params=None, value_mode: int = V_ITERATE_MEAN):
+        """Backward DCFR: ``iters`` iterations per round."""
+        torch = self.torch
+        params = params if params is not None else paper_params()
+        V = None
+        for rr in reversed(self.rounds):
+            st = rr.state if rr.state is not None else CfrState(rr.fgt, self.dtype)
+            rr.state = st
+            leaf_utilities(rr.fgt, V, self.dtype, st.u[8], self.stream)
+            cfr_init(st, self.stream)
+            cfr_iterate(st, iters, params, stream=self.stream)
+            average_strategy(st, self.stream)
+            rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
+            round_values(st, value_mode, rr.V, self.stream)
+            V = rr.V
+        return self.rounds[0].V
+
+    def exploitability(self):
+        """Composed best responses of both players against the average
+        strategies of every round; returns (BR_A, BR_B, v) at the start
+        round's roots as device double tensors.  Exploitability (points per
+        game) is (BR_A - BR_B) / 2."""
+        torch = self.torch
+        out = {}
+        for mode in (TV_BR_A, TV_BR_B, TV_EXPECT):
+            V = None
+            for rr in reversed(self.rounds):
+                leaf = torch.empty(rr.fgt.n[8], dtype=torch.float64, device="cuda")
+                leaf_utilities(rr.fgt, V, PASUR_F64, leaf, self.stream)
+                res = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
+                tree_values(rr.fgt, leaf, self.dtype, rr.state.sigma_bar, mode, res, self.stream)
+                V = res
+            out[mode] = V
+        return out[TV_BR_A], out[TV_BR_B], out[TV_EXPECT]
+
+    def free(self):
+        for rr in self.rounds:
+            rr.fgt.free()
+        self.rounds = []
