@@ -104,7 +104,8 @@ def test_fp32_state_values_and_strategy_quality(seed):
     obra, obrb, _ = oracle_exploitability(rounds, [c.sigma_bar()])
     ex_gpu, ex_or = (bra - brb) / 2, (obra - obrb) / 2
     M = oracle.tree_values(f.n, f.child_begin(), leaf, None, oracle.TV_MINIMAX)
-    assert np.all(brb - 1e-9 <= M) and np.all(M <= bra + 1e-9)
+    # FP32 sigma_bar sums to 1 only up to float rounding (~1e-7 relative)
+    assert np.all(brb - TOL32_VALUES <= M) and np.all(M <= bra + TOL32_VALUES)
     # equally good actions may split differently, but the profile must be as
     # good as the oracle's
     assert ex_gpu.max() <= 1.5 * ex_or.max() + 1e-6
