@@ -28,21 +28,28 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def up_bytes(n, l, T):
-    """Algorithmic bytes of one fused up-sweep launch for child level l:
-    per edge sigma, u, R, Sbar read and R, Sbar, sigma written (7 T); per
-    parent the CSR offset, both reaches read and u written (4 + 3 T);
-    vacc read and written at the roots."""
-    b = n[l] * 7 * T + n[l - 1] * (4 + 3 * T) + 4
-    if l == 1:
-        b += 16 * n[0]
-    return b
+def launch_bytes(kernel, level, work, T):
+    """Algorithmic bytes moved by one recorded sweep launch.
+
+    Per edge and iteration the fused up-sweep reads sigma, u, R, Sbar and
+    writes R, Sbar, sigma (7 T bytes); per parent it reads its CSR offset and
+    both reaches and writes u (4 + 3 T); every root reads and writes vacc
+    (16) and its two CSR ends add 4 per level.  The reach down-sweep reads
+    the parent index and sigma and writes two reaches per child (4 + 3 T)
+    and reads two reaches per parent (2 T).  The per-root schedule performs
+    both sweeps over all levels of each root's subtree every iteration.
+    """
+    edges, internal, roots, n7, iters = (int(x) for x in work)
+    if kernel == 1:  # one level of the up-sweep
+        return edges * 7 * T + internal * (4 + 3 * T) + 4 + (16 * internal if level == 1 else 0)
+    if kernel == 0:  # one level of the down-sweep
+        return edges * (4 + 3 * T) + internal * 2 * T
+    up = 7 * T * edges + (4 + 3 * T) * internal + 48 * roots
+    down = (4 + 3 * T) * (internal - roots) + 2 * T * (internal - n7)
+    return iters * (up + down)
 
 
-def down_bytes(n, l, T):
-    """Reach down-sweep, child level l: parent index, sigma, two reaches
-    written per child; two parent reaches read per parent."""
-    return n[l] * (4 + 3 * T) + n[l - 1] * 2 * T
+KERNEL_NAMES = {0: "k_down", 1: "k_up", 2: "k_cfr_root (all LDS)", 3: "k_cfr_root (LDS + global)"}
 
 
 def cpu_baseline(deck, roots, iters):
@@ -91,6 +98,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--state", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--sched", choices=["root", "level", "root-global"], default="root")
+    ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -105,13 +114,15 @@ def main():
     torch.cuda.set_device(0)
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
+    params = pa.paper_params({"root": pa.SCHED_ROOT, "level": pa.SCHED_LEVEL_SYNC,
+                              "root-global": pa.SCHED_ROOT_GLOBAL}[args.sched], args.block)
     deck, roots = synth.two_round_root(args.seed)
     d_roots = pa.roots_to_device(roots)  # resident before timing
     torch.cuda.synchronize()
 
     def step():
         s = pa.SubgameSolver(deck, 4, roots, dtype=dtype)
-        s.solve(args.iters)
+        s.solve(args.iters, params)
         bra, brb, v = s.exploitability()
         torch.cuda.synchronize()
         ex = float(((bra - brb) / 2).max().item())
@@ -133,32 +144,29 @@ def main():
     nodes = sum(sum(n) for n in sizes)
     value = edges * args.iters * args.steps / el
 
-    # Dominant kernel: the fused up-sweep.  Average launch duration measured
-    # live with HIP events on the launch stream over one step's iterations.
+    # Dominant kernel: the sweep kernel with the largest share of time.  Its
+    # average launch duration is measured live with HIP events on the launch
+    # stream over one step's solve (the library's per-launch profiling).
     s = pa.SubgameSolver(deck, 4, roots, dtype=dtype)
     pa.profile_enable(True)
-    s.solve(args.iters)
+    s.solve(args.iters, params)
     torch.cuda.synchronize()
-    kern, lev, ms = pa.profile_read()
+    kern, lev, ms, work = pa.profile_read()
     pa.profile_enable(False)
-    # records come round by round (last round first), iteration by iteration
-    order = [s.rounds[1].fgt.n, s.rounds[0].fgt.n]
-    recs_per_round = 15 * args.iters
-    up_b = up_t = dn_b = dn_t = 0.0
-    n_up = 0
-    for idx in range(len(kern)):
-        n = order[idx // recs_per_round]
-        if kern[idx] == 1:
-            up_b += up_bytes(n, int(lev[idx]), T)
-            up_t += float(ms[idx]) * 1e-3
-            n_up += 1
-        else:
-            dn_b += down_bytes(n, int(lev[idx]), T)
-            dn_t += float(ms[idx]) * 1e-3
     s.free()
-    achieved = up_b / up_t / 1e9
-    log(f"[bench] up-sweep: {n_up} launches, avg {up_t / n_up * 1e6:.2f} us, "
-        f"{up_b / n_up / 1e6:.3f} MB/launch; down-sweep avg {dn_t / (len(kern) - n_up) * 1e6:.2f} us")
+    per = {}
+    for i in range(len(kern)):
+        k = int(kern[i])
+        b, t, c = per.get(k, (0.0, 0.0, 0))
+        per[k] = (b + launch_bytes(k, int(lev[i]), work[i], T), t + float(ms[i]) * 1e-3, c + 1)
+    dom = max(per, key=lambda k: per[k][1])
+    db, dt, dc = per[dom]
+    achieved = db / dt / 1e9
+    all_b = sum(v[0] for v in per.values())
+    all_t = sum(v[1] for v in per.values())
+    for k, (b, t, c) in sorted(per.items()):
+        log(f"[bench] {KERNEL_NAMES[k]}: {c} launches, avg {t / c * 1e6:.1f} us, "
+            f"{b / c / 1e6:.3f} MB/launch, {b / t / 1e9:.1f} GB/s")
 
     out = {
         "metric": METRIC,
@@ -178,6 +186,8 @@ def main():
                         f"({nodes} nodes, {edges} edges), {args.iters} DCFR iterations per round, "
                         f"backward round values, composed exploitability",
             "state": args.state,
+            "schedule": args.sched,
+            "block": args.block,
             "arithmetic": "f64 registers",
             "iters_per_round": args.iters,
             "level_sizes": sizes,
@@ -185,15 +195,16 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_up<{'float' if T == 4 else 'double'}> (fused up-sweep)",
+            "kernel": f"{KERNEL_NAMES[dom]}, {'float' if T == 4 else 'double'} state",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "avg_launch_us": up_t / n_up * 1e6,
-            "algorithmic_bytes_per_launch": up_b / n_up,
-            "iteration_effective_GBs": (up_b + dn_b) / (up_t + dn_t) / 1e9,
+            "avg_launch_us": dt / dc * 1e6,
+            "launches": dc,
+            "algorithmic_bytes_per_launch": db / dc,
+            "all_sweeps_GBs": all_b / all_t / 1e9,
         },
     }
     if not args.no_cpu_baseline:

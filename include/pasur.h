@@ -161,6 +161,13 @@ typedef struct {
 
 typedef enum { PASUR_DCFR = 0, PASUR_CFR_PLUS = 1, PASUR_CFR_VANILLA = 2 } pasur_variant;
 typedef enum { PASUR_RM_FLOOR = 0, PASUR_RM_POSITIVE = 1 } pasur_rm_mode;
+/* Kernel schedule of pasur_cfr_iterate (same results bit for bit):
+ * ROOT (default): one persistent workgroup per root runs all iterations on
+ *   that root's subtree, its state held in LDS when it fits (else in global
+ *   memory); LEVEL_SYNC: one launch per level and sweep direction;
+ * ROOT_GLOBAL: the per-root schedule with state always in global memory. */
+typedef enum { PASUR_SCHED_ROOT = 0, PASUR_SCHED_LEVEL_SYNC = 1,
+               PASUR_SCHED_ROOT_GLOBAL = 2 } pasur_schedule;
 typedef struct {
   int variant;  /* pasur_variant */
   int rm_mode;  /* PASUR_RM_FLOOR: max(R, eps)/sum (the paper's executed rule);
@@ -169,6 +176,9 @@ typedef struct {
   double beta;  /* DCFR negative-regret exponent (paper: 0) */
   double gamma; /* DCFR average-strategy exponent (paper: 2) */
   double eps;   /* regret floor (paper's executed rule: 1e-8) */
+  int schedule; /* pasur_schedule */
+  int block;    /* threads per workgroup of the per-root schedule: 0 (= 1024),
+                   256, 512 or 1024 */
 } pasur_cfr_params;
 
 /* R = 0, Sbar = 0, sigma uniform over every node's children, vacc = 0. */
@@ -212,11 +222,16 @@ int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
  * launch stream around every launch made by pasur_cfr_iterate.  Enabling
  * (or disabling) clears earlier records.  pasur_profile_read waits for the
  * events and copies up to `cap` records (kernel 0 = reach down-sweep,
- * 1 = fused up-sweep; level = child level) into host arrays; *n_out gets
- * the number recorded.  Not thread-safe against concurrent iterate calls. */
+ * 1 = fused up-sweep, level = child level; 2 = per-root kernel with every
+ * subtree in LDS, 3 = per-root kernel with some subtrees in global memory,
+ * level = -1) into host arrays, with
+ * the work of each launch in `work` (5 int64 per record: edges, internal
+ * nodes, roots, level-7 nodes covered, iterations); any output array may be
+ * NULL.  *n_out gets the number recorded.  Not thread-safe against
+ * concurrent iterate calls. */
 int pasur_profile_enable(int on);
 int pasur_profile_read(int64_t cap, int32_t *kernel, int32_t *level, float *ms,
-                       int64_t *n_out);
+                       int64_t *work, int64_t *n_out);
 
 #ifdef __cplusplus
 }

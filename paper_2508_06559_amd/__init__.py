@@ -33,15 +33,19 @@ class PasurError(RuntimeError):
     pass
 
 
+SCHED_ROOT, SCHED_LEVEL_SYNC, SCHED_ROOT_GLOBAL = 0, 1, 2
+
+
 class CfrParams(C.Structure):
     _fields_ = [("variant", C.c_int), ("rm_mode", C.c_int), ("alpha", C.c_double),
-                ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double)]
+                ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double),
+                ("schedule", C.c_int), ("block", C.c_int)]
 
 
-def paper_params() -> CfrParams:
+def paper_params(schedule: int = SCHED_ROOT, block: int = 0) -> CfrParams:
     """DCFR with the paper's constants (alpha 1.5, beta 0, gamma 2) and its
     regret-matching floor (1e-8)."""
-    return CfrParams(DCFR, RM_FLOOR, 1.5, 0.0, 2.0, 1e-8)
+    return CfrParams(DCFR, RM_FLOOR, 1.5, 0.0, 2.0, 1e-8, schedule, block)
 
 
 class _State(C.Structure):
@@ -81,7 +85,7 @@ def lib():
         L.pasur_round_values.argtypes = [vp, vp, i32, i64, vp, vp, vp]
         L.pasur_tree_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
-        L.pasur_profile_read.argtypes = [i64, vp, vp, vp, C.POINTER(C.c_int64)]
+        L.pasur_profile_read.argtypes = [i64, vp, vp, vp, vp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -312,16 +316,20 @@ def profile_enable(on: bool):
 
 
 def profile_read():
-    """Recorded sweep launches: arrays (kernel, level, milliseconds)."""
+    """Recorded sweep launches: arrays (kernel, level, milliseconds, work)
+    with work[i] = (edges, internal nodes, roots, level-7 nodes, iterations)."""
     n = C.c_int64()
-    _check(lib().pasur_profile_read(0, None, None, None, C.byref(n)), "pasur_profile_read")
-    k = np.zeros(max(n.value, 1), np.int32)
-    lv = np.zeros(max(n.value, 1), np.int32)
-    ms = np.zeros(max(n.value, 1), np.float32)
+    _check(lib().pasur_profile_read(0, None, None, None, None, C.byref(n)), "pasur_profile_read")
+    m = max(n.value, 1)
+    k = np.zeros(m, np.int32)
+    lv = np.zeros(m, np.int32)
+    ms = np.zeros(m, np.float32)
+    work = np.zeros((m, 5), np.int64)
     _check(lib().pasur_profile_read(n.value, k.ctypes.data_as(C.c_void_p),
                                     lv.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p),
-                                    C.byref(n)), "pasur_profile_read")
-    return k[: n.value], lv[: n.value], ms[: n.value]
+                                    work.ctypes.data_as(C.c_void_p), C.byref(n)),
+           "pasur_profile_read")
+    return k[: n.value], lv[: n.value], ms[: n.value], work[: n.value]
 
 
 from .solver import SubgameSolver, RoundResult  # noqa: E402  (driver over the calls above)

@@ -11,6 +11,7 @@
 
 #include "pasur_internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -24,6 +25,7 @@ namespace {
 // stream), off unless pasur_profile_enable(1) was called.
 struct ProfRec {
   int kernel, level;
+  int64_t work[5];  // edges, internal nodes, roots, level-7 nodes, iterations
   hipEvent_t a, b;
 };
 std::mutex g_prof_mu;
@@ -42,10 +44,17 @@ struct ProfScope {
   ProfRec rec;
   hipStream_t s;
   bool on;
-  ProfScope(int kernel, int level, hipStream_t stream) : s(stream), on(g_prof_on) {
+  ProfScope(int kernel, int level, hipStream_t stream, int64_t edges = 0, int64_t internal = 0,
+            int64_t roots = 0, int64_t n7 = 0, int64_t iters = 1)
+      : s(stream), on(g_prof_on) {
     if (!on) return;
     rec.kernel = kernel;
     rec.level = level;
+    rec.work[0] = edges;
+    rec.work[1] = internal;
+    rec.work[2] = roots;
+    rec.work[3] = n7;
+    rec.work[4] = iters;
     (void)hipEventCreate(&rec.a);
     (void)hipEventCreate(&rec.b);
     (void)hipEventRecord(rec.a, s);
@@ -160,6 +169,301 @@ __global__ void k_up(int64_t np, int mover, const int32_t *__restrict__ cb,
   if (vacc) vacc[h] += uh;
 }
 
+
+// ---------------------------------------------------------------------------
+// Persistent per-root schedule.  The subgames below different roots never
+// interact inside a round (every root has reach 1), so one workgroup owns a
+// root's subtree and runs all iterations on it with workgroup barriers
+// between levels.  When the subtree's state fits in LDS (160 KB per
+// workgroup on gfx950) it is loaded once, iterated in LDS and written back
+// once; otherwise the same loop runs on global memory (L2/MALL resident).
+// Each parent is still updated by one thread in child order, so results are
+// bit-identical to the level-synchronous kernels.
+// ---------------------------------------------------------------------------
+
+struct IterK {
+  double dpos, dneg, avg_w, avg_t;
+};
+
+struct TreePtrs {
+  const int32_t *off[9];
+  const int32_t *parent[9];
+  const int32_t *cb[8];
+};
+
+template <class T>
+struct StatePtrs {
+  T *sigma[9], *R[9], *Sbar[9], *ra[9], *rb[9], *u[9];
+  double *vacc;
+};
+
+extern __shared__ __align__(16) unsigned char g_lds[];
+
+template <class T>
+struct LdsArr {
+  uint32_t off;
+  __device__ T &operator[](int i) const { return reinterpret_cast<T *>(g_lds + off)[i]; }
+};
+template <class T>
+struct GlbArr {
+  T *p;
+  __device__ T &operator[](int i) const { return p[i]; }
+};
+
+// Byte layout of one root's subtree state in LDS (shared by host sizing
+// and device carving): per level sigma, R, Sbar (levels 1..8), u (0..8),
+// reachA, reachB (0..7) as T, then parent (1..8) and child_begin (0..7) as
+// 16-bit indices local to the subtree; every array 16-byte aligned.
+struct LdsLayout {
+  uint32_t sg[9], R[9], Sb[9], u[9], ra[9], rb[9], par[9], cb[9];
+  uint32_t bytes;
+};
+
+__host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+
+__host__ __device__ inline LdsLayout lds_layout(const int cnt[9], uint32_t tsize) {
+  LdsLayout L;
+  uint32_t p = 0;
+  for (int l = 0; l <= 8; ++l) {
+    L.sg[l] = L.R[l] = L.Sb[l] = 0;
+    if (l >= 1) {
+      L.sg[l] = p; p = align16(p + cnt[l] * tsize);
+      L.R[l] = p; p = align16(p + cnt[l] * tsize);
+      L.Sb[l] = p; p = align16(p + cnt[l] * tsize);
+    }
+    L.u[l] = p; p = align16(p + cnt[l] * tsize);
+    L.ra[l] = L.rb[l] = 0;
+    if (l <= 7) {
+      L.ra[l] = p; p = align16(p + cnt[l] * tsize);
+      L.rb[l] = p; p = align16(p + cnt[l] * tsize);
+    }
+  }
+  for (int l = 0; l <= 8; ++l) {
+    L.par[l] = L.cb[l] = 0;
+    if (l >= 1) { L.par[l] = p; p = align16(p + cnt[l] * 2); }
+    if (l <= 7) { L.cb[l] = p; p = align16(p + (cnt[l] + 1) * 2); }
+  }
+  L.bytes = p;
+  return L;
+}
+
+template <class AT, class AI>
+struct Sub {
+  AT sg[9], Rr[9], Sb[9], uu[9], ra[9], rb[9];
+  AI par[9], cbl[9];
+  int par_sub[9], cb_sub[9];
+  int cnt[9];
+};
+
+// All iterations of one subtree (FindReachProbability then FindUtility per
+// iteration, as in k_down / k_up).
+template <class T, class SubT>
+__device__ inline void subtree_iterations(const SubT &S, const IterK *__restrict__ ks,
+                                          int n_iters, int variant, int rm_mode, double eps,
+                                          double &vacc_acc) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int it = 0; it < n_iters; ++it) {
+    const IterK k = ks[it];
+#pragma unroll
+    for (int l = 1; l <= 7; ++l) {
+      const int mover = (l - 1) & 1;
+      for (int q = tid; q < S.cnt[l]; q += nt) {
+        const int h = (int)S.par[l][q] - S.par_sub[l];
+        double a = (double)S.ra[l - 1][h];
+        double b = (double)S.rb[l - 1][h];
+        if (mover == 0) a *= (double)S.sg[l][q];
+        else b *= (double)S.sg[l][q];
+        S.ra[l][q] = (T)a;
+        S.rb[l][q] = (T)b;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int l = 8; l >= 1; --l) {
+      const int mover = (l - 1) & 1;
+      const double sgn = mover == 0 ? 1.0 : -1.0;
+      for (int h = tid; h < S.cnt[l - 1]; h += nt) {
+        const int b = (int)S.cbl[l - 1][h] - S.cb_sub[l - 1];
+        const int e = (int)S.cbl[l - 1][h + 1] - S.cb_sub[l - 1];
+        double uh = 0.0;
+        for (int q = b; q < e; ++q) uh += (double)S.sg[l][q] * (double)S.uu[l][q];
+        S.uu[l - 1][h] = (T)uh;
+        const double opp = mover == 0 ? (double)S.rb[l - 1][h] : (double)S.ra[l - 1][h];
+        const double own = mover == 0 ? (double)S.ra[l - 1][h] : (double)S.rb[l - 1][h];
+        double sum = 0.0;
+        for (int q = b; q < e; ++q) {
+          const double r = sgn * opp * ((double)S.uu[l][q] - uh);
+          double Rq = (double)S.Rr[l][q];
+          if (variant == PASUR_DCFR) {
+            const double d = Rq > 0.0 ? k.dpos : k.dneg;
+            Rq = d * Rq + r;
+          } else if (variant == PASUR_CFR_PLUS) {
+            Rq = Rq + r;
+            if (Rq < 0.0) Rq = 0.0;
+          } else {
+            Rq = Rq + r;
+          }
+          const T Rs = (T)Rq;
+          S.Rr[l][q] = Rs;
+          sum += rm_mode == PASUR_RM_FLOOR ? fmax((double)Rs, eps) : fmax((double)Rs, 0.0);
+        }
+        const double inv_k = 1.0 / (double)(e - b);
+        for (int q = b; q < e; ++q) {
+          const double x = rm_mode == PASUR_RM_FLOOR ? fmax((double)S.Rr[l][q], eps)
+                                                     : fmax((double)S.Rr[l][q], 0.0);
+          const double s_new = sum > 0.0 ? x / sum : inv_k;
+          double add = own * (double)S.sg[l][q];
+          if (variant == PASUR_CFR_PLUS) add *= k.avg_t;
+          S.Sb[l][q] = (T)(k.avg_w * (double)S.Sb[l][q] + add);
+          S.sg[l][q] = (T)s_new;
+        }
+        if (l == 1) vacc_acc += uh;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <class T, int BLOCK>
+__device__ inline void root_in_lds(const TreePtrs &tp, const StatePtrs<T> &sp, int j,
+                                   const int lo[9], const int cnt[9], const LdsLayout &L,
+                                   const IterK *__restrict__ ks, int n_iters, int variant,
+                                   int rm_mode, double eps) {
+  const int tid = threadIdx.x;
+  Sub<LdsArr<T>, LdsArr<uint16_t>> S;
+#pragma unroll
+  for (int l = 0; l <= 8; ++l) {
+    S.sg[l].off = L.sg[l];
+    S.Rr[l].off = L.R[l];
+    S.Sb[l].off = L.Sb[l];
+    S.uu[l].off = L.u[l];
+    S.ra[l].off = L.ra[l];
+    S.rb[l].off = L.rb[l];
+    S.par[l].off = L.par[l];
+    S.cbl[l].off = L.cb[l];
+    S.par_sub[l] = 0;
+    S.cb_sub[l] = 0;
+    S.cnt[l] = cnt[l];
+  }
+  // load the subtree's state
+#pragma unroll
+  for (int l = 0; l <= 8; ++l) {
+    for (int i = tid; i < cnt[l]; i += BLOCK) {
+      if (l >= 1) {
+        S.sg[l][i] = sp.sigma[l][lo[l] + i];
+        S.Rr[l][i] = sp.R[l][lo[l] + i];
+        S.Sb[l][i] = sp.Sbar[l][lo[l] + i];
+        S.par[l][i] = (uint16_t)(tp.parent[l][lo[l] + i] - lo[l - 1]);
+      }
+      if (l == 8) S.uu[l][i] = sp.u[l][lo[l] + i];
+      if (l == 0) {
+        S.ra[0][i] = sp.ra[0][lo[0] + i];
+        S.rb[0][i] = sp.rb[0][lo[0] + i];
+      }
+    }
+    if (l <= 7)
+      for (int i = tid; i <= cnt[l]; i += BLOCK)
+        S.cbl[l][i] = (uint16_t)(tp.cb[l][lo[l] + i] - lo[l + 1]);
+  }
+  __syncthreads();
+  double vacc_acc = tid == 0 ? sp.vacc[j] : 0.0;
+  subtree_iterations<T>(S, ks, n_iters, variant, rm_mode, eps, vacc_acc);
+  // write the state back
+#pragma unroll
+  for (int l = 0; l <= 8; ++l) {
+    for (int i = tid; i < cnt[l]; i += BLOCK) {
+      if (l >= 1) {
+        sp.sigma[l][lo[l] + i] = S.sg[l][i];
+        sp.R[l][lo[l] + i] = S.Rr[l][i];
+        sp.Sbar[l][lo[l] + i] = S.Sb[l][i];
+      }
+      if (l <= 7) {
+        sp.u[l][lo[l] + i] = S.uu[l][i];
+        sp.ra[l][lo[l] + i] = S.ra[l][i];
+        sp.rb[l][lo[l] + i] = S.rb[l][i];
+      }
+    }
+  }
+  if (tid == 0) sp.vacc[j] = vacc_acc;
+}
+
+// Global-memory arrays addressed through a per-workgroup pointer table kept
+// in LDS, so that the 72 per-level pointers are not all live in registers.
+__shared__ void *g_ptab[8][9];
+__shared__ int g_sub[2][9];
+
+template <class T, int SLOT>
+struct TabArr {
+  int l;
+  __device__ T &operator[](int i) const { return reinterpret_cast<T *>(g_ptab[SLOT][l])[i]; }
+};
+
+template <class T, int BLOCK>
+__device__ inline void root_in_global(const TreePtrs &tp, const StatePtrs<T> &sp, int j,
+                                      const IterK *__restrict__ ks, int n_iters, int variant,
+                                      int rm_mode, double eps) {
+  if (threadIdx.x < 9) {
+    const int l = threadIdx.x;
+    const int lo = tp.off[l][j];
+    g_ptab[0][l] = sp.sigma[l] ? (void *)(sp.sigma[l] + lo) : nullptr;
+    g_ptab[1][l] = sp.R[l] ? (void *)(sp.R[l] + lo) : nullptr;
+    g_ptab[2][l] = sp.Sbar[l] ? (void *)(sp.Sbar[l] + lo) : nullptr;
+    g_ptab[3][l] = (void *)(sp.u[l] + lo);
+    g_ptab[4][l] = sp.ra[l] ? (void *)(sp.ra[l] + lo) : nullptr;
+    g_ptab[5][l] = sp.rb[l] ? (void *)(sp.rb[l] + lo) : nullptr;
+    g_ptab[6][l] = l >= 1 ? (void *)(tp.parent[l] + lo) : nullptr;
+    g_ptab[7][l] = l <= 7 ? (void *)(tp.cb[l] + lo) : nullptr;
+    g_sub[0][l] = l >= 1 ? tp.off[l - 1][j] : 0;
+    g_sub[1][l] = l <= 7 ? tp.off[l + 1][j] : 0;
+  }
+  __syncthreads();
+  struct SubT {
+    TabArr<T, 0> sg[9];
+    TabArr<T, 1> Rr[9];
+    TabArr<T, 2> Sb[9];
+    TabArr<T, 3> uu[9];
+    TabArr<T, 4> ra[9];
+    TabArr<T, 5> rb[9];
+    TabArr<const int32_t, 6> par[9];
+    TabArr<const int32_t, 7> cbl[9];
+    int par_sub[9], cb_sub[9], cnt[9];
+  } X;
+#pragma unroll
+  for (int l = 0; l <= 8; ++l) {
+    X.sg[l].l = X.Rr[l].l = X.Sb[l].l = X.uu[l].l = X.ra[l].l = X.rb[l].l = l;
+    X.par[l].l = X.cbl[l].l = l;
+    X.par_sub[l] = g_sub[0][l];
+    X.cb_sub[l] = g_sub[1][l];
+    X.cnt[l] = tp.off[l][j + 1] - tp.off[l][j];
+  }
+  double vacc_acc = threadIdx.x == 0 ? sp.vacc[j] : 0.0;
+  subtree_iterations<T>(X, ks, n_iters, variant, rm_mode, eps, vacc_acc);
+  if (threadIdx.x == 0) sp.vacc[j] = vacc_acc;
+}
+
+// One workgroup per root; the root's subtree runs in LDS when its state fits
+// in the launch's dynamic LDS (lds_bytes), otherwise in global memory.
+template <class T, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+    k_cfr_root(TreePtrs tp, StatePtrs<T> sp, const int32_t *__restrict__ roots,
+               const IterK *__restrict__ ks, int n_iters, int variant, int rm_mode, double eps,
+               uint32_t lds_bytes) {
+  const int j = roots[blockIdx.x];
+  int lo[9], cnt[9];
+  int mx = 0;
+#pragma unroll
+  for (int l = 0; l <= 8; ++l) {
+    lo[l] = tp.off[l][j];
+    cnt[l] = tp.off[l][j + 1] - lo[l];
+    mx = cnt[l] > mx ? cnt[l] : mx;
+  }
+  const LdsLayout L = lds_layout(cnt, sizeof(T));
+  if (L.bytes <= lds_bytes && mx < 65535)
+    root_in_lds<T, BLOCK>(tp, sp, j, lo, cnt, L, ks, n_iters, variant, rm_mode, eps);
+  else
+    root_in_global<T, BLOCK>(tp, sp, j, ks, n_iters, variant, rm_mode, eps);
+}
+
 template <class T>
 __global__ void k_avg_strategy(int64_t np, const int32_t *__restrict__ cb,
                                const T *__restrict__ Sbar, T *__restrict__ out) {
@@ -269,14 +573,14 @@ int iterate_t(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_par
   for (int64_t t = t0; t < t0 + n_iters; ++t) {
     const IterConsts ic = consts_for(p, t);
     for (int l = 1; l <= 7; ++l) {
-      ProfScope ps(0, l, s);
+      ProfScope ps(0, l, s, f->n[l], f->n[l - 1]);
       k_down<T><<<grid_for(f->n[l]), kThreads, 0, s>>>(
           f->n[l], (l - 1) & 1, f->parent[l], (const T *)st->sigma[l],
           (const T *)st->reachA[l - 1], (const T *)st->reachB[l - 1], (T *)st->reachA[l],
           (T *)st->reachB[l]);
     }
     for (int l = 8; l >= 1; --l) {
-      ProfScope ps(1, l, s);
+      ProfScope ps(1, l, s, f->n[l], f->n[l - 1]);
       k_up<T><<<grid_for(f->n[l - 1]), kThreads, 0, s>>>(
           f->n[l - 1], (l - 1) & 1, f->child_begin[l - 1], (T *)st->sigma[l], (T *)st->R[l],
           (T *)st->Sbar[l], (const T *)st->u[l], (T *)st->u[l - 1],
@@ -286,6 +590,117 @@ int iterate_t(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_par
   }
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
+}
+
+
+constexpr uint32_t kLdsPerWorkgroup = 160 * 1024;
+// static LDS of the global-memory path (pointer table and index offsets)
+constexpr uint32_t kStaticLds = 8 * 9 * sizeof(void *) + 2 * 9 * sizeof(int) + 64;
+
+template <class T, int BLOCK>
+int launch_roots(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p,
+                 const IterK *d_ks, int n_iters, bool force_global, hipStream_t s) {
+  TreePtrs tp;
+  StatePtrs<T> sp;
+  for (int l = 0; l <= 8; ++l) {
+    tp.off[l] = f->root_off[l];
+    tp.parent[l] = f->parent[l];
+    if (l <= 7) tp.cb[l] = f->child_begin[l];
+    sp.sigma[l] = l >= 1 ? (T *)st->sigma[l] : nullptr;
+    sp.R[l] = l >= 1 ? (T *)st->R[l] : nullptr;
+    sp.Sbar[l] = l >= 1 ? (T *)st->Sbar[l] : nullptr;
+    sp.ra[l] = l <= 7 ? (T *)st->reachA[l] : nullptr;
+    sp.rb[l] = l <= 7 ? (T *)st->reachB[l] : nullptr;
+    sp.u[l] = (T *)st->u[l];
+  }
+  sp.vacc = st->vacc;
+  // Roots in decreasing subtree size (longest first), and the LDS each one
+  // needs; a root whose state does not fit runs in global memory.
+  const int64_t nr = f->n_roots;
+  const uint32_t budget = kLdsPerWorkgroup - kStaticLds;
+  std::vector<std::pair<int64_t, int32_t>> order((size_t)nr);
+  uint32_t max_bytes = 0;
+  int64_t work[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // edges, internal, roots, level 7
+  for (int64_t j = 0; j < nr; ++j) {
+    int cnt[9];
+    int mx = 0;
+    int64_t tot = 0;
+    for (int l = 0; l <= 8; ++l) {
+      const int32_t *o = f->h_root_off + (size_t)l * (nr + 1);
+      cnt[l] = o[j + 1] - o[j];
+      mx = cnt[l] > mx ? cnt[l] : mx;
+      tot += cnt[l];
+    }
+    const LdsLayout L = lds_layout(cnt, sizeof(T));
+    const bool lds = !force_global && L.bytes <= budget && mx < 65535;
+    if (lds) max_bytes = L.bytes > max_bytes ? L.bytes : max_bytes;
+    int64_t *w = work[lds ? 0 : 1];
+    for (int l = 1; l <= 8; ++l) w[0] += cnt[l];
+    for (int l = 0; l <= 7; ++l) w[1] += cnt[l];
+    w[2] += 1;
+    w[3] += cnt[7];
+    order[(size_t)j] = {-tot, (int32_t)j};
+  }
+  std::stable_sort(order.begin(), order.end());
+  std::vector<int32_t> ids((size_t)nr);
+  for (int64_t j = 0; j < nr; ++j) ids[(size_t)j] = order[(size_t)j].second;
+  int32_t *d_roots = nullptr;
+  PASUR_TRY_HIP(hipMallocAsync((void **)&d_roots, sizeof(int32_t) * (nr > 0 ? nr : 1), s));
+  hipError_t e = hipMemcpyAsync(d_roots, ids.data(), sizeof(int32_t) * ids.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vector goes out of scope
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_cfr_root<T, BLOCK>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+  if (e == hipSuccess) {
+    // profile record: kernel 2 if every root is LDS-resident, else 3
+    const int kid = work[1][2] == 0 ? 2 : 3;
+    ProfScope ps(kid, -1, s, work[0][0] + work[1][0], work[0][1] + work[1][1],
+                 work[0][2] + work[1][2], work[0][3] + work[1][3], n_iters);
+    k_cfr_root<T, BLOCK><<<(unsigned)nr, BLOCK, max_bytes, s>>>(
+        tp, sp, d_roots, d_ks, n_iters, p->variant, p->rm_mode, p->eps,
+        force_global ? 0u : max_bytes);
+    e = hipGetLastError();
+  }
+  (void)hipFreeAsync(d_roots, s);
+  if (e != hipSuccess) {
+    set_error("per-root sweep launch: %s", hipGetErrorString(e));
+    return PASUR_E_HIP;
+  }
+  return PASUR_OK;
+}
+
+template <class T>
+int iterate_roots(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p,
+                  int64_t t0, int n_iters, hipStream_t s) {
+  if (n_iters == 0) return PASUR_OK;
+  std::vector<IterK> ks((size_t)n_iters);
+  for (int i = 0; i < n_iters; ++i) {
+    const IterConsts ic = consts_for(p, t0 + i);
+    ks[i].dpos = ic.dpos;
+    ks[i].dneg = ic.dneg;
+    ks[i].avg_w = ic.avg_w;
+    ks[i].avg_t = ic.avg_t;
+  }
+  IterK *d_ks = nullptr;
+  PASUR_TRY_HIP(hipMallocAsync((void **)&d_ks, sizeof(IterK) * ks.size(), s));
+  hipError_t e = hipMemcpyAsync(d_ks, ks.data(), sizeof(IterK) * ks.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // ks goes out of scope
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(d_ks, s);
+    set_error("iteration constants: %s", hipGetErrorString(e));
+    return PASUR_E_HIP;
+  }
+  const bool force_global = p->schedule == PASUR_SCHED_ROOT_GLOBAL;
+  int rc;
+  switch (p->block) {
+    case 256: rc = launch_roots<T, 256>(f, st, p, d_ks, n_iters, force_global, s); break;
+    case 512: rc = launch_roots<T, 512>(f, st, p, d_ks, n_iters, force_global, s); break;
+    default: rc = launch_roots<T, 1024>(f, st, p, d_ks, n_iters, force_global, s); break;
+  }
+  (void)hipFreeAsync(d_ks, s);
+  return rc;
 }
 
 template <class T, class L>
@@ -347,9 +762,17 @@ extern "C" int pasur_cfr_iterate(const pasur_fgt *f, const pasur_cfr_state *st,
     set_error("unknown variant or regret-matching mode");
     return PASUR_E_RANGE;
   }
+  if (p->schedule < 0 || p->schedule > 2 || (p->block != 0 && p->block != 256 &&
+                                               p->block != 512 && p->block != 1024)) {
+    set_error("unknown schedule or block size");
+    return PASUR_E_RANGE;
+  }
   hipStream_t s = (hipStream_t)stream;
-  return st->dtype == PASUR_F32 ? iterate_t<float>(f, st, p, t0, n_iters, s)
-                                : iterate_t<double>(f, st, p, t0, n_iters, s);
+  if (p->schedule == PASUR_SCHED_LEVEL_SYNC)
+    return st->dtype == PASUR_F32 ? iterate_t<float>(f, st, p, t0, n_iters, s)
+                                  : iterate_t<double>(f, st, p, t0, n_iters, s);
+  return st->dtype == PASUR_F32 ? iterate_roots<float>(f, st, p, t0, n_iters, s)
+                                : iterate_roots<double>(f, st, p, t0, n_iters, s);
 }
 
 extern "C" int pasur_average_strategy(const pasur_fgt *f, const pasur_cfr_state *st,
@@ -468,7 +891,7 @@ extern "C" int pasur_profile_enable(int on) {
 }
 
 extern "C" int pasur_profile_read(int64_t cap, int32_t *kernel, int32_t *level, float *ms,
-                                  int64_t *n_out) {
+                                  int64_t *work, int64_t *n_out) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   if (!n_out) {
     set_error("n_out is NULL");
@@ -483,6 +906,8 @@ extern "C" int pasur_profile_read(int64_t cap, int32_t *kernel, int32_t *level, 
     if (kernel) kernel[i] = g_prof[i].kernel;
     if (level) level[i] = g_prof[i].level;
     if (ms) ms[i] = t;
+    if (work)
+      for (int k = 0; k < 5; ++k) work[5 * i + k] = g_prof[i].work[k];
   }
   return PASUR_OK;
 }

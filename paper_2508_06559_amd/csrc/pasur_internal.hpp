@@ -104,4 +104,9 @@ struct pasur_fgt {
   pasur_root *next_roots;
   int32_t *link;
   int16_t *leaf_base;
+  // root_off[l][j] .. root_off[l][j+1]: level-l nodes of root j's subtree
+  // (levels are root-major), on the device and copied to the host
+  int64_t n_roots;
+  int32_t *root_off[9];
+  int32_t *h_root_off;  // 9 * (n_roots + 1), level-major
 };

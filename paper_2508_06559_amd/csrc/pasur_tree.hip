@@ -8,6 +8,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -673,6 +674,8 @@ extern "C" void pasur_fgt_free(pasur_fgt *f) {
   dev_free(f->next_roots);
   dev_free(f->link);
   dev_free(f->leaf_base);
+  for (int l = 0; l < 9; ++l) dev_free(f->root_off[l]);
+  std::free(f->h_root_off);
   delete f;
 }
 
@@ -750,17 +753,26 @@ int unfold_impl(const pasur_gt *gt, const pasur_root *d_roots, int64_t n_roots, 
     return PASUR_E_INVAL;
   }
   // --- per level: root offsets
-  int32_t *off[9];
+  int32_t **off = f->root_off;
   int32_t *sz = nullptr;
   PASUR_TRY(s.alloc(&sz, n_roots));
+  f->n_roots = n_roots;
   for (int l = 0; l <= 8; ++l) {
-    PASUR_TRY(s.alloc(&off[l], n_roots + 1));
+    PASUR_TRY(dev_alloc(&off[l], n_roots + 1));
     k_range_sizes<<<grid_for(n_roots), kThreads, 0, stream>>>(n_roots, lo + (int64_t)l * n_roots,
                                                               hi + (int64_t)l * n_roots, sz);
     int64_t total = 0;
     PASUR_TRY(scan_counts(sz, n_roots, off[l], &total, stream));
     f->n[l] = total;
   }
+  f->h_root_off = (int32_t *)std::malloc(sizeof(int32_t) * 9 * (size_t)(n_roots + 1));
+  if (!f->h_root_off) {
+    set_error("host allocation failed");
+    return PASUR_E_NOMEM;
+  }
+  for (int l = 0; l <= 8; ++l)
+    PASUR_TRY_HIP(hipMemcpy(f->h_root_off + (size_t)l * (n_roots + 1), off[l],
+                            sizeof(int32_t) * (n_roots + 1), hipMemcpyDeviceToHost));
   // --- per level: FGT arrays
   for (int l = 0; l <= 8; ++l) {
     const int64_t n = f->n[l];
