@@ -162,10 +162,11 @@ typedef struct {
 typedef enum { PASUR_DCFR = 0, PASUR_CFR_PLUS = 1, PASUR_CFR_VANILLA = 2 } pasur_variant;
 typedef enum { PASUR_RM_FLOOR = 0, PASUR_RM_POSITIVE = 1 } pasur_rm_mode;
 /* Kernel schedule of pasur_cfr_iterate (same results bit for bit):
- * ROOT (default): one persistent workgroup per root runs all iterations on
- *   that root's subtree, its state held in LDS when it fits (else in global
- *   memory); LEVEL_SYNC: one launch per level and sweep direction;
- * ROOT_GLOBAL: the per-root schedule with state always in global memory. */
+ * ROOT (default): one persistent workgroup per segment (a run of
+ *   consecutive roots, see seg_nodes) runs all iterations on that segment's
+ *   subtrees, its state held in LDS when it fits (else in global memory);
+ * LEVEL_SYNC: one launch per level and sweep direction;
+ * ROOT_GLOBAL: the persistent schedule with state always in global memory. */
 typedef enum { PASUR_SCHED_ROOT = 0, PASUR_SCHED_LEVEL_SYNC = 1,
                PASUR_SCHED_ROOT_GLOBAL = 2 } pasur_schedule;
 typedef struct {
@@ -177,8 +178,10 @@ typedef struct {
   double gamma; /* DCFR average-strategy exponent (paper: 2) */
   double eps;   /* regret floor (paper's executed rule: 1e-8) */
   int schedule; /* pasur_schedule */
-  int block;    /* threads per workgroup of the per-root schedule: 0 (= 1024),
+  int block;    /* threads per workgroup of the persistent schedule: 0 (= 1024),
                    256, 512 or 1024 */
+  int seg_nodes; /* persistent schedule: a workgroup takes a run of consecutive
+                    roots of up to seg_nodes nodes (0: one root each) */
 } pasur_cfr_params;
 
 /* R = 0, Sbar = 0, sigma uniform over every node's children, vacc = 0. */
@@ -191,6 +194,27 @@ int pasur_cfr_init(const pasur_fgt *fgt, const pasur_cfr_state *st, void *stream
 int pasur_cfr_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st,
                       const pasur_cfr_params *p, int64_t t0, int n_iters,
                       void *stream);
+/* ---- a12: batched solve -------------------------------------------------------
+ * A plan gathers n_items (unfolded tree, solver state) pairs -- e.g. one
+ * round of many deals -- into one persistent launch of the segment schedule
+ * and uploads everything the launch needs: item descriptors, the segment
+ * list (longest first) and the DCFR constants of iterations
+ * t_first..t_last (computed on the host).  pasur_plan_iterate only enqueues
+ * one kernel, so it can be captured into a HIP graph; it runs iterations
+ * t0..t0+n_iters-1 (within the plan's range) on every item, with results
+ * bit-identical to pasur_cfr_iterate on each item.  Items keep their own
+ * caller-owned arrays, which must outlive the plan.  All items share one
+ * dtype.  plan_create synchronises `stream`. */
+typedef struct pasur_plan pasur_plan;
+int pasur_plan_create(const pasur_fgt *const *fgts, const pasur_cfr_state *const *states,
+                      int n_items, const pasur_cfr_params *p, int64_t t_first,
+                      int64_t t_last, pasur_plan **out, void *stream);
+int pasur_plan_iterate(const pasur_plan *plan, int64_t t0, int n_iters, void *stream);
+/* info: segments, LDS-resident segments, dynamic LDS bytes, threads per
+ * workgroup, edges, internal nodes, roots, level-7 nodes. */
+int pasur_plan_info(const pasur_plan *plan, int64_t info[8]);
+void pasur_plan_free(pasur_plan *plan);
+
 /* Normalise (CodeSnippet CFR): sigma_bar = Sbar / sum over siblings, uniform
  * where that sum is 0.  sigma_bar[l] (device, `st->dtype`, levels 1..8). */
 int pasur_average_strategy(const pasur_fgt *fgt, const pasur_cfr_state *st,

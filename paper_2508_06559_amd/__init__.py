@@ -39,13 +39,13 @@ SCHED_ROOT, SCHED_LEVEL_SYNC, SCHED_ROOT_GLOBAL = 0, 1, 2
 class CfrParams(C.Structure):
     _fields_ = [("variant", C.c_int), ("rm_mode", C.c_int), ("alpha", C.c_double),
                 ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double),
-                ("schedule", C.c_int), ("block", C.c_int)]
+                ("schedule", C.c_int), ("block", C.c_int), ("seg_nodes", C.c_int)]
 
 
-def paper_params(schedule: int = SCHED_ROOT, block: int = 0) -> CfrParams:
+def paper_params(schedule: int = SCHED_ROOT, block: int = 0, seg_nodes: int = 0) -> CfrParams:
     """DCFR with the paper's constants (alpha 1.5, beta 0, gamma 2) and its
     regret-matching floor (1e-8)."""
-    return CfrParams(DCFR, RM_FLOOR, 1.5, 0.0, 2.0, 1e-8, schedule, block)
+    return CfrParams(DCFR, RM_FLOOR, 1.5, 0.0, 2.0, 1e-8, schedule, block, seg_nodes)
 
 
 class _State(C.Structure):
@@ -84,6 +84,11 @@ def lib():
         L.pasur_average_strategy.argtypes = [vp, vp, vp, vp]
         L.pasur_round_values.argtypes = [vp, vp, i32, i64, vp, vp, vp]
         L.pasur_tree_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+        L.pasur_plan_create.argtypes = [vp, vp, i32, vp, i64, i64, C.POINTER(vp), vp]
+        L.pasur_plan_iterate.argtypes = [vp, i64, i32, vp]
+        L.pasur_plan_info.argtypes = [vp, vp]
+        L.pasur_plan_free.argtypes = [vp]
+        L.pasur_plan_free.restype = None
         L.pasur_profile_enable.argtypes = [i32]
         L.pasur_profile_read.argtypes = [i64, vp, vp, vp, vp, C.POINTER(C.c_int64)]
         _lib = L
@@ -311,6 +316,43 @@ def tree_values(fgt: UnfoldedTree, d_leaf, dtype: int, sigma: Optional[List], mo
     return d_out
 
 
+class Plan:
+    """pasur_plan: a batch of (unfolded tree, solver state) items iterated by
+    one persistent launch per call (a12).  Keeps the items alive."""
+
+    def __init__(self, states: Sequence[CfrState], params: Optional[CfrParams] = None,
+                 t_first: int = 1, t_last: int = 1000, stream=None):
+        self.states = list(states)
+        self.params = params if params is not None else paper_params()
+        fg = (C.c_void_p * len(self.states))(*[st.fgt.h for st in self.states])
+        sp = (C.c_void_p * len(self.states))(*[C.addressof(st.c) for st in self.states])
+        h = C.c_void_p()
+        _check(lib().pasur_plan_create(fg, sp, len(self.states), C.byref(self.params), t_first,
+                                       t_last, C.byref(h), _stream(stream)), "pasur_plan_create")
+        self.h = h
+        self.t_first, self.t_last = t_first, t_last
+        info = (C.c_int64 * 8)()
+        _check(lib().pasur_plan_info(self.h, info), "pasur_plan_info")
+        (self.n_segs, self.n_lds_segs, self.lds_bytes, self.block, self.edges, self.internal,
+         self.roots, self.n7) = list(info)
+
+    def iterate(self, t0: int, n_iters: int, stream=None):
+        _check(lib().pasur_plan_iterate(self.h, t0, n_iters, _stream(stream)), "pasur_plan_iterate")
+        for st in self.states:
+            st.t = t0 + n_iters
+
+    def free(self):
+        if getattr(self, "h", None):
+            lib().pasur_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 def profile_enable(on: bool):
     _check(lib().pasur_profile_enable(1 if on else 0), "pasur_profile_enable")
 
@@ -332,4 +374,4 @@ def profile_read():
     return k[: n.value], lv[: n.value], ms[: n.value], work[: n.value]
 
 
-from .solver import SubgameSolver, RoundResult  # noqa: E402  (driver over the calls above)
+from .solver import SubgameSolver, RoundResult, BatchSolver  # noqa: E402  (drivers over the calls above)

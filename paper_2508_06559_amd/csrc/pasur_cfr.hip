@@ -171,30 +171,34 @@ __global__ void k_up(int64_t np, int mover, const int32_t *__restrict__ cb,
 
 
 // ---------------------------------------------------------------------------
-// Persistent per-root schedule.  The subgames below different roots never
+// Persistent segment schedule.  The subgames below different roots never
 // interact inside a round (every root has reach 1), so one workgroup owns a
-// root's subtree and runs all iterations on it with workgroup barriers
-// between levels.  When the subtree's state fits in LDS (160 KB per
+// segment -- a run of consecutive roots of one tree, whose nodes are
+// contiguous on every level -- and runs all iterations on it with workgroup
+// barriers between levels.  When the segment's state fits in LDS (160 KB per
 // workgroup on gfx950) it is loaded once, iterated in LDS and written back
-// once; otherwise the same loop runs on global memory (L2/MALL resident).
-// Each parent is still updated by one thread in child order, so results are
-// bit-identical to the level-synchronous kernels.
+// once; otherwise the same loop runs in place in global memory (L2/MALL
+// resident).  Each parent is still updated by one thread in child order, so
+// results are bit-identical to the level-synchronous kernels.  A launch can
+// cover the trees of many deals (batched solve).
 // ---------------------------------------------------------------------------
 
 struct IterK {
   double dpos, dneg, avg_w, avg_t;
 };
 
-struct TreePtrs {
-  const int32_t *off[9];
-  const int32_t *parent[9];
-  const int32_t *cb[8];
-};
-
+// One (tree, state) pair of a launch.
 template <class T>
-struct StatePtrs {
+struct ItemDesc {
+  const int32_t *off[9];     // per-root level offsets
+  const int32_t *parent[9];  // levels 1..8
+  const int32_t *cb[9];      // levels 0..7
   T *sigma[9], *R[9], *Sbar[9], *ra[9], *rb[9], *u[9];
   double *vacc;
+};
+
+struct Seg {
+  int32_t item, j0, j1, pad;  // roots j0 .. j1-1 of item
 };
 
 extern __shared__ __align__(16) unsigned char g_lds[];
@@ -204,16 +208,11 @@ struct LdsArr {
   uint32_t off;
   __device__ T &operator[](int i) const { return reinterpret_cast<T *>(g_lds + off)[i]; }
 };
-template <class T>
-struct GlbArr {
-  T *p;
-  __device__ T &operator[](int i) const { return p[i]; }
-};
 
-// Byte layout of one root's subtree state in LDS (shared by host sizing
-// and device carving): per level sigma, R, Sbar (levels 1..8), u (0..8),
-// reachA, reachB (0..7) as T, then parent (1..8) and child_begin (0..7) as
-// 16-bit indices local to the subtree; every array 16-byte aligned.
+// Byte layout of one segment's state in LDS (shared by host sizing and
+// device carving): per level sigma, R, Sbar (levels 1..8), u (0..8), reachA,
+// reachB (0..7) as T, then parent (1..8) and child_begin (0..7) as 16-bit
+// indices local to the segment; every array 16-byte aligned.
 struct LdsLayout {
   uint32_t sg[9], R[9], Sb[9], u[9], ra[9], rb[9], par[9], cb[9];
   uint32_t bytes;
@@ -255,8 +254,9 @@ struct Sub {
   int cnt[9];
 };
 
-// All iterations of one subtree (FindReachProbability then FindUtility per
-// iteration, as in k_down / k_up).
+// All iterations of one segment (FindReachProbability then FindUtility per
+// iteration, as in k_down / k_up).  Thread t owns root t of the segment at
+// level 0 and accumulates its vacc.
 template <class T, class SubT>
 __device__ inline void subtree_iterations(const SubT &S, const IterK *__restrict__ ks,
                                           int n_iters, int variant, int rm_mode, double eps,
@@ -317,7 +317,7 @@ __device__ inline void subtree_iterations(const SubT &S, const IterK *__restrict
           S.Sb[l][q] = (T)(k.avg_w * (double)S.Sb[l][q] + add);
           S.sg[l][q] = (T)s_new;
         }
-        if (l == 1) vacc_acc += uh;
+        if (l == 1) vacc_acc += uh;  // h == tid: segments hold at most BLOCK roots
       }
       __syncthreads();
     }
@@ -325,10 +325,10 @@ __device__ inline void subtree_iterations(const SubT &S, const IterK *__restrict
 }
 
 template <class T, int BLOCK>
-__device__ inline void root_in_lds(const TreePtrs &tp, const StatePtrs<T> &sp, int j,
-                                   const int lo[9], const int cnt[9], const LdsLayout &L,
-                                   const IterK *__restrict__ ks, int n_iters, int variant,
-                                   int rm_mode, double eps) {
+__device__ inline void seg_in_lds(const ItemDesc<T> &D, int j0, int nroots, const int lo[9],
+                                  const int cnt[9], const LdsLayout &L,
+                                  const IterK *__restrict__ ks, int n_iters, int variant,
+                                  int rm_mode, double eps) {
   const int tid = threadIdx.x;
   Sub<LdsArr<T>, LdsArr<uint16_t>> S;
 #pragma unroll
@@ -345,46 +345,46 @@ __device__ inline void root_in_lds(const TreePtrs &tp, const StatePtrs<T> &sp, i
     S.cb_sub[l] = 0;
     S.cnt[l] = cnt[l];
   }
-  // load the subtree's state
+  // load the segment's state
 #pragma unroll
   for (int l = 0; l <= 8; ++l) {
     for (int i = tid; i < cnt[l]; i += BLOCK) {
       if (l >= 1) {
-        S.sg[l][i] = sp.sigma[l][lo[l] + i];
-        S.Rr[l][i] = sp.R[l][lo[l] + i];
-        S.Sb[l][i] = sp.Sbar[l][lo[l] + i];
-        S.par[l][i] = (uint16_t)(tp.parent[l][lo[l] + i] - lo[l - 1]);
+        S.sg[l][i] = D.sigma[l][lo[l] + i];
+        S.Rr[l][i] = D.R[l][lo[l] + i];
+        S.Sb[l][i] = D.Sbar[l][lo[l] + i];
+        S.par[l][i] = (uint16_t)(D.parent[l][lo[l] + i] - lo[l - 1]);
       }
-      if (l == 8) S.uu[l][i] = sp.u[l][lo[l] + i];
+      if (l == 8) S.uu[l][i] = D.u[l][lo[l] + i];
       if (l == 0) {
-        S.ra[0][i] = sp.ra[0][lo[0] + i];
-        S.rb[0][i] = sp.rb[0][lo[0] + i];
+        S.ra[0][i] = D.ra[0][lo[0] + i];
+        S.rb[0][i] = D.rb[0][lo[0] + i];
       }
     }
     if (l <= 7)
       for (int i = tid; i <= cnt[l]; i += BLOCK)
-        S.cbl[l][i] = (uint16_t)(tp.cb[l][lo[l] + i] - lo[l + 1]);
+        S.cbl[l][i] = (uint16_t)(D.cb[l][lo[l] + i] - lo[l + 1]);
   }
   __syncthreads();
-  double vacc_acc = tid == 0 ? sp.vacc[j] : 0.0;
+  double vacc_acc = tid < nroots ? D.vacc[j0 + tid] : 0.0;
   subtree_iterations<T>(S, ks, n_iters, variant, rm_mode, eps, vacc_acc);
   // write the state back
 #pragma unroll
   for (int l = 0; l <= 8; ++l) {
     for (int i = tid; i < cnt[l]; i += BLOCK) {
       if (l >= 1) {
-        sp.sigma[l][lo[l] + i] = S.sg[l][i];
-        sp.R[l][lo[l] + i] = S.Rr[l][i];
-        sp.Sbar[l][lo[l] + i] = S.Sb[l][i];
+        D.sigma[l][lo[l] + i] = S.sg[l][i];
+        D.R[l][lo[l] + i] = S.Rr[l][i];
+        D.Sbar[l][lo[l] + i] = S.Sb[l][i];
       }
       if (l <= 7) {
-        sp.u[l][lo[l] + i] = S.uu[l][i];
-        sp.ra[l][lo[l] + i] = S.ra[l][i];
-        sp.rb[l][lo[l] + i] = S.rb[l][i];
+        D.u[l][lo[l] + i] = S.uu[l][i];
+        D.ra[l][lo[l] + i] = S.ra[l][i];
+        D.rb[l][lo[l] + i] = S.rb[l][i];
       }
     }
   }
-  if (tid == 0) sp.vacc[j] = vacc_acc;
+  if (tid < nroots) D.vacc[j0 + tid] = vacc_acc;
 }
 
 // Global-memory arrays addressed through a per-workgroup pointer table kept
@@ -399,22 +399,21 @@ struct TabArr {
 };
 
 template <class T, int BLOCK>
-__device__ inline void root_in_global(const TreePtrs &tp, const StatePtrs<T> &sp, int j,
-                                      const IterK *__restrict__ ks, int n_iters, int variant,
-                                      int rm_mode, double eps) {
+__device__ inline void seg_in_global(const ItemDesc<T> &D, int j0, int nroots, const int lo[9],
+                                     const int cnt[9], const IterK *__restrict__ ks,
+                                     int n_iters, int variant, int rm_mode, double eps) {
   if (threadIdx.x < 9) {
     const int l = threadIdx.x;
-    const int lo = tp.off[l][j];
-    g_ptab[0][l] = sp.sigma[l] ? (void *)(sp.sigma[l] + lo) : nullptr;
-    g_ptab[1][l] = sp.R[l] ? (void *)(sp.R[l] + lo) : nullptr;
-    g_ptab[2][l] = sp.Sbar[l] ? (void *)(sp.Sbar[l] + lo) : nullptr;
-    g_ptab[3][l] = (void *)(sp.u[l] + lo);
-    g_ptab[4][l] = sp.ra[l] ? (void *)(sp.ra[l] + lo) : nullptr;
-    g_ptab[5][l] = sp.rb[l] ? (void *)(sp.rb[l] + lo) : nullptr;
-    g_ptab[6][l] = l >= 1 ? (void *)(tp.parent[l] + lo) : nullptr;
-    g_ptab[7][l] = l <= 7 ? (void *)(tp.cb[l] + lo) : nullptr;
-    g_sub[0][l] = l >= 1 ? tp.off[l - 1][j] : 0;
-    g_sub[1][l] = l <= 7 ? tp.off[l + 1][j] : 0;
+    g_ptab[0][l] = l >= 1 ? (void *)(D.sigma[l] + lo[l]) : nullptr;
+    g_ptab[1][l] = l >= 1 ? (void *)(D.R[l] + lo[l]) : nullptr;
+    g_ptab[2][l] = l >= 1 ? (void *)(D.Sbar[l] + lo[l]) : nullptr;
+    g_ptab[3][l] = (void *)(D.u[l] + lo[l]);
+    g_ptab[4][l] = l <= 7 ? (void *)(D.ra[l] + lo[l]) : nullptr;
+    g_ptab[5][l] = l <= 7 ? (void *)(D.rb[l] + lo[l]) : nullptr;
+    g_ptab[6][l] = l >= 1 ? (void *)(D.parent[l] + lo[l]) : nullptr;
+    g_ptab[7][l] = l <= 7 ? (void *)(D.cb[l] + lo[l]) : nullptr;
+    g_sub[0][l] = l >= 1 ? lo[l - 1] : 0;
+    g_sub[1][l] = l <= 7 ? lo[l + 1] : 0;
   }
   __syncthreads();
   struct SubT {
@@ -434,34 +433,36 @@ __device__ inline void root_in_global(const TreePtrs &tp, const StatePtrs<T> &sp
     X.par[l].l = X.cbl[l].l = l;
     X.par_sub[l] = g_sub[0][l];
     X.cb_sub[l] = g_sub[1][l];
-    X.cnt[l] = tp.off[l][j + 1] - tp.off[l][j];
+    X.cnt[l] = cnt[l];
   }
-  double vacc_acc = threadIdx.x == 0 ? sp.vacc[j] : 0.0;
+  double vacc_acc = threadIdx.x < nroots ? D.vacc[j0 + threadIdx.x] : 0.0;
   subtree_iterations<T>(X, ks, n_iters, variant, rm_mode, eps, vacc_acc);
-  if (threadIdx.x == 0) sp.vacc[j] = vacc_acc;
+  if (threadIdx.x < nroots) D.vacc[j0 + threadIdx.x] = vacc_acc;
 }
 
-// One workgroup per root; the root's subtree runs in LDS when its state fits
-// in the launch's dynamic LDS (lds_bytes), otherwise in global memory.
+// One workgroup per segment; the segment runs in LDS when its state fits in
+// the launch's dynamic LDS (lds_bytes), otherwise in global memory.
 template <class T, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-    k_cfr_root(TreePtrs tp, StatePtrs<T> sp, const int32_t *__restrict__ roots,
-               const IterK *__restrict__ ks, int n_iters, int variant, int rm_mode, double eps,
-               uint32_t lds_bytes) {
-  const int j = roots[blockIdx.x];
+    k_cfr_seg(const ItemDesc<T> *__restrict__ items, const Seg *__restrict__ segs,
+              const IterK *__restrict__ ks, int n_iters, int variant, int rm_mode, double eps,
+              uint32_t lds_bytes) {
+  const Seg sg = segs[blockIdx.x];
+  const ItemDesc<T> &D = items[sg.item];
   int lo[9], cnt[9];
   int mx = 0;
 #pragma unroll
   for (int l = 0; l <= 8; ++l) {
-    lo[l] = tp.off[l][j];
-    cnt[l] = tp.off[l][j + 1] - lo[l];
+    lo[l] = D.off[l][sg.j0];
+    cnt[l] = D.off[l][sg.j1] - lo[l];
     mx = cnt[l] > mx ? cnt[l] : mx;
   }
   const LdsLayout L = lds_layout(cnt, sizeof(T));
   if (L.bytes <= lds_bytes && mx < 65535)
-    root_in_lds<T, BLOCK>(tp, sp, j, lo, cnt, L, ks, n_iters, variant, rm_mode, eps);
+    seg_in_lds<T, BLOCK>(D, sg.j0, sg.j1 - sg.j0, lo, cnt, L, ks, n_iters, variant, rm_mode, eps);
   else
-    root_in_global<T, BLOCK>(tp, sp, j, ks, n_iters, variant, rm_mode, eps);
+    seg_in_global<T, BLOCK>(D, sg.j0, sg.j1 - sg.j0, lo, cnt, ks, n_iters, variant, rm_mode,
+                            eps);
 }
 
 template <class T>
@@ -598,110 +599,257 @@ constexpr uint32_t kLdsPerWorkgroup = 160 * 1024;
 constexpr uint32_t kStaticLds = 8 * 9 * sizeof(void *) + 2 * 9 * sizeof(int) + 64;
 
 template <class T, int BLOCK>
-int launch_roots(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p,
-                 const IterK *d_ks, int n_iters, bool force_global, hipStream_t s) {
-  TreePtrs tp;
-  StatePtrs<T> sp;
-  for (int l = 0; l <= 8; ++l) {
-    tp.off[l] = f->root_off[l];
-    tp.parent[l] = f->parent[l];
-    if (l <= 7) tp.cb[l] = f->child_begin[l];
-    sp.sigma[l] = l >= 1 ? (T *)st->sigma[l] : nullptr;
-    sp.R[l] = l >= 1 ? (T *)st->R[l] : nullptr;
-    sp.Sbar[l] = l >= 1 ? (T *)st->Sbar[l] : nullptr;
-    sp.ra[l] = l <= 7 ? (T *)st->reachA[l] : nullptr;
-    sp.rb[l] = l <= 7 ? (T *)st->reachB[l] : nullptr;
-    sp.u[l] = (T *)st->u[l];
-  }
-  sp.vacc = st->vacc;
-  // Roots in decreasing subtree size (longest first), and the LDS each one
-  // needs; a root whose state does not fit runs in global memory.
-  const int64_t nr = f->n_roots;
-  const uint32_t budget = kLdsPerWorkgroup - kStaticLds;
-  std::vector<std::pair<int64_t, int32_t>> order((size_t)nr);
+void *seg_kernel() {
+  return (void *)k_cfr_seg<T, BLOCK>;
+}
+
+}  // namespace
+
+struct pasur_plan {
+  int dtype, block, variant, rm_mode;
+  double eps;
+  int64_t t_first, t_last;
+  int n_items, n_segs;
+  void *d_items;
+  Seg *d_segs;
+  IterK *d_ks;
+  uint32_t lds_bytes;
+  int64_t work[4];  // edges, internal nodes, roots, level-7 nodes
+  int64_t n_lds_segs;
+};
+
+namespace {
+
+template <class T>
+int plan_build(pasur_plan *pl, const pasur_fgt *const *fgts, const pasur_cfr_state *const *states,
+               const pasur_cfr_params *p, int force_global, hipStream_t s) {
+  const int n_items = pl->n_items;
+  std::vector<ItemDesc<T>> items((size_t)n_items);
+  std::vector<Seg> segs;
+  std::vector<int64_t> seg_size;
+  const uint32_t budget = force_global ? 0u : kLdsPerWorkgroup - kStaticLds;
   uint32_t max_bytes = 0;
-  int64_t work[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // edges, internal, roots, level 7
-  for (int64_t j = 0; j < nr; ++j) {
-    int cnt[9];
-    int mx = 0;
-    int64_t tot = 0;
+  for (int64_t k = 0; k < 4; ++k) pl->work[k] = 0;
+  pl->n_lds_segs = 0;
+  for (int it = 0; it < n_items; ++it) {
+    const pasur_fgt *f = fgts[it];
+    const pasur_cfr_state *st = states[it];
+    ItemDesc<T> &D = items[(size_t)it];
     for (int l = 0; l <= 8; ++l) {
-      const int32_t *o = f->h_root_off + (size_t)l * (nr + 1);
-      cnt[l] = o[j + 1] - o[j];
-      mx = cnt[l] > mx ? cnt[l] : mx;
-      tot += cnt[l];
+      D.off[l] = f->root_off[l];
+      D.parent[l] = f->parent[l];
+      D.cb[l] = l <= 7 ? f->child_begin[l] : nullptr;
+      D.sigma[l] = l >= 1 ? (T *)st->sigma[l] : nullptr;
+      D.R[l] = l >= 1 ? (T *)st->R[l] : nullptr;
+      D.Sbar[l] = l >= 1 ? (T *)st->Sbar[l] : nullptr;
+      D.ra[l] = l <= 7 ? (T *)st->reachA[l] : nullptr;
+      D.rb[l] = l <= 7 ? (T *)st->reachB[l] : nullptr;
+      D.u[l] = (T *)st->u[l];
     }
-    const LdsLayout L = lds_layout(cnt, sizeof(T));
-    const bool lds = !force_global && L.bytes <= budget && mx < 65535;
-    if (lds) max_bytes = L.bytes > max_bytes ? L.bytes : max_bytes;
-    int64_t *w = work[lds ? 0 : 1];
-    for (int l = 1; l <= 8; ++l) w[0] += cnt[l];
-    for (int l = 0; l <= 7; ++l) w[1] += cnt[l];
-    w[2] += 1;
-    w[3] += cnt[7];
-    order[(size_t)j] = {-tot, (int32_t)j};
+    D.vacc = st->vacc;
+    // Segments: runs of consecutive roots, closed when the next root would
+    // exceed seg_nodes nodes, the workgroup's thread count, or LDS.
+    const int64_t nr = f->n_roots;
+    auto cnt_of = [&](int64_t a, int64_t b, int cnt[9]) {
+      int64_t tot = 0;
+      for (int l = 0; l <= 8; ++l) {
+        const int32_t *o = f->h_root_off + (size_t)l * (nr + 1);
+        cnt[l] = o[b] - o[a];
+        tot += cnt[l];
+      }
+      return tot;
+    };
+    int64_t j0 = 0;
+    while (j0 < nr) {
+      int64_t j1 = j0 + 1;
+      int cnt[9];
+      int64_t tot = cnt_of(j0, j1, cnt);
+      while (p->seg_nodes > 0 && j1 < nr && j1 - j0 < pl->block) {
+        int c2[9];
+        const int64_t t2 = cnt_of(j0, j1 + 1, c2);
+        int mx = 0;
+        for (int l = 0; l <= 8; ++l) mx = c2[l] > mx ? c2[l] : mx;
+        if (t2 > p->seg_nodes || lds_layout(c2, sizeof(T)).bytes > budget || mx >= 65535) break;
+        ++j1;
+        tot = t2;
+        for (int l = 0; l <= 8; ++l) cnt[l] = c2[l];
+      }
+      int mx = 0;
+      for (int l = 0; l <= 8; ++l) mx = cnt[l] > mx ? cnt[l] : mx;
+      const uint32_t bytes = lds_layout(cnt, sizeof(T)).bytes;
+      if (bytes <= budget && mx < 65535) {
+        max_bytes = bytes > max_bytes ? bytes : max_bytes;
+        pl->n_lds_segs += 1;
+      }
+      for (int l = 1; l <= 8; ++l) pl->work[0] += cnt[l];
+      for (int l = 0; l <= 7; ++l) pl->work[1] += cnt[l];
+      pl->work[2] += j1 - j0;
+      pl->work[3] += cnt[7];
+      Seg sg;
+      sg.item = it;
+      sg.j0 = (int32_t)j0;
+      sg.j1 = (int32_t)j1;
+      sg.pad = 0;
+      segs.push_back(sg);
+      seg_size.push_back(tot);
+      j0 = j1;
+    }
   }
-  std::stable_sort(order.begin(), order.end());
-  std::vector<int32_t> ids((size_t)nr);
-  for (int64_t j = 0; j < nr; ++j) ids[(size_t)j] = order[(size_t)j].second;
-  int32_t *d_roots = nullptr;
-  PASUR_TRY_HIP(hipMallocAsync((void **)&d_roots, sizeof(int32_t) * (nr > 0 ? nr : 1), s));
-  hipError_t e = hipMemcpyAsync(d_roots, ids.data(), sizeof(int32_t) * ids.size(),
-                                hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vector goes out of scope
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_cfr_root<T, BLOCK>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
-  if (e == hipSuccess) {
-    // profile record: kernel 2 if every root is LDS-resident, else 3
-    const int kid = work[1][2] == 0 ? 2 : 3;
-    ProfScope ps(kid, -1, s, work[0][0] + work[1][0], work[0][1] + work[1][1],
-                 work[0][2] + work[1][2], work[0][3] + work[1][3], n_iters);
-    k_cfr_root<T, BLOCK><<<(unsigned)nr, BLOCK, max_bytes, s>>>(
-        tp, sp, d_roots, d_ks, n_iters, p->variant, p->rm_mode, p->eps,
-        force_global ? 0u : max_bytes);
-    e = hipGetLastError();
+  // longest segments first
+  std::vector<size_t> idx(segs.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](size_t a, size_t b) { return seg_size[a] > seg_size[b]; });
+  std::vector<Seg> sorted(segs.size());
+  for (size_t i = 0; i < idx.size(); ++i) sorted[i] = segs[idx[i]];
+  pl->n_segs = (int)sorted.size();
+  pl->lds_bytes = force_global ? 0u : max_bytes;
+  // iteration constants for t_first .. t_last, computed on the host
+  const int64_t nt = pl->t_last - pl->t_first + 1;
+  std::vector<IterK> ks((size_t)nt);
+  for (int64_t i = 0; i < nt; ++i) {
+    const IterConsts ic = consts_for(p, pl->t_first + i);
+    ks[(size_t)i].dpos = ic.dpos;
+    ks[(size_t)i].dneg = ic.dneg;
+    ks[(size_t)i].avg_w = ic.avg_w;
+    ks[(size_t)i].avg_t = ic.avg_t;
   }
-  (void)hipFreeAsync(d_roots, s);
-  if (e != hipSuccess) {
-    set_error("per-root sweep launch: %s", hipGetErrorString(e));
-    return PASUR_E_HIP;
-  }
+  PASUR_TRY_HIP(hipMalloc(&pl->d_items, sizeof(ItemDesc<T>) * items.size()));
+  PASUR_TRY_HIP(hipMalloc((void **)&pl->d_segs, sizeof(Seg) * (sorted.size() + 1)));
+  PASUR_TRY_HIP(hipMalloc((void **)&pl->d_ks, sizeof(IterK) * ks.size()));
+  PASUR_TRY_HIP(hipMemcpyAsync(pl->d_items, items.data(), sizeof(ItemDesc<T>) * items.size(),
+                               hipMemcpyHostToDevice, s));
+  PASUR_TRY_HIP(hipMemcpyAsync(pl->d_segs, sorted.data(), sizeof(Seg) * sorted.size(),
+                               hipMemcpyHostToDevice, s));
+  PASUR_TRY_HIP(hipMemcpyAsync(pl->d_ks, ks.data(), sizeof(IterK) * ks.size(),
+                               hipMemcpyHostToDevice, s));
+  PASUR_TRY_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
+  void *kern = pl->block == 256   ? seg_kernel<T, 256>()
+               : pl->block == 512 ? seg_kernel<T, 512>()
+                                  : seg_kernel<T, 1024>();
+  PASUR_TRY_HIP(hipFuncSetAttribute((const void *)kern,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)pl->lds_bytes));
   return PASUR_OK;
 }
 
-template <class T>
-int iterate_roots(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p,
-                  int64_t t0, int n_iters, hipStream_t s) {
-  if (n_iters == 0) return PASUR_OK;
-  std::vector<IterK> ks((size_t)n_iters);
-  for (int i = 0; i < n_iters; ++i) {
-    const IterConsts ic = consts_for(p, t0 + i);
-    ks[i].dpos = ic.dpos;
-    ks[i].dneg = ic.dneg;
-    ks[i].avg_w = ic.avg_w;
-    ks[i].avg_t = ic.avg_t;
-  }
-  IterK *d_ks = nullptr;
-  PASUR_TRY_HIP(hipMallocAsync((void **)&d_ks, sizeof(IterK) * ks.size(), s));
-  hipError_t e = hipMemcpyAsync(d_ks, ks.data(), sizeof(IterK) * ks.size(),
-                                hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);  // ks goes out of scope
-  if (e != hipSuccess) {
-    (void)hipFreeAsync(d_ks, s);
-    set_error("iteration constants: %s", hipGetErrorString(e));
-    return PASUR_E_HIP;
-  }
-  const bool force_global = p->schedule == PASUR_SCHED_ROOT_GLOBAL;
-  int rc;
-  switch (p->block) {
-    case 256: rc = launch_roots<T, 256>(f, st, p, d_ks, n_iters, force_global, s); break;
-    case 512: rc = launch_roots<T, 512>(f, st, p, d_ks, n_iters, force_global, s); break;
-    default: rc = launch_roots<T, 1024>(f, st, p, d_ks, n_iters, force_global, s); break;
-  }
-  (void)hipFreeAsync(d_ks, s);
-  return rc;
+template <class T, int BLOCK>
+void plan_launch(const pasur_plan *pl, int64_t t0, int n_iters, hipStream_t s) {
+  k_cfr_seg<T, BLOCK><<<(unsigned)pl->n_segs, BLOCK, pl->lds_bytes, s>>>(
+      (const ItemDesc<T> *)pl->d_items, pl->d_segs, pl->d_ks + (t0 - pl->t_first), n_iters,
+      pl->variant, pl->rm_mode, pl->eps, pl->lds_bytes);
 }
+
+}  // namespace
+
+extern "C" void pasur_plan_free(pasur_plan *pl) {
+  if (!pl) return;
+  if (pl->d_items) (void)hipFree(pl->d_items);
+  if (pl->d_segs) (void)hipFree(pl->d_segs);
+  if (pl->d_ks) (void)hipFree(pl->d_ks);
+  delete pl;
+}
+
+extern "C" int pasur_plan_create(const pasur_fgt *const *fgts,
+                                 const pasur_cfr_state *const *states, int n_items,
+                                 const pasur_cfr_params *p, int64_t t_first, int64_t t_last,
+                                 pasur_plan **out, void *stream) {
+  if (!out || !fgts || !states || !p || n_items < 1) {
+    set_error("null argument or empty batch");
+    return PASUR_E_INVAL;
+  }
+  *out = nullptr;
+  if (t_first < 1 || t_last < t_first) {
+    set_error("need 1 <= t_first <= t_last");
+    return PASUR_E_RANGE;
+  }
+  if (p->variant < 0 || p->variant > 2 || p->rm_mode < 0 || p->rm_mode > 1 ||
+      p->schedule < 0 || p->schedule > 2 || p->seg_nodes < 0 ||
+      (p->block != 0 && p->block != 256 && p->block != 512 && p->block != 1024)) {
+    set_error("unknown variant, regret-matching mode, schedule, block or segment size");
+    return PASUR_E_RANGE;
+  }
+  if (p->schedule == PASUR_SCHED_LEVEL_SYNC) {
+    set_error("plans use the persistent segment schedule");
+    return PASUR_E_RANGE;
+  }
+  const int dtype = states[0]->dtype;
+  for (int i = 0; i < n_items; ++i) {
+    if (!fgts[i] || !states[i]) {
+      set_error("item %d is NULL", i);
+      return PASUR_E_INVAL;
+    }
+    PASUR_TRY(check_state(fgts[i], states[i]));
+    if (states[i]->dtype != dtype) {
+      set_error("all items of a plan need the same dtype");
+      return PASUR_E_INVAL;
+    }
+  }
+  pasur_plan *pl = new pasur_plan();
+  std::memset(pl, 0, sizeof(*pl));
+  pl->dtype = dtype;
+  pl->block = p->block ? p->block : 1024;
+  pl->variant = p->variant;
+  pl->rm_mode = p->rm_mode;
+  pl->eps = p->eps;
+  pl->t_first = t_first;
+  pl->t_last = t_last;
+  pl->n_items = n_items;
+  hipStream_t s = (hipStream_t)stream;
+  const int fg = p->schedule == PASUR_SCHED_ROOT_GLOBAL;
+  int st = dtype == PASUR_F32 ? plan_build<float>(pl, fgts, states, p, fg, s)
+                              : plan_build<double>(pl, fgts, states, p, fg, s);
+  if (st) {
+    pasur_plan_free(pl);
+    return st;
+  }
+  *out = pl;
+  return PASUR_OK;
+}
+
+extern "C" int pasur_plan_iterate(const pasur_plan *pl, int64_t t0, int n_iters, void *stream) {
+  if (!pl) {
+    set_error("plan is NULL");
+    return PASUR_E_INVAL;
+  }
+  if (n_iters < 0 || t0 < pl->t_first || t0 + n_iters - 1 > pl->t_last) {
+    set_error("iterations %lld..%lld outside the plan's %lld..%lld", (long long)t0,
+              (long long)(t0 + n_iters - 1), (long long)pl->t_first, (long long)pl->t_last);
+    return PASUR_E_RANGE;
+  }
+  if (n_iters == 0) return PASUR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  {
+    ProfScope ps(pl->n_lds_segs == pl->n_segs ? 2 : 3, -1, s, pl->work[0], pl->work[1],
+                 pl->work[2], pl->work[3], n_iters);
+    const bool f32 = pl->dtype == PASUR_F32;
+    switch (pl->block) {
+      case 256: f32 ? plan_launch<float, 256>(pl, t0, n_iters, s) : plan_launch<double, 256>(pl, t0, n_iters, s); break;
+      case 512: f32 ? plan_launch<float, 512>(pl, t0, n_iters, s) : plan_launch<double, 512>(pl, t0, n_iters, s); break;
+      default: f32 ? plan_launch<float, 1024>(pl, t0, n_iters, s) : plan_launch<double, 1024>(pl, t0, n_iters, s); break;
+    }
+  }
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+extern "C" int pasur_plan_info(const pasur_plan *pl, int64_t info[8]) {
+  if (!pl || !info) {
+    set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  info[0] = pl->n_segs;
+  info[1] = pl->n_lds_segs;
+  info[2] = pl->lds_bytes;
+  info[3] = pl->block;
+  info[4] = pl->work[0];
+  info[5] = pl->work[1];
+  info[6] = pl->work[2];
+  info[7] = pl->work[3];
+  return PASUR_OK;
+}
+
+namespace {
 
 template <class T, class L>
 int values_t(const pasur_fgt *f, const L *leaf, void *const sigma[9], int mode, double *out,
@@ -771,8 +919,18 @@ extern "C" int pasur_cfr_iterate(const pasur_fgt *f, const pasur_cfr_state *st,
   if (p->schedule == PASUR_SCHED_LEVEL_SYNC)
     return st->dtype == PASUR_F32 ? iterate_t<float>(f, st, p, t0, n_iters, s)
                                   : iterate_t<double>(f, st, p, t0, n_iters, s);
-  return st->dtype == PASUR_F32 ? iterate_roots<float>(f, st, p, t0, n_iters, s)
-                                : iterate_roots<double>(f, st, p, t0, n_iters, s);
+  if (n_iters == 0) return PASUR_OK;
+  pasur_plan *pl = nullptr;
+  PASUR_TRY(pasur_plan_create(&f, &st, 1, p, t0, t0 + n_iters - 1, &pl, stream));
+  int rc = pasur_plan_iterate(pl, t0, n_iters, stream);
+  hipError_t e = hipStreamSynchronize(s);  // the plan's buffers are freed below
+  pasur_plan_free(pl);
+  if (rc) return rc;
+  if (e != hipSuccess) {
+    set_error("iterate: %s", hipGetErrorString(e));
+    return PASUR_E_HIP;
+  }
+  return PASUR_OK;
 }
 
 extern "C" int pasur_average_strategy(const pasur_fgt *f, const pasur_cfr_state *st,

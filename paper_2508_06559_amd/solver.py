@@ -13,7 +13,7 @@ from dataclasses import dataclass
 from typing import List, Optional
 
 from . import (PASUR_F32, PASUR_F64, TV_BR_A, TV_BR_B, TV_EXPECT, V_ITERATE_MEAN, CfrState,
-               UnfoldedTree, average_strategy, build_round_tree, cfr_init, cfr_iterate,
+               Plan, UnfoldedTree, average_strategy, build_round_tree, cfr_init, cfr_iterate,
                leaf_utilities, paper_params, round_values, roots_to_device, tree_values,
                unfold_scores, _torch)
 
@@ -93,3 +93,75 @@ class SubgameSolver:
         for rr in self.rounds:
             rr.fgt.free()
         self.rounds = []
+
+
+class BatchSolver:
+    """Many deals solved together (a12): every round of every deal is built
+    and unfolded as in SubgameSolver; the backward solve then runs one
+    persistent launch per round over the trees of all deals (a plan), with
+    per-deal leaf utilities, initialisation, average strategies and round
+    values around it.  ``capture()`` records the whole backward solve into a
+    HIP graph (torch.cuda.CUDAGraph) so that ``replay()`` is one graph launch."""
+
+    def __init__(self, problems, start_round: int, iters: int, dtype: int = PASUR_F32,
+                 params=None, value_mode: int = V_ITERATE_MEAN):
+        torch = _torch()
+        self.torch = torch
+        self.iters = iters
+        self.params = params if params is not None else paper_params()
+        self.value_mode = value_mode
+        self.deals = [SubgameSolver(deck, start_round, roots, dtype=dtype) for deck, roots in problems]
+        self.n_rounds = 6 - start_round
+        for sv in self.deals:
+            for rr in sv.rounds:
+                rr.state = CfrState(rr.fgt, dtype)
+                rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
+        # one plan per round over all deals
+        self.plans = [Plan([sv.rounds[k].state for sv in self.deals], self.params, 1, iters)
+                      for k in range(self.n_rounds)]
+        self.graph = None
+
+    def edges(self) -> int:
+        return sum(sv.edges() for sv in self.deals)
+
+    def _backward(self, stream=None):
+        for k in range(self.n_rounds - 1, -1, -1):
+            for sv in self.deals:
+                rr = sv.rounds[k]
+                V = None if k == self.n_rounds - 1 else sv.rounds[k + 1].V
+                leaf_utilities(rr.fgt, V, rr.state.dtype, rr.state.u[8], stream)
+                cfr_init(rr.state, stream)
+            self.plans[k].iterate(1, self.iters, stream)
+            for sv in self.deals:
+                rr = sv.rounds[k]
+                average_strategy(rr.state, stream)
+                round_values(rr.state, self.value_mode, rr.V, stream)
+
+    def solve(self):
+        self._backward()
+
+    def capture(self):
+        torch = self.torch
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self._backward(s)
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def exploitability(self):
+        return [sv.exploitability() for sv in self.deals]
+
+    def free(self):
+        for p in self.plans:
+            p.free()
+        self.plans = []
+        self.graph = None
+        for sv in self.deals:
+            sv.free()
