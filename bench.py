@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -90,6 +92,77 @@ def cpu_baseline(deck, roots, iters):
             "seconds": el}
 
 
+def bench_batched(args):
+    """64 seeded deals (seeds 100..163), rounds 4-6 from a synthetic round-4
+    start, 1000 DCFR iterations per round; the backward solve of all deals is
+    captured in one HIP graph and replayed.  Schedules are autotuned first."""
+    import torch
+    import paper_2508_06559_amd as pa
+    from paper_2508_06559_amd import autotune
+    import synth
+
+    dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
+    T = 4 if args.state == "f32" else 8
+    iters = 1000 if args.iters == 2000 else args.iters
+    probs = [synth.subgame_roots(seed, 3) for seed in range(100, 164)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = pa.BatchSolver(probs, 3, iters, dtype=dtype)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    edges = b.edges()
+    sizes = [sum(sum(rr.fgt.n) for rr in sv.rounds) for sv in b.deals]
+    log(f"[bench] batched: {len(probs)} deals, {sum(sizes)} nodes ({min(sizes)}..{max(sizes)}), "
+        f"built in {build_s:.2f} s")
+    sched = autotune.autotune(b.round_states(), iters=10, out_json=args.schedule_json, log=log)
+    b.set_params(autotune.params_from(sched))
+    for w in range(args.warmup):
+        b.solve()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    b.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        b.replay()
+        torch.cuda.synchronize()
+        log(f"[bench] step {k + 1}/{args.steps} done")
+    el = time.perf_counter() - t0
+    value = edges * iters * args.steps / el
+    # roofline: per-launch timing of the plans over one eager solve
+    pa.profile_enable(True)
+    b.solve()
+    torch.cuda.synchronize()
+    kern, lev, ms, work = pa.profile_read()
+    pa.profile_enable(False)
+    tot_b = sum(launch_bytes(int(kern[i]), int(lev[i]), work[i], T) for i in range(len(kern)))
+    tot_t = sum(float(x) for x in ms) * 1e-3
+    dom = int(np.argmax(ms))
+    db = launch_bytes(int(kern[dom]), int(lev[dom]), work[dom], T)
+    dt = float(ms[dom]) * 1e-3
+    ex = [float(((x[0] - x[1]) / 2).max().item()) for x in b.exploitability()[:4]]
+    out = {
+        "metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: 64 seeded deals (seeds 100-163), rounds 4-6, {sum(sizes)} "
+                               f"nodes ({min(sizes)}..{max(sizes)} per deal), {iters} DCFR iterations "
+                               f"per round, backward solve of all deals replayed as one HIP graph",
+                   "state": args.state, "build_seconds": build_s,
+                   "schedule": [r["best"] for r in sched["rounds"]],
+                   "exploitability_points_first_deals": ex},
+        "roofline": {"bound": "hbm", "kernel": f"k_cfr_seg ({'float' if T == 4 else 'double'} state), "
+                                             f"largest launch",
+                     "achieved": db / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": db / dt / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": dt * 1e6, "algorithmic_bytes_per_launch": db,
+                     "all_sweeps_GBs": tot_b / tot_t / 1e9},
+    }
+    print(json.dumps(out), flush=True)
+    b.free()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +174,9 @@ def main():
     ap.add_argument("--sched", choices=["root", "level", "root-global"], default="root")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["two-round", "batched"], default="two-round",
+                    help="two-round: the headline configuration; batched: 64 deals, rounds 4-6")
+    ap.add_argument("--schedule-json", default=None, help="where the batched autotuner writes its schedule")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this solver is a single-GPU build "
@@ -112,6 +188,8 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        return bench_batched(args)
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
     params = pa.paper_params({"root": pa.SCHED_ROOT, "level": pa.SCHED_LEVEL_SYNC,

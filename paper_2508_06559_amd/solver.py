@@ -108,7 +108,6 @@ class BatchSolver:
         torch = _torch()
         self.torch = torch
         self.iters = iters
-        self.params = params if params is not None else paper_params()
         self.value_mode = value_mode
         self.deals = [SubgameSolver(deck, start_round, roots, dtype=dtype) for deck, roots in problems]
         self.n_rounds = 6 - start_round
@@ -116,9 +115,24 @@ class BatchSolver:
             for rr in sv.rounds:
                 rr.state = CfrState(rr.fgt, dtype)
                 rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
-        # one plan per round over all deals
-        self.plans = [Plan([sv.rounds[k].state for sv in self.deals], self.params, 1, iters)
-                      for k in range(self.n_rounds)]
+        self.plans = []
+        self.set_params(params)
+
+    def round_states(self):
+        """States covered by each round's plan (round slot k = start_round + k)."""
+        return [[sv.rounds[k].state for sv in self.deals] for k in range(self.n_rounds)]
+
+    def set_params(self, params=None):
+        """One CfrParams for every round, or a list with one per round slot;
+        (re)creates the per-round plans."""
+        for p in self.plans:
+            p.free()
+        if params is None:
+            params = paper_params()
+        plist = list(params) if isinstance(params, (list, tuple)) else [params] * self.n_rounds
+        self.params = plist
+        self.plans = [Plan(states, plist[k], 1, self.iters)
+                      for k, states in enumerate(self.round_states())]
         self.graph = None
 
     def edges(self) -> int:
