@@ -163,6 +163,88 @@ def bench_batched(args):
     b.free()
 
 
+def bench_warm(args):
+    """Learned warm start: train the MLP on DCFR solutions of --train-deals
+    seeded two-round deals (seeds 10000..), then on --test-deals held-out
+    deals (seeds 20000..) measure the seconds (and iterations) DCFR needs to
+    reach exploitability <= 1e-3 at the round-5 root, plain vs warm-started
+    (inference included, exploitability checks excluded, plain DCFR as the
+    fallback).  Also reports the MFMA throughput of the network's GEMMs."""
+    import torch
+    import paper_2508_06559_amd as pa
+    from paper_2508_06559_amd import learn
+    import synth
+
+    t0 = time.perf_counter()
+    train = [synth.two_round_root(s) for s in range(10000, 10000 + args.train_deals)]
+    units = learn.training_units(train, 1000)
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    rows = sum(u.n_rows for u in units)
+    log(f"[bench] training data: {len(units)} units, {rows} rows, {data_s:.1f} s")
+    model = learn.WarmStartMLP(0)
+    # MFMA throughput: one epoch of training steps timed with events
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    hist = learn.train(model, units, 1, seed=99, log=log)
+    b.record()
+    b.synchronize()
+    train_ms = a.elapsed_time(b)
+    per_row = 2 * (160 * 256 + 256 * 256 + 256 * 2)
+    train_tflops = 3 * per_row * rows / (train_ms * 1e-3) / 1e12
+    hist += learn.train(model, units, args.epochs - 1, seed=0, log=log)
+    big = torch.zeros((1 << 20, 160), dtype=torch.int16, device="cuda")
+    model.forward(big, big.shape[0])
+    a.record()
+    for _ in range(5):
+        model.forward(big, big.shape[0])
+    b.record()
+    b.synchronize()
+    inf_tflops = 5 * per_row * big.shape[0] / (a.elapsed_time(b) * 1e-3) / 1e12
+    del big
+    grid = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
+    test = [synth.two_round_root(s) for s in range(20000, 20000 + args.test_deals)]
+    res = {"plain": [], "warm": []}
+    ex0 = {"uniform": [], "network": []}
+    for k, (deck, roots) in enumerate(test):
+        res["plain"].append(learn.seconds_to_target(deck, 4, roots, 1e-3, grid, None))
+        res["warm"].append(learn.seconds_to_target(deck, 4, roots, 1e-3, grid, model))
+        if k < 32:
+            ex0["uniform"].append(learn.initial_profile_exploitability(deck, roots, None))
+            ex0["network"].append(learn.initial_profile_exploitability(deck, roots, model))
+        if k % 32 == 31:
+            log(f"[bench] evaluated {k + 1}/{len(test)} held-out deals")
+
+    def summ(rs):
+        sec = np.array([r["seconds"] for r in rs if r["seconds"] is not None])
+        it = np.array([r["iters"] for r in rs if r["iters"] is not None])
+        return {"median_seconds": float(np.median(sec)), "p25_seconds": float(np.percentile(sec, 25)),
+                "p75_seconds": float(np.percentile(sec, 75)), "median_iters": float(np.median(it)),
+                "mean_iters": float(np.mean(it)), "reached": int(len(sec)),
+                "fallbacks": int(sum(r["fallback"] for r in rs))}
+
+    sp, sw = summ(res["plain"]), summ(res["warm"])
+    out = {
+        "metric": METRIC, "value": sw["median_seconds"], "unit": "s to exploitability 1e-3 (warm start)",
+        "n_gpus": 1, "steps": len(test), "warmup": 0, "ms_per_step": sw["median_seconds"] * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"learned warm start: MLP 160-256-256-2 trained on DCFR solutions of "
+                               f"{len(train)} seeded two-round deals ({rows} rows, {args.epochs} epochs); "
+                               f"seconds to exploitability 1e-3 on {len(test)} held-out deals, "
+                               f"iteration grid {list(grid)}",
+                   "plain": sp, "warm": sw,
+                   "speedup_median_seconds": sp["median_seconds"] / sw["median_seconds"],
+                   "initial_profile_exploitability_median": {k: float(np.median(v)) for k, v in ex0.items()},
+                   "final_train_loss": hist[-1], "data_seconds": data_s},
+        "roofline": {"bound": "mfma", "kernel": "k_gemm (BF16 MFMA 16x16x32, FP32 accumulate)",
+                     "achieved": inf_tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": inf_tflops / 2500.0, "traffic": None,
+                     "training_TFLOPs": train_tflops},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,8 +256,12 @@ def main():
     ap.add_argument("--sched", choices=["root", "level", "root-global"], default="root")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["two-round", "batched"], default="two-round",
-                    help="two-round: the headline configuration; batched: 64 deals, rounds 4-6")
+    ap.add_argument("--workload", choices=["two-round", "batched", "warm-start"], default="two-round",
+                    help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
+                         "warm-start: learned warm start vs plain DCFR")
+    ap.add_argument("--train-deals", type=int, default=512)
+    ap.add_argument("--test-deals", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--schedule-json", default=None, help="where the batched autotuner writes its schedule")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -190,6 +276,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "warm-start":
+        return bench_warm(args)
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
     params = pa.paper_params({"root": pa.SCHED_ROOT, "level": pa.SCHED_LEVEL_SYNC,

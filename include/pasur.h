@@ -241,6 +241,73 @@ int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
                       void *const sigma[9], int mode, double *d_out,
                       void *stream);
 
+/* ---- a13: learned warm start ------------------------------------------------
+ * Not in the paper (its learned model is an XGBoost regressor on infoset
+ * rows).  A 160-256-256-2 MLP: input = the child node's card state (Alex's
+ * hand, Bob's hand, pool as 3 x 52 bits) and inherited score (ca/7, cb/7,
+ * d/16, +1/-1/0 bonus owner); two ReLU hidden layers of 256; outputs a
+ * policy logit (softmax over siblings = predicted average strategy) and a
+ * node value.  Weights are row-major [in][out]; BF16 arrays are raw 16-bit
+ * words.  All GEMMs run on MFMA (BF16 x BF16 -> FP32). */
+typedef struct {
+  const uint16_t *W1; const float *b1; /* [160][256], [256] */
+  const uint16_t *W2; const float *b2; /* [256][256], [256] */
+  const uint16_t *W3; const float *b3; /* [256][2], [2] */
+} pasur_mlp_weights;
+typedef struct {
+  float *dW1, *db1, *dW2, *db2, *dW3, *db3; /* FP32, same shapes */
+} pasur_mlp_grads;
+
+/* C[M,N] = op(A) op(B) (+ bias per column, ReLU) with op(A)(m,k) =
+ * A[m*sar + k*sac], op(B)(k,n) = B[k*sbr + n*sbc]; BF16 operands, FP32
+ * accumulation; writes Cf (FP32) and/or Cb (BF16) with row stride ldc. */
+int pasur_gemm_bf16(int M, int N, int K, const uint16_t *A, int64_t sar, int64_t sac,
+                    const uint16_t *B, int64_t sbr, int64_t sbc, float *Cf, uint16_t *Cb,
+                    int64_t ldc, const float *bias, int relu, void *stream);
+/* Forward for M rows of X [M][160] (BF16): H1, H2 [M][256] (BF16, after
+ * ReLU), Y [M][2] (FP32: logit, value). */
+int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
+                      uint16_t *H1, uint16_t *H2, float *Y, void *stream);
+/* Gradients of the loss with respect to the weights given dY [M][2] (FP32);
+ * dY is rounded to BF16 for the GEMMs.  Uses stream-ordered scratch. */
+int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X, const uint16_t *H1,
+                       const uint16_t *H2, const float *dY, int64_t M, pasur_mlp_grads *g,
+                       void *stream);
+/* Rows seg[p]..seg[p+1] are the children of sampled parent p.  Policy loss:
+ * cross-entropy of softmax(logits over siblings) against target_sigma,
+ * averaged over parents; value loss: value_weight/2 (value - target)^2
+ * averaged over rows.  Writes dY [n_rows][2] and loss [n_parents][2]. */
+int pasur_mlp_loss(const float *Y, const float *target_sigma, const float *target_value,
+                   const int32_t *seg, int64_t n_parents, int64_t n_rows, float value_weight,
+                   float *dY, float *loss, void *stream);
+/* Adam on an FP32 master array; refreshes its BF16 copy when w_bf16 != NULL. */
+int pasur_adam_step(float *w, const float *g, float *m, float *v, uint16_t *w_bf16, int64_t n,
+                    float lr, float beta1, float beta2, float eps, int64_t step, void *stream);
+/* Feature rows (BF16 [n][160]) of FGT nodes of `level`: the nodes d_edges[i]
+ * (device) or, with d_edges NULL, all n = n[level] nodes in order.  `gt` must
+ * be the game tree `fgt` was unfolded from. */
+int pasur_edge_features(const pasur_gt *gt, const pasur_fgt *fgt, int level,
+                        const int32_t *d_edges, int64_t n, uint16_t *d_X, void *stream);
+/* Training sample: decision parents (two or more children) on level-1 kept
+ * when a seeded hash falls below keep_prob; d_seg (n[level-1]+1 capacity)
+ * receives the offsets of their children in d_edges (n[level] capacity),
+ * which receives the child indices.  Synchronises `stream`. */
+int pasur_sample_parents(const pasur_fgt *fgt, int level, uint64_t seed, double keep_prob,
+                         int32_t *d_seg, int32_t *d_edges, int64_t *n_parents,
+                         int64_t *n_edges, void *stream);
+/* Warm start of one level from predicted logits Y [n[level]][2]: sigma =
+ * softmax over each node's children, R = kappa_r sigma, Sbar = kappa_s sigma.
+ * Call after pasur_cfr_init; iterate from a later t0 so that the DCFR
+ * discounts treat the warm start as earlier iterations. */
+int pasur_cfr_warm_init(const pasur_fgt *fgt, const pasur_cfr_state *st, int level,
+                        const float *Y, float kappa_r, float kappa_s, void *stream);
+
+/* Training-data helpers: dst[i] = (float)src[idx[i]] (idx NULL: src[i]) for
+ * a `dtype` array; dst[i] = src[i] + add for int32 offsets. */
+int pasur_gather_f32(const void *src, int dtype, const int32_t *idx, int64_t n, float *dst,
+                     void *stream);
+int pasur_shift_i32(const int32_t *src, int64_t n, int32_t add, int32_t *dst, void *stream);
+
 /* ---- tracing ----------------------------------------------------------------
  * Per-launch timing of the sweep kernels with HIP events recorded on the
  * launch stream around every launch made by pasur_cfr_iterate.  Enabling

@@ -89,6 +89,19 @@ def lib():
         L.pasur_plan_info.argtypes = [vp, vp]
         L.pasur_plan_free.argtypes = [vp]
         L.pasur_plan_free.restype = None
+        L.pasur_gemm_bf16.argtypes = [i32, i32, i32, vp, i64, i64, vp, i64, i64, vp, vp, i64, vp,
+                                      i32, vp]
+        L.pasur_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.pasur_mlp_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.pasur_mlp_loss.argtypes = [vp, vp, vp, vp, i64, i64, C.c_float, vp, vp, vp]
+        L.pasur_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
+                                      C.c_float, i64, vp]
+        L.pasur_edge_features.argtypes = [vp, vp, i32, vp, i64, vp, vp]
+        L.pasur_sample_parents.argtypes = [vp, i32, C.c_uint64, C.c_double, vp, vp,
+                                           C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
+        L.pasur_cfr_warm_init.argtypes = [vp, vp, i32, vp, C.c_float, C.c_float, vp]
+        L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
+        L.pasur_shift_i32.argtypes = [vp, i64, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
         L.pasur_profile_read.argtypes = [i64, vp, vp, vp, vp, C.POINTER(C.c_int64)]
         _lib = L
@@ -351,6 +364,76 @@ class Plan:
             self.free()
         except Exception:
             pass
+
+
+class MlpWeights(C.Structure):
+    _fields_ = [("W1", C.c_void_p), ("b1", C.c_void_p), ("W2", C.c_void_p), ("b2", C.c_void_p),
+                ("W3", C.c_void_p), ("b3", C.c_void_p)]
+
+
+class MlpGrads(C.Structure):
+    _fields_ = [("dW1", C.c_void_p), ("db1", C.c_void_p), ("dW2", C.c_void_p),
+                ("db2", C.c_void_p), ("dW3", C.c_void_p), ("db3", C.c_void_p)]
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def gemm_bf16(M, N, K, A, sar, sac, B, sbr, sbc, Cf=None, Cb=None, ldc=None, bias=None,
+              relu=False, stream=None):
+    """pasur_gemm_bf16 on torch tensors (A, B, Cb as int16 bit patterns)."""
+    _check(lib().pasur_gemm_bf16(M, N, K, _p(A), sar, sac, _p(B), sbr, sbc, _p(Cf), _p(Cb),
+                                 N if ldc is None else ldc, _p(bias), 1 if relu else 0,
+                                 _stream(stream)), "pasur_gemm_bf16")
+
+
+def mlp_forward(w: MlpWeights, X, M, H1, H2, Y, stream=None):
+    _check(lib().pasur_mlp_forward(C.byref(w), _p(X), M, _p(H1), _p(H2), _p(Y), _stream(stream)),
+           "pasur_mlp_forward")
+
+
+def mlp_backward(w: MlpWeights, X, H1, H2, dY, M, g: MlpGrads, stream=None):
+    _check(lib().pasur_mlp_backward(C.byref(w), _p(X), _p(H1), _p(H2), _p(dY), M, C.byref(g),
+                                    _stream(stream)), "pasur_mlp_backward")
+
+
+def mlp_loss(Y, tsig, tval, seg, n_par, n_rows, value_weight, dY, loss, stream=None):
+    _check(lib().pasur_mlp_loss(_p(Y), _p(tsig), _p(tval), _p(seg), n_par, n_rows,
+                                value_weight, _p(dY), _p(loss), _stream(stream)), "pasur_mlp_loss")
+
+
+def adam_step(w, g, m, v, wb, lr, b1, b2, eps, step, stream=None):
+    _check(lib().pasur_adam_step(_p(w), _p(g), _p(m), _p(v), _p(wb), w.numel(), lr, b1, b2, eps,
+                                 step, _stream(stream)), "pasur_adam_step")
+
+
+def edge_features(gt: GameTree, fgt: UnfoldedTree, level: int, edges, n: int, X, stream=None):
+    _check(lib().pasur_edge_features(gt.h, fgt.h, level, _p(edges), n, _p(X), _stream(stream)),
+           "pasur_edge_features")
+
+
+def sample_parents(fgt: UnfoldedTree, level: int, seed: int, keep_prob: float, seg, edges,
+                   stream=None):
+    npar, ne = C.c_int64(), C.c_int64()
+    _check(lib().pasur_sample_parents(fgt.h, level, seed, keep_prob, _p(seg), _p(edges),
+                                      C.byref(npar), C.byref(ne), _stream(stream)),
+           "pasur_sample_parents")
+    return npar.value, ne.value
+
+
+def cfr_warm_init(st: CfrState, level: int, Y, kappa_r: float, kappa_s: float, stream=None):
+    _check(lib().pasur_cfr_warm_init(st.fgt.h, C.byref(st.c), level, _p(Y), kappa_r, kappa_s,
+                                     _stream(stream)), "pasur_cfr_warm_init")
+
+
+def gather_f32(src, dtype: int, idx, n: int, dst, stream=None):
+    _check(lib().pasur_gather_f32(_p(src), dtype, _p(idx), n, _p(dst), _stream(stream)),
+           "pasur_gather_f32")
+
+
+def shift_i32(src, n: int, add: int, dst, stream=None):
+    _check(lib().pasur_shift_i32(_p(src), n, add, _p(dst), _stream(stream)), "pasur_shift_i32")
 
 
 def profile_enable(on: bool):

@@ -1,0 +1,572 @@
+// pasur_mlp.hip -- the learned warm start: a 160-256-256-2 MLP over card
+// bitmasks and the inherited score, trained on the average strategies and
+// node values that the DCFR kernels produce, and used to initialise DCFR on
+// new deals.  GEMMs run on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16:
+// BF16 operands, FP32 accumulation).
+#include "pasur_internal.hpp"
+
+#include <cmath>
+#include <cstring>
+
+using namespace pasur;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+namespace {
+
+constexpr int kIn = 160, kHid = 256, kOut = 2;
+constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // 80-byte LDS rows keep 16-byte alignment
+
+struct GemmArgs {
+  int M, N, K;
+  const __bf16 *A;
+  int64_t sar, sac;  // op(A)(m, k) = A[m * sar + k * sac]
+  const __bf16 *B;
+  int64_t sbr, sbc;  // op(B)(k, n) = B[k * sbr + n * sbc]
+  float *Cf;         // FP32 output (row stride ldc), split-K partial z at Cf + z * split_stride
+  __bf16 *Cb;        // BF16 output (row stride ldc), unused with split-K
+  int64_t ldc, split_stride;
+  const float *bias;  // per output column, may be null
+  int relu;
+  int kchunk;  // K range of one split (blockIdx.z)
+};
+
+// C = op(A) op(B) (+ bias, ReLU).  Workgroup tile 64x64, K step 32; four
+// waves each own a 32x32 quadrant as 2x2 MFMA 16x16x32 tiles.  MFMA operand
+// layout: lane l holds row (l % 16) of the A tile and column (l % 16) of the
+// B tile, K elements 8*(l/16) .. 8*(l/16)+7; the accumulator holds rows
+// 4*(l/16) .. +3 of column (l % 16).
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  __shared__ __align__(16) __bf16 As[BM][LDK];
+  __shared__ __align__(16) __bf16 Bs[BN][LDK];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const __bf16 zero = (__bf16)0.f;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    // global -> LDS, the contiguous global direction fastest across threads
+    for (int e = tid; e < BM * BK; e += 256) {
+      int r, c;
+      if (g.sac == 1) { r = e / BK; c = e % BK; } else { c = e / BM; r = e % BM; }
+      const int m = m0 + r, k = k0 + c;
+      As[r][c] = (m < g.M && k < kend) ? g.A[m * g.sar + k * g.sac] : zero;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      int r, c;
+      if (g.sbr == 1) { r = e / BK; c = e % BK; } else { c = e / BN; r = e % BN; }
+      const int n = n0 + r, k = k0 + c;
+      Bs[r][c] = (n < g.N && k < kend) ? g.B[k * g.sbr + n * g.sbc] : zero;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[wn + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          float v = acc[i][j][r];
+          if (g.bias) v += g.bias[n];
+          if (g.relu) v = fmaxf(v, 0.f);
+          if (g.Cf) g.Cf[(int64_t)blockIdx.z * g.split_stride + (int64_t)m * g.ldc + n] = v;
+          if (g.Cb) g.Cb[(int64_t)m * g.ldc + n] = (__bf16)v;
+        }
+      }
+}
+
+int gemm(GemmArgs g, int splits, hipStream_t s) {
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)splits);
+  k_gemm<<<grid, 256, 0, s>>>(g);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+// out[i] = sum over splits of part[z * n + i], in split order; optional BF16
+// copy and ReLU-mask multiply (mask[i] > 0).
+__global__ void k_split_sum(const float *__restrict__ part, int splits, int64_t n,
+                            float *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * n + i];
+  out[i] = s;
+}
+
+// Column sums of a row-major [M, N] FP32 matrix (bias gradients), one thread
+// per column, rows in order.
+__global__ void k_col_sum(const float *__restrict__ X, int64_t M, int N, float *__restrict__ out) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int64_t m = 0; m < M; ++m) s += X[m * N + n];
+  out[n] = s;
+}
+
+// dH = G * (H > 0) for ReLU layers, FP32 in, BF16 out (also FP32 copy).
+__global__ void k_relu_back(const float *__restrict__ G, const __bf16 *__restrict__ H, int64_t n,
+                            float *__restrict__ outf, __bf16 *__restrict__ outb) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = (float)H[i] > 0.f ? G[i] : 0.f;
+  outf[i] = v;
+  outb[i] = (__bf16)v;
+}
+
+__global__ void k_f32_to_bf16(const float *__restrict__ x, int64_t n, __bf16 *__restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (__bf16)x[i];
+}
+
+// Features of FGT edges (the child node's card state and score): Alex's
+// hand, Bob's hand and the pool as three 52-bit masks, then ca/7, cb/7,
+// d/16 and +1/-1/0 for the 7-club bonus owner.  One row of 160 BF16 values
+// per edge.
+struct HandCards {
+  uint8_t card[8];
+};
+
+__global__ void k_features(int64_t n, const int32_t *__restrict__ edges, const int32_t *__restrict__ f_gt,
+                           const int32_t *__restrict__ f_sid, const uint64_t *__restrict__ pool,
+                           const uint8_t *__restrict__ hands, const int8_t *__restrict__ tab,
+                           HandCards hc, __bf16 *__restrict__ X) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t q = edges ? edges[i] : (int32_t)i;
+  const int32_t g = f_gt[q];
+  const uint8_t h = hands[g];
+  uint64_t ha = 0, hb = 0;
+  for (int b = 0; b < 4; ++b) {
+    if ((h >> b) & 1) ha |= 1ull << hc.card[b];
+    if ((h >> (4 + b)) & 1) hb |= 1ull << hc.card[4 + b];
+  }
+  const uint64_t p = pool[g];
+  __bf16 *row = X + i * kIn;
+  const __bf16 one = (__bf16)1.f, zero = (__bf16)0.f;
+  for (int c = 0; c < 52; ++c) {
+    row[c] = ((ha >> c) & 1) ? one : zero;
+    row[52 + c] = ((hb >> c) & 1) ? one : zero;
+    row[104 + c] = ((p >> c) & 1) ? one : zero;
+  }
+  const int8_t *s = tab + 4 * f_sid[q];
+  row[156] = (__bf16)((float)s[0] / 7.f);
+  row[157] = (__bf16)((float)s[1] / 7.f);
+  row[158] = (__bf16)((float)s[2] / 16.f);
+  row[159] = (__bf16)(s[3] == 1 ? 1.f : (s[3] == 2 ? -1.f : 0.f));
+}
+
+// Policy / value loss gradient.  seg[p]..seg[p+1] are the rows (edges) of
+// parent p; Y[r] = (logit, value).  Policy: cross-entropy between the
+// softmax of the logits over the siblings and the target strategy, averaged
+// over parents; value: vw/2 (value - target)^2 averaged over rows.
+__global__ void k_loss(int64_t n_par, const int32_t *__restrict__ seg, const float *__restrict__ Y,
+                       const float *__restrict__ tsig, const float *__restrict__ tval, float vw,
+                       int64_t n_rows, float *__restrict__ dY, float *__restrict__ loss) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_par) return;
+  const int32_t b = seg[p], e = seg[p + 1];
+  float mx = -INFINITY;
+  for (int32_t r = b; r < e; ++r) mx = fmaxf(mx, Y[2 * r]);
+  float z = 0.f;
+  for (int32_t r = b; r < e; ++r) z += expf(Y[2 * r] - mx);
+  float lp = 0.f, lv = 0.f;
+  const float inv_p = 1.f / (float)n_par, inv_r = 1.f / (float)n_rows;
+  for (int32_t r = b; r < e; ++r) {
+    const float pr = expf(Y[2 * r] - mx) / z;
+    dY[2 * r] = (pr - tsig[r]) * inv_p;
+    if (tsig[r] > 0.f) lp -= tsig[r] * logf(fmaxf(pr, 1e-30f));
+    const float dv = Y[2 * r + 1] - tval[r];
+    dY[2 * r + 1] = vw * dv * inv_r;
+    lv += 0.5f * vw * dv * dv;
+  }
+  loss[2 * p] = lp * inv_p;
+  loss[2 * p + 1] = lv * inv_r;
+}
+
+__global__ void k_adam(int64_t n, float *__restrict__ w, const float *__restrict__ g,
+                       float *__restrict__ m, float *__restrict__ v, __bf16 *__restrict__ wb,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = (__bf16)wi;
+}
+
+// Warm start of one level: sigma = softmax of the predicted logits over
+// each parent's children; R = kappa_r * sigma; Sbar = kappa_s * sigma.
+template <class T>
+__global__ void k_warm_init(int64_t np, const int32_t *__restrict__ cb, const float *__restrict__ Y,
+                            float kappa_r, float kappa_s, T *__restrict__ sigma, T *__restrict__ R,
+                            T *__restrict__ Sbar) {
+  int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= np) return;
+  const int32_t b = cb[h], e = cb[h + 1];
+  double mx = -INFINITY;
+  for (int32_t q = b; q < e; ++q) mx = fmax(mx, (double)Y[2 * q]);
+  double z = 0.0;
+  for (int32_t q = b; q < e; ++q) z += exp((double)Y[2 * q] - mx);
+  for (int32_t q = b; q < e; ++q) {
+    const double s = exp((double)Y[2 * q] - mx) / z;
+    sigma[q] = (T)s;
+    R[q] = (T)(kappa_r * s);
+    Sbar[q] = (T)(kappa_s * s);
+  }
+}
+
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+template <class T>
+__global__ void k_gather(const T *__restrict__ src, const int32_t *__restrict__ idx, int64_t n,
+                         float *__restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[idx ? idx[i] : i];
+}
+
+__global__ void k_shift(const int32_t *__restrict__ src, int64_t n, int32_t add,
+                        int32_t *__restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i] + add;
+}
+
+// SplitMix64 finaliser as a hash of (seed, level, parent).
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_sel_flags(int64_t np, const int32_t *__restrict__ cb, uint64_t seed, int level,
+                            uint64_t thr, int32_t *__restrict__ flags) {
+  int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= np) return;
+  const bool decision = cb[h + 1] - cb[h] >= 2;
+  const uint64_t key = mix64(seed ^ ((uint64_t)level << 56) ^ (uint64_t)h);
+  flags[h] = (decision && key <= thr) ? 1 : 0;
+}
+
+__global__ void k_sel_compact(int64_t np, const int32_t *__restrict__ flags,
+                              const int32_t *__restrict__ pos, const int32_t *__restrict__ cb,
+                              int32_t *__restrict__ par, int32_t *__restrict__ fan) {
+  int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= np || !flags[h]) return;
+  par[pos[h]] = (int32_t)h;
+  fan[pos[h]] = cb[h + 1] - cb[h];
+}
+
+__global__ void k_sel_expand(int64_t n_sel, const int32_t *__restrict__ par,
+                             const int32_t *__restrict__ seg, const int32_t *__restrict__ cb,
+                             int32_t *__restrict__ edges) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_sel) return;
+  const int32_t h = par[p];
+  for (int32_t i = 0; i < seg[p + 1] - seg[p]; ++i) edges[seg[p] + i] = cb[h] + i;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// C ABI
+// --------------------------------------------------------------------------
+
+extern "C" int pasur_gemm_bf16(int M, int N, int K, const uint16_t *A, int64_t sar, int64_t sac,
+                               const uint16_t *B, int64_t sbr, int64_t sbc, float *Cf,
+                               uint16_t *Cb, int64_t ldc, const float *bias, int relu,
+                               void *stream) {
+  if (M < 0 || N < 0 || K < 1 || !A || !B || (!Cf && !Cb)) {
+    set_error("bad GEMM arguments");
+    return PASUR_E_INVAL;
+  }
+  if (M == 0 || N == 0) return PASUR_OK;
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.M = M; g.N = N; g.K = K;
+  g.A = (const __bf16 *)A; g.sar = sar; g.sac = sac;
+  g.B = (const __bf16 *)B; g.sbr = sbr; g.sbc = sbc;
+  g.Cf = Cf; g.Cb = (__bf16 *)Cb; g.ldc = ldc; g.split_stride = 0;
+  g.bias = bias; g.relu = relu; g.kchunk = K;
+  return gemm(g, 1, (hipStream_t)stream);
+}
+
+extern "C" int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
+                                 uint16_t *H1, uint16_t *H2, float *Y, void *stream) {
+  if (!w || !X || !H1 || !H2 || !Y || M < 0 || M > INT32_MAX) {
+    set_error("bad MLP forward arguments");
+    return PASUR_E_INVAL;
+  }
+  if (M == 0) return PASUR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int m = (int)M;
+  PASUR_TRY(pasur_gemm_bf16(m, kHid, kIn, X, kIn, 1, w->W1, kHid, 1, nullptr, H1, kHid, w->b1, 1, s));
+  PASUR_TRY(pasur_gemm_bf16(m, kHid, kHid, H1, kHid, 1, w->W2, kHid, 1, nullptr, H2, kHid, w->b2, 1, s));
+  PASUR_TRY(pasur_gemm_bf16(m, kOut, kHid, H2, kHid, 1, w->W3, kOut, 1, Y, nullptr, kOut, w->b3, 0, s));
+  return PASUR_OK;
+}
+
+extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
+                                  const uint16_t *H1, const uint16_t *H2, const float *dY,
+                                  int64_t M, pasur_mlp_grads *gr, void *stream) {
+  if (!w || !X || !H1 || !H2 || !dY || !gr || M < 1 || M > INT32_MAX) {
+    set_error("bad MLP backward arguments");
+    return PASUR_E_INVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int m = (int)M;
+  // workspace: dY in BF16, dH (FP32 and BF16) for both hidden layers, split-K partials
+  const int splits = m >= 8192 ? 32 : (m >= 1024 ? 8 : 1);
+  const int kchunk = ((m + splits - 1) / splits + BK - 1) / BK * BK;
+  __bf16 *dYb = nullptr, *G2b = nullptr, *G1b = nullptr;
+  float *G2f = nullptr, *G1f = nullptr, *part = nullptr;
+  const size_t part_n = (size_t)splits * kHid * kHid;
+  hipError_t e = hipMallocAsync((void **)&dYb, sizeof(__bf16) * m * kOut, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&G2b, sizeof(__bf16) * (size_t)m * kHid, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&G1b, sizeof(__bf16) * (size_t)m * kHid, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&G2f, sizeof(float) * (size_t)m * kHid, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&G1f, sizeof(float) * (size_t)m * kHid, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&part, sizeof(float) * part_n, s);
+  int st = PASUR_OK;
+  if (e != hipSuccess) {
+    set_error("MLP backward workspace: %s", hipGetErrorString(e));
+    st = PASUR_E_NOMEM;
+  }
+  auto dW = [&](const __bf16 *Act, int kin, const __bf16 *G, int nout, float *out) -> int {
+    // out[kin, nout] = Act^T G, reduced over the M rows in `splits` chunks
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.M = kin; g.N = nout; g.K = m;
+    g.A = Act; g.sar = 1; g.sac = kin;
+    g.B = G; g.sbr = nout; g.sbc = 1;
+    g.Cf = part; g.ldc = nout; g.split_stride = (int64_t)kin * nout;
+    g.kchunk = kchunk;
+    int r = gemm(g, splits, s);
+    if (r) return r;
+    k_split_sum<<<blocks((int64_t)kin * nout), 256, 0, s>>>(part, splits, (int64_t)kin * nout, out);
+    return PASUR_OK;
+  };
+  if (!st) {
+    k_f32_to_bf16<<<blocks((int64_t)m * kOut), 256, 0, s>>>(dY, (int64_t)m * kOut, dYb);
+    // layer 3: dW3 = H2^T dY, db3 = colsum dY, dH2 = dY W3^T masked
+    st = dW((const __bf16 *)H2, kHid, dYb, kOut, gr->dW3);
+  }
+  if (!st) {
+    k_col_sum<<<1, 64, 0, s>>>(dY, m, kOut, gr->db3);
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.M = m; g.N = kHid; g.K = kOut;
+    g.A = dYb; g.sar = kOut; g.sac = 1;
+    g.B = (const __bf16 *)w->W3; g.sbr = 1; g.sbc = kOut;  // W3^T(k, n) = W3[n, k]
+    g.Cf = G2f; g.ldc = kHid; g.kchunk = kOut;
+    st = gemm(g, 1, s);
+  }
+  if (!st) {
+    k_relu_back<<<blocks((int64_t)m * kHid), 256, 0, s>>>(G2f, (const __bf16 *)H2, (int64_t)m * kHid,
+                                                          G2f, G2b);
+    st = dW((const __bf16 *)H1, kHid, G2b, kHid, gr->dW2);
+  }
+  if (!st) {
+    k_col_sum<<<blocks(kHid, 64), 64, 0, s>>>(G2f, m, kHid, gr->db2);
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.M = m; g.N = kHid; g.K = kHid;
+    g.A = G2b; g.sar = kHid; g.sac = 1;
+    g.B = (const __bf16 *)w->W2; g.sbr = 1; g.sbc = kHid;  // W2^T
+    g.Cf = G1f; g.ldc = kHid; g.kchunk = kHid;
+    st = gemm(g, 1, s);
+  }
+  if (!st) {
+    k_relu_back<<<blocks((int64_t)m * kHid), 256, 0, s>>>(G1f, (const __bf16 *)H1, (int64_t)m * kHid,
+                                                          G1f, G1b);
+    st = dW((const __bf16 *)X, kIn, G1b, kHid, gr->dW1);
+  }
+  if (!st) {
+    k_col_sum<<<blocks(kHid, 64), 64, 0, s>>>(G1f, m, kHid, gr->db1);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error("MLP backward: %s", hipGetErrorString(e));
+      st = PASUR_E_HIP;
+    }
+  }
+  (void)hipFreeAsync(dYb, s);
+  (void)hipFreeAsync(G2b, s);
+  (void)hipFreeAsync(G1b, s);
+  (void)hipFreeAsync(G2f, s);
+  (void)hipFreeAsync(G1f, s);
+  (void)hipFreeAsync(part, s);
+  return st;
+}
+
+extern "C" int pasur_mlp_loss(const float *Y, const float *target_sigma, const float *target_value,
+                              const int32_t *seg, int64_t n_parents, int64_t n_rows,
+                              float value_weight, float *dY, float *loss, void *stream) {
+  if (!Y || !target_sigma || !target_value || !seg || !dY || !loss || n_parents < 1 || n_rows < 1) {
+    set_error("bad loss arguments");
+    return PASUR_E_INVAL;
+  }
+  k_loss<<<blocks(n_parents), 256, 0, (hipStream_t)stream>>>(n_parents, seg, Y, target_sigma,
+                                                             target_value, value_weight, n_rows,
+                                                             dY, loss);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+extern "C" int pasur_adam_step(float *w, const float *g, float *m, float *v, uint16_t *w_bf16,
+                               int64_t n, float lr, float beta1, float beta2, float eps,
+                               int64_t step, void *stream) {
+  if (!w || !g || !m || !v || n < 0 || step < 1) {
+    set_error("bad Adam arguments");
+    return PASUR_E_INVAL;
+  }
+  const float c1 = 1.f - std::pow(beta1, (float)step);
+  const float c2 = 1.f - std::pow(beta2, (float)step);
+  k_adam<<<blocks(n), 256, 0, (hipStream_t)stream>>>(n, w, g, m, v, (__bf16 *)w_bf16, lr, beta1,
+                                                     beta2, eps, c1, c2);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+extern "C" int pasur_edge_features(const pasur_gt *gt, const pasur_fgt *fgt, int level,
+                                   const int32_t *d_edges, int64_t n, uint16_t *d_X,
+                                   void *stream) {
+  if (!gt || !fgt || !d_X || n < 0) {
+    set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  if (level < 0 || level > 8) {
+    set_error("level %d outside 0..8", level);
+    return PASUR_E_RANGE;
+  }
+  if (!d_edges && n != fgt->n[level]) {
+    set_error("without an edge list n must be the level size");
+    return PASUR_E_INVAL;
+  }
+  if (gt->n[0] == 0 || fgt->round != gt->round) {
+    set_error("the game tree does not belong to this unfolded tree");
+    return PASUR_E_INVAL;
+  }
+  HandCards hc;
+  for (int b = 0; b < 8; ++b) hc.card[b] = gt->deck[4 + 8 * gt->round + b];
+  k_features<<<blocks(n), 256, 0, (hipStream_t)stream>>>(
+      n, d_edges, fgt->gt[level], fgt->sid[level], gt->pool[level], gt->hands[level],
+      fgt->score_tab, hc, (__bf16 *)d_X);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+extern "C" int pasur_cfr_warm_init(const pasur_fgt *f, const pasur_cfr_state *st, int level,
+                                   const float *Y, float kappa_r, float kappa_s, void *stream) {
+  if (!f || !st || !Y) {
+    set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  if (level < 1 || level > 8) {
+    set_error("level %d outside 1..8", level);
+    return PASUR_E_RANGE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t np = f->n[level - 1];
+  if (st->dtype == PASUR_F32)
+    k_warm_init<float><<<blocks(np), 256, 0, s>>>(np, f->child_begin[level - 1], Y, kappa_r,
+                                                  kappa_s, (float *)st->sigma[level],
+                                                  (float *)st->R[level], (float *)st->Sbar[level]);
+  else
+    k_warm_init<double><<<blocks(np), 256, 0, s>>>(np, f->child_begin[level - 1], Y, kappa_r,
+                                                   kappa_s, (double *)st->sigma[level],
+                                                   (double *)st->R[level], (double *)st->Sbar[level]);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+extern "C" int pasur_sample_parents(const pasur_fgt *f, int level, uint64_t seed, double keep_prob,
+                                    int32_t *d_seg, int32_t *d_edges, int64_t *n_parents,
+                                    int64_t *n_edges, void *stream) {
+  if (!f || !d_seg || !d_edges || !n_parents || !n_edges) {
+    set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  if (level < 1 || level > 8 || !(keep_prob >= 0.0 && keep_prob <= 1.0)) {
+    set_error("need level in 1..8 and keep_prob in [0, 1]");
+    return PASUR_E_RANGE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t np = f->n[level - 1];
+  const uint64_t thr = keep_prob >= 1.0 ? ~0ull : (uint64_t)(keep_prob * 18446744073709551615.0);
+  int32_t *flags = nullptr, *pos = nullptr, *par = nullptr, *fan = nullptr;
+  int st = dev_alloc(&flags, np);
+  if (!st) st = dev_alloc(&pos, np + 1);
+  if (!st) st = dev_alloc(&par, np);
+  if (!st) st = dev_alloc(&fan, np);
+  int64_t nsel = 0, ne = 0;
+  if (!st) {
+    k_sel_flags<<<blocks(np), 256, 0, s>>>(np, f->child_begin[level - 1], seed, level, thr, flags);
+    st = scan_counts(flags, np, pos, &nsel, s);
+  }
+  if (!st && nsel > 0) {
+    k_sel_compact<<<blocks(np), 256, 0, s>>>(np, flags, pos, f->child_begin[level - 1], par, fan);
+    st = scan_counts(fan, nsel, d_seg, &ne, s);
+    if (!st) {
+      k_sel_expand<<<blocks(nsel), 256, 0, s>>>(nsel, par, d_seg, f->child_begin[level - 1], d_edges);
+      hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        set_error("sample parents: %s", hipGetErrorString(e));
+        st = PASUR_E_HIP;
+      }
+    }
+  }
+  dev_free(flags);
+  dev_free(pos);
+  dev_free(par);
+  dev_free(fan);
+  *n_parents = nsel;
+  *n_edges = ne;
+  return st;
+}
+
+extern "C" int pasur_gather_f32(const void *src, int dtype, const int32_t *idx, int64_t n,
+                                float *dst, void *stream) {
+  if (!src || !dst || n < 0 || (dtype != PASUR_F32 && dtype != PASUR_F64)) {
+    set_error("bad gather arguments");
+    return PASUR_E_INVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == PASUR_F32)
+    k_gather<float><<<blocks(n), 256, 0, s>>>((const float *)src, idx, n, dst);
+  else
+    k_gather<double><<<blocks(n), 256, 0, s>>>((const double *)src, idx, n, dst);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+extern "C" int pasur_shift_i32(const int32_t *src, int64_t n, int32_t add, int32_t *dst,
+                               void *stream) {
+  if (!src || !dst || n < 0) {
+    set_error("bad shift arguments");
+    return PASUR_E_INVAL;
+  }
+  k_shift<<<blocks(n), 256, 0, (hipStream_t)stream>>>(src, n, add, dst);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}

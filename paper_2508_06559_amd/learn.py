@@ -1,0 +1,286 @@
+"""Learned warm start for DCFR (a13): driver over the libpasur MLP kernels.
+
+Training data come from this solver's own DCFR runs: for sampled decision
+nodes of every level, the feature rows of their children (card masks and
+inherited score, ``pasur_edge_features``), the average strategy of those
+children (policy target) and their node values (value target).  Training
+runs forward, loss, backward and Adam in libpasur kernels (BF16 MFMA GEMMs
+with FP32 accumulation, FP32 master weights).  The warm start predicts
+every node's policy logit, sets sigma = softmax over siblings, seeds the
+regrets and average-strategy sums with that profile, and iterates from a
+later t0 so that the DCFR discounts treat it as earlier iterations.  Plain
+DCFR is the fallback when the warm start does not reach the target.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import (PASUR_F32, PASUR_F64, MlpGrads, MlpWeights, CfrState, adam_step, average_strategy,
+               cfr_init, cfr_iterate, cfr_warm_init, edge_features, gather_f32, leaf_utilities,
+               mlp_backward, mlp_forward, mlp_loss, paper_params, round_values, sample_parents,
+               shift_i32, _torch)
+from .solver import SubgameSolver
+
+N_IN, N_HID, N_OUT = 160, 256, 2
+
+
+def _bf16_bits(x: np.ndarray) -> np.ndarray:
+    """float32 -> bfloat16 bit patterns, round to nearest even (host-side init)."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16).view(np.int16)
+
+
+@dataclass
+class Unit:
+    """One training unit: sampled parents of one round of one deal."""
+    X: object      # [rows, 160] BF16 bits (int16)
+    seg: object    # [parents + 1] int32 row offsets
+    tsig: object   # [rows] float32 target average strategy
+    tval: object   # [rows] float32 target node value
+    n_par: int
+    n_rows: int
+
+
+class WarmStartMLP:
+    """160-256-256-2 MLP; FP32 master weights with BF16 copies for the GEMMs."""
+
+    def __init__(self, seed: int = 0):
+        torch = _torch()
+        self.torch = torch
+        rng = np.random.default_rng(seed)
+        shapes = [(N_IN, N_HID), (N_HID,), (N_HID, N_HID), (N_HID,), (N_HID, N_OUT), (N_OUT,)]
+        init = [rng.normal(0, math.sqrt(2.0 / N_IN), shapes[0]), np.zeros(N_HID),
+                rng.normal(0, math.sqrt(2.0 / N_HID), shapes[2]), np.zeros(N_HID),
+                rng.normal(0, math.sqrt(1.0 / N_HID), shapes[4]), np.zeros(N_OUT)]
+        self.master = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in init]
+        self.bf = {k: torch.from_numpy(_bf16_bits(init[k]).copy()).cuda() for k in (0, 2, 4)}
+        self.m = [torch.zeros_like(t) for t in self.master]
+        self.v = [torch.zeros_like(t) for t in self.master]
+        self.g = [torch.zeros_like(t) for t in self.master]
+        self.step = 0
+        self._bufs = {}
+
+    def set_weights(self, W: Sequence[np.ndarray]):
+        """Load FP32 weights (W1, b1, W2, b2, W3, b3) and their BF16 copies."""
+        torch = self.torch
+        self.master = [torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda") for a in W]
+        self.bf = {k: torch.from_numpy(_bf16_bits(np.asarray(W[k], np.float32)).copy()).cuda()
+                   for k in (0, 2, 4)}
+
+    def weights(self) -> MlpWeights:
+        m, b = self.master, self.bf
+        return MlpWeights(b[0].data_ptr(), m[1].data_ptr(), b[2].data_ptr(), m[3].data_ptr(),
+                          b[4].data_ptr(), m[5].data_ptr())
+
+    def grads(self) -> MlpGrads:
+        g = self.g
+        return MlpGrads(*[t.data_ptr() for t in g])
+
+    def _buffers(self, M: int):
+        torch = self.torch
+        cap = self._bufs.get("cap", 0)
+        if M > cap:
+            cap = max(M, 2 * cap)
+            self._bufs = {"cap": cap,
+                          "H1": torch.empty((cap, N_HID), dtype=torch.int16, device="cuda"),
+                          "H2": torch.empty((cap, N_HID), dtype=torch.int16, device="cuda"),
+                          "Y": torch.empty((cap, N_OUT), dtype=torch.float32, device="cuda"),
+                          "dY": torch.empty((cap, N_OUT), dtype=torch.float32, device="cuda")}
+        return self._bufs
+
+    def forward(self, X, M: int):
+        """Y [M, 2] (a view into a reused buffer) for feature rows X."""
+        b = self._buffers(M)
+        w = self.weights()
+        mlp_forward(w, X, M, b["H1"], b["H2"], b["Y"])
+        return b["Y"][:M]
+
+    def train_unit(self, u: Unit, lr: float, value_weight: float = 0.05,
+                   betas=(0.9, 0.999), eps=1e-8):
+        torch = self.torch
+        b = self._buffers(u.n_rows)
+        w = self.weights()
+        mlp_forward(w, u.X, u.n_rows, b["H1"], b["H2"], b["Y"])
+        loss = torch.empty((u.n_par, 2), dtype=torch.float32, device="cuda")
+        mlp_loss(b["Y"], u.tsig, u.tval, u.seg, u.n_par, u.n_rows, value_weight, b["dY"], loss)
+        mlp_backward(w, u.X, b["H1"], b["H2"], b["dY"], u.n_rows, self.grads())
+        self.step += 1
+        for k in range(6):
+            adam_step(self.master[k], self.g[k], self.m[k], self.v[k], self.bf.get(k), lr,
+                      betas[0], betas[1], eps, self.step)
+        return loss
+
+    def state_dict(self):
+        return [t.detach().cpu().numpy().copy() for t in self.master]
+
+
+def make_units(solver: SubgameSolver, seed: int, parents_per_level: int = 400) -> List[Unit]:
+    """Training units from a solved SubgameSolver built with keep_gt=True:
+    one unit per round, sampled decision parents of every level."""
+    torch = _torch()
+    units = []
+    for rr in solver.rounds:
+        f, st = rr.fgt, rr.state
+        parts = []
+        for l in range(1, 9):
+            seg = torch.empty(f.n[l - 1] + 1, dtype=torch.int32, device="cuda")
+            edges = torch.empty(f.n[l], dtype=torch.int32, device="cuda")
+            keep = min(1.0, parents_per_level / max(1, f.n[l - 1]))
+            npar, ne = sample_parents(f, l, (seed << 8) ^ (rr.round << 4) ^ l, keep, seg, edges)
+            if npar:
+                parts.append((l, seg, edges, npar, ne))
+        rows = sum(p[4] for p in parts)
+        pars = sum(p[3] for p in parts)
+        if rows == 0:
+            continue
+        X = torch.empty((rows, N_IN), dtype=torch.int16, device="cuda")
+        tsig = torch.empty(rows, dtype=torch.float32, device="cuda")
+        tval = torch.empty(rows, dtype=torch.float32, device="cuda")
+        useg = torch.empty(pars + 1, dtype=torch.int32, device="cuda")
+        off = poff = 0
+        for l, seg, edges, npar, ne in parts:
+            edge_features(rr.gt, f, l, edges, ne, X[off:])
+            gather_f32(st.sigma_bar[l], st.dtype, edges, ne, tsig[off:])
+            gather_f32(st.u[l], st.dtype, edges, ne, tval[off:])
+            shift_i32(seg, npar + 1, off, useg[poff:])
+            off += ne
+            poff += npar
+        units.append(Unit(X, useg, tsig, tval, pars, rows))
+    return units
+
+
+def warm_start_round(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float):
+    """Predict every level's logits and seed sigma, R and Sbar (after cfr_init)."""
+    torch = _torch()
+    f = rr.fgt
+    for l in range(1, 9):
+        n = f.n[l]
+        X = torch.empty((n, N_IN), dtype=torch.int16, device="cuda")
+        edge_features(rr.gt, f, l, None, n, X)
+        Y = model.forward(X, n)
+        cfr_warm_init(rr.state, l, Y, kappa_r, kappa_s)
+
+
+@dataclass
+class WarmParams:
+    """kappa_r, kappa_s: regret and average-sum seeds (multiples of the
+    predicted profile); t_virtual: iterations the seeds stand for.  The
+    default uses the prediction as the first iterate only (seeds 0, t0 = 1):
+    on held-out two-round deals seeding regrets or averages with a profile
+    this exploitable slowed convergence, while starting from it did not."""
+    kappa_r: float = 0.0
+    kappa_s: float = 0.0
+    t_virtual: int = 0
+
+
+def solve_subgame(deck, start_round: int, roots, iters: int, dtype: int = PASUR_F32,
+                  model: Optional[WarmStartMLP] = None, warm: WarmParams = WarmParams(),
+                  params=None):
+    """Backward solve of a subgame, plain or warm-started; returns the solver
+    (states and round values filled)."""
+    torch = _torch()
+    sv = SubgameSolver(deck, start_round, roots, dtype=dtype, keep_gt=model is not None)
+    params = params if params is not None else paper_params()
+    V = None
+    for rr in reversed(sv.rounds):
+        rr.state = CfrState(rr.fgt, dtype)
+        leaf_utilities(rr.fgt, V, dtype, rr.state.u[8])
+        cfr_init(rr.state)
+        t0 = 1
+        if model is not None:
+            warm_start_round(model, rr, warm.kappa_r, warm.kappa_s)
+            t0 = warm.t_virtual + 1
+        cfr_iterate(rr.state, iters, params, t0=t0)
+        average_strategy(rr.state)
+        rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
+        # round value: mean of the iterate values of the iterations run (the
+        # paper's g_UTL / NUM_ITER); vacc holds exactly `iters` terms
+        rr.state.t = 1 + iters
+        round_values(rr.state, 0, rr.V)
+        rr.state.t = t0 + iters
+        V = rr.V
+    return sv
+
+
+def exploitability(sv: SubgameSolver) -> float:
+    bra, brb, _ = sv.exploitability()
+    return float(((bra - brb) / 2).max().item())
+
+
+def seconds_to_target(deck, start_round: int, roots, target: float, grid: Sequence[int],
+                      model: Optional[WarmStartMLP] = None, warm: WarmParams = WarmParams(),
+                      fallback: bool = True):
+    """Smallest iteration count of ``grid`` whose solve reaches exploitability
+    <= target, and the wall-clock seconds of that solve (exploitability checks
+    excluded).  A warm start that misses the target on the whole grid falls
+    back to plain DCFR; its seconds then include the failed warm attempts."""
+    torch = _torch()
+    spent = 0.0
+    for T in grid:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv = solve_subgame(deck, start_round, roots, T, model=model, warm=warm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ex = exploitability(sv)
+        sv.free()
+        if ex <= target:
+            return {"iters": T, "seconds": el, "exploitability": ex, "fallback": False}
+        if model is not None:
+            spent += el
+    if model is not None and fallback:
+        r = seconds_to_target(deck, start_round, roots, target, grid, None)
+        r["seconds"] += spent
+        r["fallback"] = True
+        return r
+    return {"iters": None, "seconds": None, "exploitability": ex, "fallback": False}
+
+
+def train(model: WarmStartMLP, units: List[Unit], epochs: int, seed: int = 0, lr: float = 2e-3,
+          log=None):
+    """Adam over shuffled units; lr stepped down at 1/2 and 3/4 of the epochs."""
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        r = lr if ep < epochs // 2 else (lr * 0.3 if ep < 3 * epochs // 4 else lr * 0.1)
+        tot = np.zeros(2)
+        for i in rng.permutation(len(units)):
+            tot += model.train_unit(units[i], lr=r).sum(0).cpu().numpy()
+        hist.append((tot / max(1, len(units))).tolist())
+        if log:
+            log(f"[train] epoch {ep}: policy {hist[-1][0]:.4f} value {hist[-1][1]:.4f}")
+    return hist
+
+
+def training_units(problems, iters: int, parents_per_level: int = 600, seed0: int = 0):
+    """Solve every (deck, roots) two-round problem with plain DCFR and sample
+    training units from the solution."""
+    units = []
+    for k, (deck, roots) in enumerate(problems):
+        sv = SubgameSolver(deck, 4, roots, keep_gt=True)
+        sv.solve(iters)
+        units += make_units(sv, seed0 + k, parents_per_level)
+        sv.free()
+    return units
+
+
+def initial_profile_exploitability(deck, roots, model: Optional[WarmStartMLP]):
+    """Exploitability of the profile DCFR starts from: uniform, or the
+    network's prediction."""
+    sv = SubgameSolver(deck, 4, roots, keep_gt=True)
+    for rr in sv.rounds:
+        rr.state = CfrState(rr.fgt, PASUR_F32)
+        cfr_init(rr.state)
+        if model is not None:
+            warm_start_round(model, rr, 0.0, 0.0)
+        for l in range(1, 9):
+            rr.state.sigma_bar[l].copy_(rr.state.sigma[l])
+    ex = exploitability(sv)
+    sv.free()
+    return ex

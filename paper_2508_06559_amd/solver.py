@@ -24,12 +24,14 @@ class RoundResult:
     fgt: UnfoldedTree
     state: Optional[CfrState] = None
     V: Optional[object] = None  # device double tensor, one value per root
+    gt: Optional[object] = None  # the round's game tree, kept when features are needed
 
 
 class SubgameSolver:
     """All rounds from ``start_round`` to 5 of one deal."""
 
-    def __init__(self, deck, start_round: int, roots, dtype: int = PASUR_F32, stream=None):
+    def __init__(self, deck, start_round: int, roots, dtype: int = PASUR_F32, stream=None,
+                 keep_gt: bool = False):
         torch = _torch()
         self.deck = list(int(c) for c in deck)
         self.start = start_round
@@ -42,8 +44,10 @@ class SubgameSolver:
         for r in range(start_round, 6):
             gt = build_round_tree(self.deck, r, ptr, n, stream)
             fgt = unfold_scores(gt, ptr, n, stream)
-            gt.free()
-            self.rounds.append(RoundResult(r, fgt))
+            if not keep_gt:
+                gt.free()
+                gt = None
+            self.rounds.append(RoundResult(r, fgt, gt=gt))
             if r < 5:
                 ptr, n = fgt.next_roots_device()
         self.torch = torch
@@ -92,6 +96,8 @@ class SubgameSolver:
     def free(self):
         for rr in self.rounds:
             rr.fgt.free()
+            if rr.gt is not None:
+                rr.gt.free()
         self.rounds = []
 
 

@@ -1,0 +1,138 @@
+"""GPU parity of the learned part: the BF16 MFMA GEMM, the MLP forward and
+backward passes, the loss and the features, against the FP64 oracle with
+bfloat16 rounding at the same points (oracle/mlp.py).  Tolerances: products
+of bfloat16 values are exact in FP32, so GEMMs differ from the FP64 sum only
+by FP32 accumulation (relative 1e-6 of the sum of |terms|); a hidden
+activation can round to a neighbouring bfloat16 value when the FP32 and FP64
+pre-activations straddle a rounding boundary, so activations are compared to
+one bfloat16 ulp and gradients by relative norm (1e-2)."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import require_gpu, to_np
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_tensor(x):
+    import torch
+    return torch.from_numpy(omlp.bf16_bits(x).view(np.int16).copy()).cuda()
+
+
+def from_bf16(t):
+    u = to_np(t).view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("M,N,K,transA,transB", [(100, 70, 45, False, False), (64, 64, 32, False, False),
+                                                  (33, 257, 160, False, True), (160, 256, 1000, True, False),
+                                                  (1, 2, 256, False, False), (515, 2, 256, False, False)])
+def test_gemm_matches_fp64(M, N, K, transA, transB):
+    pa = require_gpu()
+    import torch
+    rng = np.random.default_rng(M * 7 + N)
+    A = omlp.bf16_round(rng.normal(0, 1, (K, M) if transA else (M, K)))
+    B = omlp.bf16_round(rng.normal(0, 1, (N, K) if transB else (K, N)))
+    opA = A.T if transA else A
+    opB = B.T if transB else B
+    want = opA @ opB
+    bound = np.abs(opA) @ np.abs(opB) * 2e-6 + 1e-30
+    dA, dB = bf16_tensor(A), bf16_tensor(B)
+    C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    sar, sac = (1, M) if transA else (K, 1)
+    sbr, sbc = (1, K) if transB else (N, 1)
+    print(f"[gemm] M={M} N={N} K={K} transA={transA} transB={transB}", flush=True)
+    pa.gemm_bf16(M, N, K, dA, sar, sac, dB, sbr, sbc, Cf=C)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(to_np(C) - want) <= bound)
+
+
+def make_problem(seed, n_par=300):
+    rng = np.random.default_rng(seed)
+    fan = rng.integers(1, 6, n_par)
+    seg = np.concatenate([[0], np.cumsum(fan)]).astype(np.int32)
+    M = int(seg[-1])
+    X = rng.integers(0, 2, (M, 160)).astype(np.float64)
+    X[:, 156:] = rng.normal(0, 0.5, (M, 4))
+    X = omlp.bf16_round(X)
+    tsig = np.concatenate([rng.dirichlet(np.ones(k)) for k in fan]).astype(np.float32)
+    tval = rng.normal(0, 3, M).astype(np.float32)
+    W = omlp.init_weights(rng)
+    W[1] = rng.normal(0, 0.1, 256)
+    W[3] = rng.normal(0, 0.1, 256)
+    W[5] = rng.normal(0, 0.1, 2)
+    W = [np.asarray(w, np.float32).astype(np.float64) for w in W]
+    return X, seg, tsig, tval, W
+
+
+def test_mlp_forward_backward_match_oracle():
+    pa = require_gpu()
+    from paper_2508_06559_amd import learn
+    import torch
+    X, seg, tsig, tval, W = make_problem(3)
+    M = X.shape[0]
+    model = learn.WarmStartMLP(0)
+    model.set_weights(W)
+    # the host-side bfloat16 conversion of the binding equals the oracle's
+    for k in (0, 2, 4):
+        assert np.array_equal(to_np(model.bf[k]).view(np.uint16), omlp.bf16_bits(W[k]))
+    dX = bf16_tensor(X)
+    b = model._buffers(M)
+    w = model.weights()
+    pa.mlp_forward(w, dX, M, b["H1"], b["H2"], b["Y"])
+    dseg = torch.from_numpy(seg).cuda()
+    dts, dtv = torch.from_numpy(tsig).cuda(), torch.from_numpy(tval).cuda()
+    loss = torch.empty((len(seg) - 1, 2), dtype=torch.float32, device="cuda")
+    pa.mlp_loss(b["Y"], dts, dtv, dseg, len(seg) - 1, M, 0.5, b["dY"], loss)
+    pa.mlp_backward(w, dX, b["H1"], b["H2"], b["dY"], M, model.grads())
+    torch.cuda.synchronize()
+    H1o, H2o, Yo = omlp.forward(W, X, bf16=True)
+    H1g, H2g = from_bf16(b["H1"][:M]), from_bf16(b["H2"][:M])
+    for Hg, Ho in ((H1g, H1o), (H2g, H2o)):
+        assert np.all(np.abs(Hg - Ho) <= np.abs(Ho) * 2 ** -7 + 1e-6)
+        assert np.mean(Hg != Ho) < 0.01
+    Yg = to_np(b["Y"][:M]).astype(np.float64)
+    assert np.abs(Yg - Yo).max() <= 1e-2 * (np.abs(Yo).max() + 1)
+    # loss gradient and weight gradients, both from the oracle's own activations
+    lo, dYo = omlp.loss_and_dY(Yg, seg, tsig.astype(np.float64), tval.astype(np.float64), 0.5)
+    dYg = to_np(b["dY"][:M]).astype(np.float64)
+    assert np.abs(dYg - dYo).max() <= 1e-6 * (np.abs(dYo).max() + 1e-12) + 1e-9
+    assert float(loss.sum()) == pytest.approx(lo, rel=1e-4)
+    go = omlp.backward(W, X, H1g, H2g, dYg, bf16=True)
+    for gg, gref in zip(model.g, go):
+        gg = to_np(gg).astype(np.float64).reshape(gref.shape)
+        assert np.linalg.norm(gg - gref) <= 1e-2 * np.linalg.norm(gref) + 1e-12
+
+
+def test_features_encode_state_and_score():
+    pa = require_gpu()
+    import torch
+    deck, roots = synth.last_round_roots(2)
+    s = pa.SubgameSolver(deck, 5, roots, keep_gt=True)
+    rr = s.rounds[0]
+    l = 3
+    n = rr.fgt.n[l]
+    X = torch.empty((n, 160), dtype=torch.int16, device="cuda")
+    pa.edge_features(rr.gt, rr.fgt, l, None, n, X)
+    torch.cuda.synchronize()
+    Xf = from_bf16(X)
+    g = rr.fgt.read(pa.FGT_GT, l)
+    sid = rr.fgt.read(pa.FGT_SID, l)
+    tab = rr.fgt.read(pa.FGT_SCORE_TAB)
+    pool = rr.gt.read(pa.GT_POOL, l)
+    hands = rr.gt.read(pa.GT_HANDS, l)
+    a, b = synth.round_hands(deck, 5)
+    for i in range(0, n, max(1, n // 50)):
+        t = g[i]
+        ha = [a[k] for k in range(4) if (hands[t] >> k) & 1]
+        hb = [b[k] for k in range(4) if (hands[t] >> (4 + k)) & 1]
+        want = np.zeros(160)
+        want[ha] = 1
+        want[[52 + c for c in hb]] = 1
+        want[[104 + c for c in range(52) if (int(pool[t]) >> c) & 1]] = 1
+        ca, cb, d, bo = tab[sid[i]]
+        want[156:] = omlp.bf16_round([ca / 7, cb / 7, d / 16, {0: 0, 1: 1, 2: -1}[int(bo)]])
+        assert np.array_equal(Xf[i], want), i
+    s.free()
