@@ -23,6 +23,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CFR node-updates/s at 1 GPU; secs to exploitability 1e-3, warm-start vs plain"
+
+# HBM bytes per k_cfr_seg launch of the two-round workload (FP32 state, default
+# schedule) from rocprofv3 FETCH_SIZE / WRITE_SIZE counters, scaled by a
+# plain-copy calibration (profiles/k_cfr_seg_two_round_seed1.md).  Valid only
+# while the kernel source is unchanged.
+TRAFFIC = {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
+           "sha256": "a9ddbbca49737eeb500f3a224d5a02ed7f42e08c47e730a4e615fae2780b6f9b",
+           "bytes_per_launch": 10.2e6}
+
+
+def counted_traffic(args):
+    import hashlib
+    path = os.path.join(ROOT, TRAFFIC["source"])
+    with open(path, "rb") as fh:
+        same = hashlib.sha256(fh.read()).hexdigest() == TRAFFIC["sha256"]
+    if same and args.state == "f32" and args.sched == "root" and args.block in (0, 1024):
+        return TRAFFIC["bytes_per_launch"]
+    return None
 HBM_PEAK_GBS = 8000.0
 
 
@@ -256,7 +274,8 @@ def main():
     ap.add_argument("--sched", choices=["root", "level", "root-global"], default="root")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["two-round", "batched", "warm-start"], default="two-round",
+    ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "copy"],
+                    default="two-round",
                     help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
     ap.add_argument("--train-deals", type=int, default=512)
@@ -278,6 +297,16 @@ def main():
         return bench_batched(args)
     if args.workload == "warm-start":
         return bench_warm(args)
+    if args.workload == "copy":
+        # calibration for hardware byte counters: a plain device copy of a
+        # known size (256 MiB read + 256 MiB written per launch, 4 launches)
+        x = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(4):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy", "bytes_per_launch_each_way": 1 << 28, "launches": 4}))
+        return
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
     params = pa.paper_params({"root": pa.SCHED_ROOT, "level": pa.SCHED_LEVEL_SYNC,
@@ -366,7 +395,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": counted_traffic(args),
             "avg_launch_us": dt / dc * 1e6,
             "launches": dc,
             "algorithmic_bytes_per_launch": db / dc,
