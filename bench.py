@@ -29,8 +29,8 @@ METRIC = "CFR node-updates/s at 1 GPU; secs to exploitability 1e-3, warm-start v
 # plain-copy calibration (profiles/k_cfr_seg_two_round_seed1.md).  Valid only
 # while the kernel source is unchanged.
 TRAFFIC = {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
-           "sha256": "a9ddbbca49737eeb500f3a224d5a02ed7f42e08c47e730a4e615fae2780b6f9b",
-           "bytes_per_launch": 10.2e6}
+           "sha256": "16fb5a51500e640915b88842d39d7bc2c57124c5aebbb58c19f469bc39f8126d",
+           "bytes_per_launch": 4.38e6}
 
 
 def counted_traffic(args):
@@ -69,7 +69,7 @@ def launch_bytes(kernel, level, work, T):
     return iters * (up + down)
 
 
-KERNEL_NAMES = {0: "k_down", 1: "k_up", 2: "k_cfr_root (all LDS)", 3: "k_cfr_root (LDS + global)"}
+KERNEL_NAMES = {0: "k_down", 1: "k_up", 2: "k_cfr_seg (all LDS)", 3: "k_cfr_seg (LDS + global)"}
 
 
 def cpu_baseline(deck, roots, iters):
@@ -181,6 +181,50 @@ def bench_batched(args):
     b.free()
 
 
+def bench_full(args):
+    """All six rounds of seeded deal --seed from the initial deal (survey
+    config 3): build and unfold every round, then DCFR round by round from
+    round 6 backward (--iters per round, default 1000), with exploitability."""
+    import torch
+    import paper_2508_06559_amd as pa
+    import synth
+
+    dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
+    T = 4 if args.state == "f32" else 8
+    iters = 1000 if args.iters == 2000 else args.iters
+    deck, roots = synth.full_game_root(args.seed)
+    params = pa.paper_params(block=args.block)
+    times = []
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = pa.SubgameSolver(deck, 0, roots, dtype=dtype)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        s.solve(iters, params)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bra, brb, _ = s.exploitability()
+        ex = float(((bra - brb) / 2).max().item())
+        sizes = s.sizes()
+        V0 = float(s.rounds[0].V[0].item())
+        s.free()
+        times.append((t1 - t0, tb - t0))
+        log(f"[bench] full game step {k + 1}: build {tb - t0:.2f} s, total {t1 - t0:.2f} s, "
+            f"exploitability {ex:.2e}, value {V0:.3f}")
+    el = sum(t for t, _ in times[args.warmup:])
+    edges = sum(sum(n[1:]) for n in sizes)
+    out = {"metric": METRIC, "value": edges * iters * args.steps / el, "unit": "node-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"full game of seeded deal {args.seed}: 6 rounds, "
+                                  f"{sum(sum(n) for n in sizes)} nodes, {iters} DCFR iterations per round",
+                      "state": args.state, "round_sizes": [sum(n) for n in sizes],
+                      "build_seconds": times[-1][1], "exploitability_points": ex, "game_value": V0}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_warm(args):
     """Learned warm start: train the MLP on DCFR solutions of --train-deals
     seeded two-round deals (seeds 10000..), then on --test-deals held-out
@@ -274,7 +318,7 @@ def main():
     ap.add_argument("--sched", choices=["root", "level", "root-global"], default="root")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "copy"],
+    ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game", "copy"],
                     default="two-round",
                     help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
@@ -297,6 +341,8 @@ def main():
         return bench_batched(args)
     if args.workload == "warm-start":
         return bench_warm(args)
+    if args.workload == "full-game":
+        return bench_full(args)
     if args.workload == "copy":
         # calibration for hardware byte counters: a plain device copy of a
         # known size (256 MiB read + 256 MiB written per launch, 4 launches)

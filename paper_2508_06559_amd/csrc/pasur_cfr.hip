@@ -203,121 +203,168 @@ struct Seg {
 
 extern __shared__ __align__(16) unsigned char g_lds[];
 
-template <class T>
-struct LdsArr {
-  uint32_t off;
-  __device__ T &operator[](int i) const { return reinterpret_cast<T *>(g_lds + off)[i]; }
-};
-
 // Byte layout of one segment's state in LDS (shared by host sizing and
-// device carving): per level sigma, R, Sbar (levels 1..8), u (0..8), reachA,
-// reachB (0..7) as T, then parent (1..8) and child_begin (0..7) as 16-bit
-// indices local to the segment; every array 16-byte aligned.
-struct LdsLayout {
-  uint32_t sg[9], R[9], Sb[9], u[9], ra[9], rb[9], par[9], cb[9];
-  uint32_t bytes;
-};
+// device carving).  Level l occupies one block starting at base[l]: its T
+// arrays in fixed slots of stride[l] = align16(n_l * sizeof(T)) bytes --
+// u (slot 0), sigma, R, Sbar (slots 1-3, levels 1..8), reachA, reachB
+// (slots 4-5, levels 0..7; level 8 has only slots 0-3) -- then the 16-bit
+// segment-local parent (levels 1..8) and child_begin (levels 0..7) indices.
+// The roots' utility sums (double) follow the last level.
+// Every address is base + slot * stride, so a kernel keeps two scalars per
+// level instead of one offset per array.
+enum { F_U = 0, F_SG = 1, F_R = 2, F_SB = 3, F_RA = 4, F_RB = 5 };
 
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+__host__ __device__ inline uint32_t lds_tslots(int l) { return l == 8 ? 4u : 6u; }
+
+struct LdsLayout {
+  uint32_t base[9], stride[9];
+  uint32_t vacc;  // double per root: running sum of root utilities
+  uint32_t bytes;
+};
 
 __host__ __device__ inline LdsLayout lds_layout(const int cnt[9], uint32_t tsize) {
   LdsLayout L;
   uint32_t p = 0;
   for (int l = 0; l <= 8; ++l) {
-    L.sg[l] = L.R[l] = L.Sb[l] = 0;
-    if (l >= 1) {
-      L.sg[l] = p; p = align16(p + cnt[l] * tsize);
-      L.R[l] = p; p = align16(p + cnt[l] * tsize);
-      L.Sb[l] = p; p = align16(p + cnt[l] * tsize);
-    }
-    L.u[l] = p; p = align16(p + cnt[l] * tsize);
-    L.ra[l] = L.rb[l] = 0;
-    if (l <= 7) {
-      L.ra[l] = p; p = align16(p + cnt[l] * tsize);
-      L.rb[l] = p; p = align16(p + cnt[l] * tsize);
-    }
+    L.base[l] = p;
+    L.stride[l] = align16((uint32_t)cnt[l] * tsize);
+    p += lds_tslots(l) * L.stride[l];
+    if (l >= 1) p += align16((uint32_t)cnt[l] * 2u);
+    if (l <= 7) p += align16((uint32_t)(cnt[l] + 1) * 2u);
   }
-  for (int l = 0; l <= 8; ++l) {
-    L.par[l] = L.cb[l] = 0;
-    if (l >= 1) { L.par[l] = p; p = align16(p + cnt[l] * 2); }
-    if (l <= 7) { L.cb[l] = p; p = align16(p + (cnt[l] + 1) * 2); }
-  }
+  L.vacc = p;
+  p += align16((uint32_t)cnt[0] * 8u);
   L.bytes = p;
   return L;
 }
 
-template <class AT, class AI>
-struct Sub {
-  AT sg[9], Rr[9], Sb[9], uu[9], ra[9], rb[9];
-  AI par[9], cbl[9];
-  int par_sub[9], cb_sub[9];
-  int cnt[9];
+// A uniform value the optimiser must treat as unknown at each use.  Without
+// it, loop-invariant code motion lifts every level's per-lane LDS addresses
+// (9 levels x 8 arrays) out of the iteration loop; they do not fit in
+// registers and spill to scratch, and each level phase then starts with
+// scratch reloads.  Recomputing an address costs a few scalar operations.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  x = __builtin_amdgcn_readfirstlane(x);
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
+template <class T>
+struct LdsArr {
+  uint32_t off;
+  __device__ __forceinline__ T &operator[](int i) const { return reinterpret_cast<T *>(g_lds + off)[i]; }
 };
 
+// A segment's state in LDS, addressed through lds_layout.
+template <class T>
+struct SubLds {
+  uint32_t base[9], stride[9], vacc;
+  int cnt[9];
+  __device__ __forceinline__ void vacc_add(int h, double v, double &) const {
+    LdsArr<double>{opaque(vacc)}[h] += v;
+  }
+  __device__ __forceinline__ LdsArr<T> f(int l, int slot) const {
+    return {opaque(base[l]) + slot * opaque(stride[l])};
+  }
+  __device__ __forceinline__ LdsArr<T> sg(int l) const { return f(l, F_SG); }
+  __device__ __forceinline__ LdsArr<T> Rr(int l) const { return f(l, F_R); }
+  __device__ __forceinline__ LdsArr<T> Sb(int l) const { return f(l, F_SB); }
+  __device__ __forceinline__ LdsArr<T> uu(int l) const { return f(l, F_U); }
+  __device__ __forceinline__ LdsArr<T> ra(int l) const { return f(l, F_RA); }
+  __device__ __forceinline__ LdsArr<T> rb(int l) const { return f(l, F_RB); }
+  __device__ __forceinline__ LdsArr<uint16_t> par(int l) const {
+    return {opaque(base[l]) + lds_tslots(l) * opaque(stride[l])};
+  }
+  __device__ __forceinline__ LdsArr<uint16_t> cbl(int l) const {
+    return {opaque(base[l]) + lds_tslots(l) * opaque(stride[l]) +
+            (l >= 1 ? align16((uint32_t)cnt[l] * 2u) : 0u)};
+  }
+  __device__ __forceinline__ int par_sub(int) const { return 0; }
+  __device__ __forceinline__ int cb_sub(int) const { return 0; }
+};
+
+// FindUtility for one parent whose children sit at b..e-1 of the level
+// arrays: returns u(h) and updates R, sigma and Sbar of the children, in the
+// same operation order as k_up.
+template <class T, class AS, class AR, class AB, class AU>
+__device__ __forceinline__ double update_parent(const AS &sg, const AR &Rr, const AB &Sb,
+                                                const AU &uu, int b, int e, int mover,
+                                                double opp, double own, const IterK &ik,
+                                                int variant, int rm_mode, double eps) {
+  const double sgn = mover == 0 ? 1.0 : -1.0;
+  double uh = 0.0;
+  for (int q = b; q < e; ++q) uh += (double)sg[q] * (double)uu[q];
+  double sum = 0.0;
+  for (int q = b; q < e; ++q) {
+    const double r = sgn * opp * ((double)uu[q] - uh);
+    double Rq = (double)Rr[q];
+    if (variant == PASUR_DCFR) {
+      const double d = Rq > 0.0 ? ik.dpos : ik.dneg;
+      Rq = d * Rq + r;
+    } else if (variant == PASUR_CFR_PLUS) {
+      Rq = Rq + r;
+      if (Rq < 0.0) Rq = 0.0;
+    } else {
+      Rq = Rq + r;
+    }
+    const T Rs = (T)Rq;
+    Rr[q] = Rs;
+    sum += rm_mode == PASUR_RM_FLOOR ? fmax((double)Rs, eps) : fmax((double)Rs, 0.0);
+  }
+  const double inv_k = 1.0 / (double)(e - b);
+  for (int q = b; q < e; ++q) {
+    const double x = rm_mode == PASUR_RM_FLOOR ? fmax((double)Rr[q], eps) : fmax((double)Rr[q], 0.0);
+    const double s_new = sum > 0.0 ? x / sum : inv_k;
+    double add = own * (double)sg[q];
+    if (variant == PASUR_CFR_PLUS) add *= ik.avg_t;
+    Sb[q] = (T)(ik.avg_w * (double)Sb[q] + add);
+    sg[q] = (T)s_new;
+  }
+  return uh;
+}
+
 // All iterations of one segment (FindReachProbability then FindUtility per
-// iteration, as in k_down / k_up).  Thread t owns root t of the segment at
-// level 0 and accumulates its vacc.
+// iteration, as in k_down / k_up): every level is one phase of the whole
+// workgroup, one thread per node (down) or per parent (up), with a barrier
+// between levels.
 template <class T, class SubT>
-__device__ inline void subtree_iterations(const SubT &S, const IterK *__restrict__ ks,
-                                          int n_iters, int variant, int rm_mode, double eps,
-                                          double &vacc_acc) {
+__device__ __forceinline__ void subtree_iterations(const SubT &S, const IterK *__restrict__ ks,
+                                                   int n_iters, int variant, int rm_mode,
+                                                   double eps, double &vacc_reg) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int it = 0; it < n_iters; ++it) {
     const IterK k = ks[it];
 #pragma unroll
     for (int l = 1; l <= 7; ++l) {
       const int mover = (l - 1) & 1;
-      for (int q = tid; q < S.cnt[l]; q += nt) {
-        const int h = (int)S.par[l][q] - S.par_sub[l];
-        double a = (double)S.ra[l - 1][h];
-        double b = (double)S.rb[l - 1][h];
-        if (mover == 0) a *= (double)S.sg[l][q];
-        else b *= (double)S.sg[l][q];
-        S.ra[l][q] = (T)a;
-        S.rb[l][q] = (T)b;
+      int t0 = tid;
+      asm volatile("" : "+v"(t0));  // per-lane start stays inside the phase (see opaque)
+      for (int q = t0; q < S.cnt[l]; q += nt) {
+        const int h = (int)S.par(l)[q] - S.par_sub(l);
+        double a = (double)S.ra(l - 1)[h];
+        double b = (double)S.rb(l - 1)[h];
+        if (mover == 0) a *= (double)S.sg(l)[q];
+        else b *= (double)S.sg(l)[q];
+        S.ra(l)[q] = (T)a;
+        S.rb(l)[q] = (T)b;
       }
       __syncthreads();
     }
 #pragma unroll
     for (int l = 8; l >= 1; --l) {
       const int mover = (l - 1) & 1;
-      const double sgn = mover == 0 ? 1.0 : -1.0;
-      for (int h = tid; h < S.cnt[l - 1]; h += nt) {
-        const int b = (int)S.cbl[l - 1][h] - S.cb_sub[l - 1];
-        const int e = (int)S.cbl[l - 1][h + 1] - S.cb_sub[l - 1];
-        double uh = 0.0;
-        for (int q = b; q < e; ++q) uh += (double)S.sg[l][q] * (double)S.uu[l][q];
-        S.uu[l - 1][h] = (T)uh;
-        const double opp = mover == 0 ? (double)S.rb[l - 1][h] : (double)S.ra[l - 1][h];
-        const double own = mover == 0 ? (double)S.ra[l - 1][h] : (double)S.rb[l - 1][h];
-        double sum = 0.0;
-        for (int q = b; q < e; ++q) {
-          const double r = sgn * opp * ((double)S.uu[l][q] - uh);
-          double Rq = (double)S.Rr[l][q];
-          if (variant == PASUR_DCFR) {
-            const double d = Rq > 0.0 ? k.dpos : k.dneg;
-            Rq = d * Rq + r;
-          } else if (variant == PASUR_CFR_PLUS) {
-            Rq = Rq + r;
-            if (Rq < 0.0) Rq = 0.0;
-          } else {
-            Rq = Rq + r;
-          }
-          const T Rs = (T)Rq;
-          S.Rr[l][q] = Rs;
-          sum += rm_mode == PASUR_RM_FLOOR ? fmax((double)Rs, eps) : fmax((double)Rs, 0.0);
-        }
-        const double inv_k = 1.0 / (double)(e - b);
-        for (int q = b; q < e; ++q) {
-          const double x = rm_mode == PASUR_RM_FLOOR ? fmax((double)S.Rr[l][q], eps)
-                                                     : fmax((double)S.Rr[l][q], 0.0);
-          const double s_new = sum > 0.0 ? x / sum : inv_k;
-          double add = own * (double)S.sg[l][q];
-          if (variant == PASUR_CFR_PLUS) add *= k.avg_t;
-          S.Sb[l][q] = (T)(k.avg_w * (double)S.Sb[l][q] + add);
-          S.sg[l][q] = (T)s_new;
-        }
-        if (l == 1) vacc_acc += uh;  // h == tid: segments hold at most BLOCK roots
+      int t0 = tid;
+      asm volatile("" : "+v"(t0));
+      for (int h = t0; h < S.cnt[l - 1]; h += nt) {
+        const int b = (int)S.cbl(l - 1)[h] - S.cb_sub(l - 1);
+        const int e = (int)S.cbl(l - 1)[h + 1] - S.cb_sub(l - 1);
+        const double opp = mover == 0 ? (double)S.rb(l - 1)[h] : (double)S.ra(l - 1)[h];
+        const double own = mover == 0 ? (double)S.ra(l - 1)[h] : (double)S.rb(l - 1)[h];
+        const double uh = update_parent<T>(S.sg(l), S.Rr(l), S.Sb(l), S.uu(l), b, e, mover,
+                                           opp, own, k, variant, rm_mode, eps);
+        S.uu(l - 1)[h] = (T)uh;
+        if (l == 1) S.vacc_add(h, uh, vacc_reg);
       }
       __syncthreads();
     }
@@ -325,66 +372,61 @@ __device__ inline void subtree_iterations(const SubT &S, const IterK *__restrict
 }
 
 template <class T, int BLOCK>
-__device__ inline void seg_in_lds(const ItemDesc<T> &D, int j0, int nroots, const int lo[9],
+__device__ __forceinline__ void seg_in_lds(const ItemDesc<T> &D, int j0, int nroots, const int lo[9],
                                   const int cnt[9], const LdsLayout &L,
                                   const IterK *__restrict__ ks, int n_iters, int variant,
                                   int rm_mode, double eps) {
   const int tid = threadIdx.x;
-  Sub<LdsArr<T>, LdsArr<uint16_t>> S;
+  SubLds<T> S;
 #pragma unroll
   for (int l = 0; l <= 8; ++l) {
-    S.sg[l].off = L.sg[l];
-    S.Rr[l].off = L.R[l];
-    S.Sb[l].off = L.Sb[l];
-    S.uu[l].off = L.u[l];
-    S.ra[l].off = L.ra[l];
-    S.rb[l].off = L.rb[l];
-    S.par[l].off = L.par[l];
-    S.cbl[l].off = L.cb[l];
-    S.par_sub[l] = 0;
-    S.cb_sub[l] = 0;
+    S.base[l] = L.base[l];
+    S.stride[l] = L.stride[l];
     S.cnt[l] = cnt[l];
   }
+  S.vacc = L.vacc;
+  const LdsArr<double> vacc{L.vacc};
   // load the segment's state
 #pragma unroll
   for (int l = 0; l <= 8; ++l) {
     for (int i = tid; i < cnt[l]; i += BLOCK) {
       if (l >= 1) {
-        S.sg[l][i] = D.sigma[l][lo[l] + i];
-        S.Rr[l][i] = D.R[l][lo[l] + i];
-        S.Sb[l][i] = D.Sbar[l][lo[l] + i];
-        S.par[l][i] = (uint16_t)(D.parent[l][lo[l] + i] - lo[l - 1]);
+        S.sg(l)[i] = D.sigma[l][lo[l] + i];
+        S.Rr(l)[i] = D.R[l][lo[l] + i];
+        S.Sb(l)[i] = D.Sbar[l][lo[l] + i];
+        S.par(l)[i] = (uint16_t)(D.parent[l][lo[l] + i] - lo[l - 1]);
       }
-      if (l == 8) S.uu[l][i] = D.u[l][lo[l] + i];
+      if (l == 8) S.uu(l)[i] = D.u[l][lo[l] + i];
       if (l == 0) {
-        S.ra[0][i] = D.ra[0][lo[0] + i];
-        S.rb[0][i] = D.rb[0][lo[0] + i];
+        S.ra(0)[i] = D.ra[0][lo[0] + i];
+        S.rb(0)[i] = D.rb[0][lo[0] + i];
       }
     }
     if (l <= 7)
       for (int i = tid; i <= cnt[l]; i += BLOCK)
-        S.cbl[l][i] = (uint16_t)(D.cb[l][lo[l] + i] - lo[l + 1]);
+        S.cbl(l)[i] = (uint16_t)(D.cb[l][lo[l] + i] - lo[l + 1]);
   }
+  for (int i = tid; i < nroots; i += BLOCK) vacc[i] = D.vacc[j0 + i];
   __syncthreads();
-  double vacc_acc = tid < nroots ? D.vacc[j0 + tid] : 0.0;
-  subtree_iterations<T>(S, ks, n_iters, variant, rm_mode, eps, vacc_acc);
+  double unused = 0.0;
+  subtree_iterations<T>(S, ks, n_iters, variant, rm_mode, eps, unused);
   // write the state back
 #pragma unroll
   for (int l = 0; l <= 8; ++l) {
     for (int i = tid; i < cnt[l]; i += BLOCK) {
       if (l >= 1) {
-        D.sigma[l][lo[l] + i] = S.sg[l][i];
-        D.R[l][lo[l] + i] = S.Rr[l][i];
-        D.Sbar[l][lo[l] + i] = S.Sb[l][i];
+        D.sigma[l][lo[l] + i] = S.sg(l)[i];
+        D.R[l][lo[l] + i] = S.Rr(l)[i];
+        D.Sbar[l][lo[l] + i] = S.Sb(l)[i];
       }
       if (l <= 7) {
-        D.u[l][lo[l] + i] = S.uu[l][i];
-        D.ra[l][lo[l] + i] = S.ra[l][i];
-        D.rb[l][lo[l] + i] = S.rb[l][i];
+        D.u[l][lo[l] + i] = S.uu(l)[i];
+        D.ra[l][lo[l] + i] = S.ra(l)[i];
+        D.rb[l][lo[l] + i] = S.rb(l)[i];
       }
     }
   }
-  if (tid < nroots) D.vacc[j0 + tid] = vacc_acc;
+  for (int i = tid; i < nroots; i += BLOCK) D.vacc[j0 + i] = vacc[i];
 }
 
 // Global-memory arrays addressed through a per-workgroup pointer table kept
@@ -395,11 +437,11 @@ __shared__ int g_sub[2][9];
 template <class T, int SLOT>
 struct TabArr {
   int l;
-  __device__ T &operator[](int i) const { return reinterpret_cast<T *>(g_ptab[SLOT][l])[i]; }
+  __device__ __forceinline__ T &operator[](int i) const { return reinterpret_cast<T *>(g_ptab[SLOT][l])[i]; }
 };
 
 template <class T, int BLOCK>
-__device__ inline void seg_in_global(const ItemDesc<T> &D, int j0, int nroots, const int lo[9],
+__device__ __forceinline__ void seg_in_global(const ItemDesc<T> &D, int j0, int nroots, const int lo[9],
                                      const int cnt[9], const IterK *__restrict__ ks,
                                      int n_iters, int variant, int rm_mode, double eps) {
   if (threadIdx.x < 9) {
@@ -417,27 +459,32 @@ __device__ inline void seg_in_global(const ItemDesc<T> &D, int j0, int nroots, c
   }
   __syncthreads();
   struct SubT {
-    TabArr<T, 0> sg[9];
-    TabArr<T, 1> Rr[9];
-    TabArr<T, 2> Sb[9];
-    TabArr<T, 3> uu[9];
-    TabArr<T, 4> ra[9];
-    TabArr<T, 5> rb[9];
-    TabArr<const int32_t, 6> par[9];
-    TabArr<const int32_t, 7> cbl[9];
-    int par_sub[9], cb_sub[9], cnt[9];
+    int cnt[9];
+    __device__ __forceinline__ TabArr<T, 0> sg(int l) const { return {l}; }
+    __device__ __forceinline__ TabArr<T, 1> Rr(int l) const { return {l}; }
+    __device__ __forceinline__ TabArr<T, 2> Sb(int l) const { return {l}; }
+    __device__ __forceinline__ TabArr<T, 3> uu(int l) const { return {l}; }
+    __device__ __forceinline__ TabArr<T, 4> ra(int l) const { return {l}; }
+    __device__ __forceinline__ TabArr<T, 5> rb(int l) const { return {l}; }
+    __device__ __forceinline__ TabArr<const int32_t, 6> par(int l) const { return {l}; }
+    __device__ __forceinline__ TabArr<const int32_t, 7> cbl(int l) const { return {l}; }
+    __device__ __forceinline__ int par_sub(int l) const { return g_sub[0][l]; }
+    __device__ __forceinline__ int cb_sub(int l) const { return g_sub[1][l]; }
+    // Segments that run in global memory hold one root (the plan packs
+    // several roots only into segments that fit in LDS); that root's sum is
+    // kept in a register of thread 0, which updates it.
+    double *vacc_g;
+    __device__ __forceinline__ void vacc_add(int h, double v, double &reg) const {
+      if (h == 0) reg += v;
+      else vacc_g[h] += v;
+    }
   } X;
 #pragma unroll
-  for (int l = 0; l <= 8; ++l) {
-    X.sg[l].l = X.Rr[l].l = X.Sb[l].l = X.uu[l].l = X.ra[l].l = X.rb[l].l = l;
-    X.par[l].l = X.cbl[l].l = l;
-    X.par_sub[l] = g_sub[0][l];
-    X.cb_sub[l] = g_sub[1][l];
-    X.cnt[l] = cnt[l];
-  }
-  double vacc_acc = threadIdx.x < nroots ? D.vacc[j0 + threadIdx.x] : 0.0;
-  subtree_iterations<T>(X, ks, n_iters, variant, rm_mode, eps, vacc_acc);
-  if (threadIdx.x < nroots) D.vacc[j0 + threadIdx.x] = vacc_acc;
+  for (int l = 0; l <= 8; ++l) X.cnt[l] = cnt[l];
+  X.vacc_g = D.vacc + j0;
+  double vacc_reg = threadIdx.x == 0 ? D.vacc[j0] : 0.0;
+  subtree_iterations<T>(X, ks, n_iters, variant, rm_mode, eps, vacc_reg);
+  if (threadIdx.x == 0) D.vacc[j0] = vacc_reg;
 }
 
 // One workgroup per segment; the segment runs in LDS when its state fits in
