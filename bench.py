@@ -29,8 +29,8 @@ METRIC = "CFR node-updates/s at 1 GPU; secs to exploitability 1e-3, warm-start v
 # plain-copy calibration (profiles/k_cfr_seg_two_round_seed1.md).  Valid only
 # while the kernel source is unchanged.
 TRAFFIC = {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
-           "sha256": "16fb5a51500e640915b88842d39d7bc2c57124c5aebbb58c19f469bc39f8126d",
-           "bytes_per_launch": 4.38e6}
+           "sha256": "3d61e3c8630a33e8b5152bc8be7c4d7ff42bdc0c6cc21da5b4dd3fdf34ca4ac8",
+           "bytes_per_launch": 4.53e6}
 
 
 def counted_traffic(args):

@@ -202,6 +202,11 @@ struct Seg {
 };
 
 extern __shared__ __align__(16) unsigned char g_lds[];
+// per level of the segment in LDS (set at load): largest sibling group, and
+// whether the up sweep runs one lane per child in chunks (1) or one lane per
+// parent (0)
+__shared__ int g_kmax[9];
+__shared__ int g_chunked[9];
 
 // Byte layout of one segment's state in LDS (shared by host sizing and
 // device carving).  Level l occupies one block starting at base[l]: its T
@@ -209,13 +214,18 @@ extern __shared__ __align__(16) unsigned char g_lds[];
 // u (slot 0), sigma, R, Sbar (slots 1-3, levels 1..8), reachA, reachB
 // (slots 4-5, levels 0..7; level 8 has only slots 0-3) -- then the 16-bit
 // segment-local parent (levels 1..8) and child_begin (levels 0..7) indices.
-// The roots' utility sums (double) follow the last level.
+// Levels 1..8 end with their chunk starts (16-bit, chunk_cap(n_l) entries):
+// the up sweep hands children to lanes in chunks of at most 64 that never
+// split a sibling group.  The roots' utility sums (double) follow the last
+// level.
 // Every address is base + slot * stride, so a kernel keeps two scalars per
 // level instead of one offset per array.
 enum { F_U = 0, F_SG = 1, F_R = 2, F_SB = 3, F_RA = 4, F_RB = 5 };
 
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 __host__ __device__ inline uint32_t lds_tslots(int l) { return l == 8 ? 4u : 6u; }
+// capacity of a level's chunk-start array: chunks hold at least 32 children
+__host__ __device__ inline uint32_t chunk_cap(int n) { return (uint32_t)(n + 31) / 32u + 2u; }
 
 struct LdsLayout {
   uint32_t base[9], stride[9];
@@ -232,6 +242,7 @@ __host__ __device__ inline LdsLayout lds_layout(const int cnt[9], uint32_t tsize
     p += lds_tslots(l) * L.stride[l];
     if (l >= 1) p += align16((uint32_t)cnt[l] * 2u);
     if (l <= 7) p += align16((uint32_t)(cnt[l] + 1) * 2u);
+    if (l >= 1) p += align16(chunk_cap(cnt[l]) * 2u);
   }
   L.vacc = p;
   p += align16((uint32_t)cnt[0] * 8u);
@@ -280,6 +291,11 @@ struct SubLds {
     return {opaque(base[l]) + lds_tslots(l) * opaque(stride[l]) +
             (l >= 1 ? align16((uint32_t)cnt[l] * 2u) : 0u)};
   }
+  __device__ __forceinline__ LdsArr<uint16_t> chk(int l) const {
+    return {opaque(base[l]) + lds_tslots(l) * opaque(stride[l]) +
+            align16((uint32_t)cnt[l] * 2u) + (l <= 7 ? align16((uint32_t)(cnt[l] + 1) * 2u) : 0u)};
+  }
+  static constexpr bool chunked() { return true; }
   __device__ __forceinline__ int par_sub(int) const { return 0; }
   __device__ __forceinline__ int cb_sub(int) const { return 0; }
 };
@@ -312,7 +328,9 @@ __device__ __forceinline__ double update_parent(const AS &sg, const AR &Rr, cons
     Rr[q] = Rs;
     sum += rm_mode == PASUR_RM_FLOOR ? fmax((double)Rs, eps) : fmax((double)Rs, 0.0);
   }
-  const double inv_k = 1.0 / (double)(e - b);
+  // sum is positive unless no regret is (RM+ or a zero floor); 1/k is then
+  // computed on that branch only
+  const double inv_k = sum > 0.0 ? 0.0 : 1.0 / (double)(e - b);
   for (int q = b; q < e; ++q) {
     const double x = rm_mode == PASUR_RM_FLOOR ? fmax((double)Rr[q], eps) : fmax((double)Rr[q], 0.0);
     const double s_new = sum > 0.0 ? x / sum : inv_k;
@@ -324,54 +342,216 @@ __device__ __forceinline__ double update_parent(const AS &sg, const AR &Rr, cons
   return uh;
 }
 
-// All iterations of one segment (FindReachProbability then FindUtility per
-// iteration, as in k_down / k_up): every level is one phase of the whole
-// workgroup, one thread per node (down) or per parent (up), with a barrier
-// between levels.
-template <class T, class SubT>
-__device__ __forceinline__ void subtree_iterations(const SubT &S, const IterK *__restrict__ ks,
-                                                   int n_iters, int variant, int rm_mode,
-                                                   double eps, double &vacc_reg) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int it = 0; it < n_iters; ++it) {
-    const IterK k = ks[it];
-#pragma unroll
-    for (int l = 1; l <= 7; ++l) {
-      const int mover = (l - 1) & 1;
-      int t0 = tid;
-      asm volatile("" : "+v"(t0));  // per-lane start stays inside the phase (see opaque)
-      for (int q = t0; q < S.cnt[l]; q += nt) {
-        const int h = (int)S.par(l)[q] - S.par_sub(l);
-        double a = (double)S.ra(l - 1)[h];
-        double b = (double)S.rb(l - 1)[h];
-        if (mover == 0) a *= (double)S.sg(l)[q];
-        else b *= (double)S.sg(l)[q];
-        S.ra(l)[q] = (T)a;
-        S.rb(l)[q] = (T)b;
-      }
-      __syncthreads();
+// FindUtility for the parents h0, h0+nt, ... of level l-1 (children on level l).
+template <class T, int L, class SubT>
+__device__ __forceinline__ void up_one(const SubT &S, const IterK &k, int variant, int rm_mode,
+                                       double eps, double &vacc_reg) {
+  const int mover = (L - 1) & 1;
+  int t0 = threadIdx.x;
+  asm volatile("" : "+v"(t0));  // per-lane start stays inside the phase (see opaque)
+  for (int h = t0; h < S.cnt[L - 1]; h += blockDim.x) {
+    const int b = (int)S.cbl(L - 1)[h] - S.cb_sub(L - 1);
+    const int e = (int)S.cbl(L - 1)[h + 1] - S.cb_sub(L - 1);
+    const double opp = mover == 0 ? (double)S.rb(L - 1)[h] : (double)S.ra(L - 1)[h];
+    const double own = mover == 0 ? (double)S.ra(L - 1)[h] : (double)S.rb(L - 1)[h];
+    const double uh = update_parent<T>(S.sg(L), S.Rr(L), S.Sb(L), S.uu(L), b, e, mover, opp,
+                                       own, k, variant, rm_mode, eps);
+    S.uu(L - 1)[h] = (T)uh;
+    if (L == 1) S.vacc_add(h, uh, vacc_reg);
+  }
+}
+
+// Largest sibling group the chunked up sweep handles (chunks of at most 64
+// children then start at least every 32 children).
+constexpr int kMaxChunkGroup = 33;
+
+// The value of lane i-1 (lane_from_below) or lane i+1 (lane_from_above) of
+// the wave, by a DPP whole-wave shift; lane 0 (resp. 63) receives 0.
+__device__ __forceinline__ double lane_from_below(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x138, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_from_above(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x130, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of v over each sibling group of the wave (the group's lanes are
+// consecutive; pos = index within the group, k = group size), added in
+// sibling order from 0.0 exactly as the sequential loop does, and returned
+// on every lane of the group.  Each step moves values one lane; the steps
+// stop once no lane of the wave needs another (kw = largest group of the
+// wave).  Must run with all lanes of the wave active.
+__device__ __forceinline__ double group_sum(double v, int pos, int k, int kw) {
+  double acc = 0.0 + v;
+  for (int s = 1; s < kw; ++s) {
+    const double prev = lane_from_below(acc);
+    acc = pos == s ? prev + v : acc;
+  }
+  for (int s = 1; s < kw; ++s) {
+    const double next = lane_from_above(acc);
+    acc = k - 1 - pos == s ? next : acc;
+  }
+  return acc;
+}
+
+// Largest value of x over the wave (x >= 0), as a wave-uniform scalar.
+__device__ __forceinline__ int wave_max(int x) {
+  int m = x;
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x111, 0xF, 0xF, false));  // row_shr:1
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x112, 0xF, 0xF, false));  // row_shr:2
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x114, 0xF, 0xF, false));  // row_shr:4
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x118, 0xF, 0xF, false));  // row_shr:8
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x142, 0xF, 0xF, false));  // row_bcast:15
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x143, 0xF, 0xF, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(m, 63);
+}
+
+// FindUtility on level L, one lane per child: wave w takes chunks w, w+nw,
+// ... of the level's children (a chunk never splits a sibling group); the
+// two per-parent sums (sigma*u, and the regret-matching denominator) are
+// group_sum scans, every other operation is per child and in k_up's order.
+// The last child of each group writes the parent's utility.
+template <class T, int L, class SubT>
+__device__ __forceinline__ void up_chunked(const SubT &S, const IterK &ik, int variant,
+                                           int rm_mode, double eps, double &vacc_reg) {
+  const int mover = (L - 1) & 1;
+  const double sgn = mover == 0 ? 1.0 : -1.0;
+  const int lane = (int)(threadIdx.x & 63), nw = (int)(blockDim.x >> 6);
+  int w = (int)(threadIdx.x >> 6);
+  asm volatile("" : "+v"(w));  // (see opaque)
+  const int n = S.cnt[L], cap = (int)chunk_cap(n);
+  for (int c = w; c + 1 < cap; c += nw) {
+    const int c0 = S.chk(L)[c], c1 = S.chk(L)[c + 1];
+    if (c0 >= n) break;
+    if (c1 <= c0) continue;
+    const bool valid = c0 + lane < c1;
+    const int q = valid ? c0 + lane : c1 - 1;
+    const int h = (int)S.par(L)[q] - S.par_sub(L);
+    const T sq = S.sg(L)[q], uq = S.uu(L)[q], rq = S.Rr(L)[q], bq = S.Sb(L)[q];
+    const int b = (int)S.cbl(L - 1)[h] - S.cb_sub(L - 1);
+    const int e = (int)S.cbl(L - 1)[h + 1] - S.cb_sub(L - 1);
+    const double opp = mover == 0 ? (double)S.rb(L - 1)[h] : (double)S.ra(L - 1)[h];
+    const double own = mover == 0 ? (double)S.ra(L - 1)[h] : (double)S.rb(L - 1)[h];
+    const int pos = q - b, k = e - b;
+    const int kw = wave_max(k);
+    const double uh = group_sum((double)sq * (double)uq, pos, k, kw);
+    const double r = sgn * opp * ((double)uq - uh);
+    double Rq = (double)rq;
+    if (variant == PASUR_DCFR) {
+      const double d = Rq > 0.0 ? ik.dpos : ik.dneg;
+      Rq = d * Rq + r;
+    } else if (variant == PASUR_CFR_PLUS) {
+      Rq = Rq + r;
+      if (Rq < 0.0) Rq = 0.0;
+    } else {
+      Rq = Rq + r;
     }
-#pragma unroll
-    for (int l = 8; l >= 1; --l) {
-      const int mover = (l - 1) & 1;
-      int t0 = tid;
-      asm volatile("" : "+v"(t0));
-      for (int h = t0; h < S.cnt[l - 1]; h += nt) {
-        const int b = (int)S.cbl(l - 1)[h] - S.cb_sub(l - 1);
-        const int e = (int)S.cbl(l - 1)[h + 1] - S.cb_sub(l - 1);
-        const double opp = mover == 0 ? (double)S.rb(l - 1)[h] : (double)S.ra(l - 1)[h];
-        const double own = mover == 0 ? (double)S.ra(l - 1)[h] : (double)S.rb(l - 1)[h];
-        const double uh = update_parent<T>(S.sg(l), S.Rr(l), S.Sb(l), S.uu(l), b, e, mover,
-                                           opp, own, k, variant, rm_mode, eps);
-        S.uu(l - 1)[h] = (T)uh;
-        if (l == 1) S.vacc_add(h, uh, vacc_reg);
+    const T Rs = (T)Rq;
+    const double x = rm_mode == PASUR_RM_FLOOR ? fmax((double)Rs, eps) : fmax((double)Rs, 0.0);
+    const double sum = group_sum(x, pos, k, kw);
+    double add = own * (double)sq;
+    if (variant == PASUR_CFR_PLUS) add *= ik.avg_t;
+    if (valid) {
+      const double s_new = sum > 0.0 ? x / sum : 1.0 / (double)k;
+      S.Rr(L)[q] = Rs;
+      S.Sb(L)[q] = (T)(ik.avg_w * (double)bq + add);
+      S.sg(L)[q] = (T)s_new;
+      if (pos == k - 1) {
+        S.uu(L - 1)[h] = (T)uh;
+        if (L == 1) S.vacc_add(h, uh, vacc_reg);
       }
-      __syncthreads();
     }
   }
 }
 
-template <class T, int BLOCK>
+// One level of the up sweep, then the workgroup barrier.
+template <class T, int L, class SubT>
+__device__ __forceinline__ void up_phase(const SubT &S, const IterK &k, int variant, int rm_mode,
+                                         double eps, double &vacc_reg) {
+  if constexpr (SubT::chunked()) {
+    if (g_chunked[L])
+      up_chunked<T, L>(S, k, variant, rm_mode, eps, vacc_reg);
+    else
+      up_one<T, L>(S, k, variant, rm_mode, eps, vacc_reg);
+  } else {
+    up_one<T, L>(S, k, variant, rm_mode, eps, vacc_reg);
+  }
+  __syncthreads();
+}
+
+// All iterations of one segment (FindReachProbability then FindUtility per
+// iteration, as in k_down / k_up): every level is one phase of the whole
+// workgroup, one thread per node (down) or per parent (up), with a barrier
+// between levels.
+//
+// PAPER fixes the paper's variant (DCFR with the regret floor) at compile time,
+// which removes the per-child variant tests from the loop.
+template <class T, bool PAPER, class SubT>
+__device__ __forceinline__ void subtree_iterations(const SubT &S, const IterK *__restrict__ ks,
+                                                   int n_iters, int variant, int rm_mode,
+                                                   double eps, double &vacc_reg) {
+  if (PAPER) {
+    variant = PASUR_DCFR;
+    rm_mode = PASUR_RM_FLOOR;
+  }
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int it = 0; it < n_iters; ++it) {
+    const IterK k = ks[it];
+    // FindReachProbability, two levels per phase: a node of the second level
+    // l+1 starts from its grandparent's reaches and applies its parent's and
+    // its own action probability, rounding to T after each level exactly as
+    // the level-by-level form does (the movers alternate, so each level
+    // scales one of the two reaches).
+#pragma unroll
+    for (int l = 1; l <= 7; l += 2) {
+      const int l2 = l < 7 ? l + 1 : 0;  // second level of the phase (0: none)
+      const int n1 = S.cnt[l], n2 = l2 ? S.cnt[l2] : 0;
+      int t0 = tid;
+      asm volatile("" : "+v"(t0));  // per-lane start stays inside the phase (see opaque)
+      for (int i = t0; i < n1 + n2; i += nt) {
+        if (i < n1) {
+          const int h = (int)S.par(l)[i] - S.par_sub(l);
+          double a = (double)S.ra(l - 1)[h];
+          double b = (double)S.rb(l - 1)[h];
+          if (((l - 1) & 1) == 0) a *= (double)S.sg(l)[i];
+          else b *= (double)S.sg(l)[i];
+          S.ra(l)[i] = (T)a;
+          S.rb(l)[i] = (T)b;
+        } else if (l2) {
+          const int q = i - n1;
+          const int h = (int)S.par(l2)[q] - S.par_sub(l2);
+          const int g = (int)S.par(l)[h] - S.par_sub(l);
+          double a = (double)S.ra(l - 1)[g];
+          double b = (double)S.rb(l - 1)[g];
+          if (((l - 1) & 1) == 0) a *= (double)S.sg(l)[h];
+          else b *= (double)S.sg(l)[h];
+          a = (double)(T)a;
+          b = (double)(T)b;
+          if (((l2 - 1) & 1) == 0) a *= (double)S.sg(l2)[q];
+          else b *= (double)S.sg(l2)[q];
+          S.ra(l2)[q] = (T)a;
+          S.rb(l2)[q] = (T)b;
+        }
+      }
+      __syncthreads();
+    }
+    up_phase<T, 8>(S, k, variant, rm_mode, eps, vacc_reg);
+    up_phase<T, 7>(S, k, variant, rm_mode, eps, vacc_reg);
+    up_phase<T, 6>(S, k, variant, rm_mode, eps, vacc_reg);
+    up_phase<T, 5>(S, k, variant, rm_mode, eps, vacc_reg);
+    up_phase<T, 4>(S, k, variant, rm_mode, eps, vacc_reg);
+    up_phase<T, 3>(S, k, variant, rm_mode, eps, vacc_reg);
+    up_phase<T, 2>(S, k, variant, rm_mode, eps, vacc_reg);
+    up_phase<T, 1>(S, k, variant, rm_mode, eps, vacc_reg);
+  }
+}
+
+template <class T, int BLOCK, bool PAPER>
 __device__ __forceinline__ void seg_in_lds(const ItemDesc<T> &D, int j0, int nroots, const int lo[9],
                                   const int cnt[9], const LdsLayout &L,
                                   const IterK *__restrict__ ks, int n_iters, int variant,
@@ -407,9 +587,42 @@ __device__ __forceinline__ void seg_in_lds(const ItemDesc<T> &D, int j0, int nro
         S.cbl(l)[i] = (uint16_t)(D.cb[l][lo[l] + i] - lo[l + 1]);
   }
   for (int i = tid; i < nroots; i += BLOCK) vacc[i] = D.vacc[j0 + i];
+  if (tid <= 8) g_kmax[tid] = 0;
+  __syncthreads();
+  // largest sibling group per level, then the chunk starts of the up sweep:
+  // chunk c begins at the first sibling of child c*stride, stride = 64 - (kmax - 1),
+  // so a chunk holds at most 64 children; unused entries hold n
+#pragma unroll
+  for (int l = 1; l <= 8; ++l) {
+    int km = 0;
+    for (int h = tid; h < cnt[l - 1]; h += BLOCK) {
+      const int k = (int)S.cbl(l - 1)[h + 1] - (int)S.cbl(l - 1)[h];
+      km = k > km ? k : km;
+    }
+    if (km > 0) atomicMax(&g_kmax[l], km);
+  }
+  __syncthreads();
+  // Lanes per child pay off where siblings groups of 3 or more make the
+  // per-parent loops diverge, unless chunking needs more passes than one lane
+  // per parent (measured on the two-round and full-game trees).
+#pragma unroll
+  for (int l = 1; l <= 8; ++l) {
+    const int km = g_kmax[l];
+    const int stride = 64 - ((km > 1 ? km : 1) - 1);
+    const int passes_child = ((cnt[l] + stride - 1) / stride + BLOCK / 64 - 1) / (BLOCK / 64);
+    const int passes_parent = (cnt[l - 1] + BLOCK - 1) / BLOCK;
+    const bool chunked = km >= 3 && km <= kMaxChunkGroup && passes_child <= passes_parent;
+    if (tid == 0) g_chunked[l] = chunked ? 1 : 0;
+    if (!chunked) continue;
+    const int cap = (int)chunk_cap(cnt[l]);
+    for (int c = tid; c < cap; c += BLOCK) {
+      const int x = c * stride;
+      S.chk(l)[c] = (uint16_t)(x < cnt[l] ? (int)S.cbl(l - 1)[S.par(l)[x]] : cnt[l]);
+    }
+  }
   __syncthreads();
   double unused = 0.0;
-  subtree_iterations<T>(S, ks, n_iters, variant, rm_mode, eps, unused);
+  subtree_iterations<T, PAPER>(S, ks, n_iters, variant, rm_mode, eps, unused);
   // write the state back
 #pragma unroll
   for (int l = 0; l <= 8; ++l) {
@@ -440,7 +653,7 @@ struct TabArr {
   __device__ __forceinline__ T &operator[](int i) const { return reinterpret_cast<T *>(g_ptab[SLOT][l])[i]; }
 };
 
-template <class T, int BLOCK>
+template <class T, int BLOCK, bool PAPER>
 __device__ __forceinline__ void seg_in_global(const ItemDesc<T> &D, int j0, int nroots, const int lo[9],
                                      const int cnt[9], const IterK *__restrict__ ks,
                                      int n_iters, int variant, int rm_mode, double eps) {
@@ -470,6 +683,7 @@ __device__ __forceinline__ void seg_in_global(const ItemDesc<T> &D, int j0, int 
     __device__ __forceinline__ TabArr<const int32_t, 7> cbl(int l) const { return {l}; }
     __device__ __forceinline__ int par_sub(int l) const { return g_sub[0][l]; }
     __device__ __forceinline__ int cb_sub(int l) const { return g_sub[1][l]; }
+    static constexpr bool chunked() { return false; }
     // Segments that run in global memory hold one root (the plan packs
     // several roots only into segments that fit in LDS); that root's sum is
     // kept in a register of thread 0, which updates it.
@@ -483,13 +697,13 @@ __device__ __forceinline__ void seg_in_global(const ItemDesc<T> &D, int j0, int 
   for (int l = 0; l <= 8; ++l) X.cnt[l] = cnt[l];
   X.vacc_g = D.vacc + j0;
   double vacc_reg = threadIdx.x == 0 ? D.vacc[j0] : 0.0;
-  subtree_iterations<T>(X, ks, n_iters, variant, rm_mode, eps, vacc_reg);
+  subtree_iterations<T, PAPER>(X, ks, n_iters, variant, rm_mode, eps, vacc_reg);
   if (threadIdx.x == 0) D.vacc[j0] = vacc_reg;
 }
 
 // One workgroup per segment; the segment runs in LDS when its state fits in
 // the launch's dynamic LDS (lds_bytes), otherwise in global memory.
-template <class T, int BLOCK>
+template <class T, int BLOCK, bool PAPER>
 __global__ void __launch_bounds__(BLOCK)
     k_cfr_seg(const ItemDesc<T> *__restrict__ items, const Seg *__restrict__ segs,
               const IterK *__restrict__ ks, int n_iters, int variant, int rm_mode, double eps,
@@ -506,9 +720,9 @@ __global__ void __launch_bounds__(BLOCK)
   }
   const LdsLayout L = lds_layout(cnt, sizeof(T));
   if (L.bytes <= lds_bytes && mx < 65535)
-    seg_in_lds<T, BLOCK>(D, sg.j0, sg.j1 - sg.j0, lo, cnt, L, ks, n_iters, variant, rm_mode, eps);
+    seg_in_lds<T, BLOCK, PAPER>(D, sg.j0, sg.j1 - sg.j0, lo, cnt, L, ks, n_iters, variant, rm_mode, eps);
   else
-    seg_in_global<T, BLOCK>(D, sg.j0, sg.j1 - sg.j0, lo, cnt, ks, n_iters, variant, rm_mode,
+    seg_in_global<T, BLOCK, PAPER>(D, sg.j0, sg.j1 - sg.j0, lo, cnt, ks, n_iters, variant, rm_mode,
                             eps);
 }
 
@@ -642,12 +856,17 @@ int iterate_t(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_par
 
 
 constexpr uint32_t kLdsPerWorkgroup = 160 * 1024;
-// static LDS of the global-memory path (pointer table and index offsets)
-constexpr uint32_t kStaticLds = 8 * 9 * sizeof(void *) + 2 * 9 * sizeof(int) + 64;
+// static LDS: the global-memory path's pointer table and index offsets, the
+// per-level sibling-group statistics
+constexpr uint32_t kStaticLds = 8 * 9 * sizeof(void *) + 4 * 9 * sizeof(int) + 64;
+
+inline bool paper_variant(int variant, int rm_mode) {
+  return variant == PASUR_DCFR && rm_mode == PASUR_RM_FLOOR;
+}
 
 template <class T, int BLOCK>
-void *seg_kernel() {
-  return (void *)k_cfr_seg<T, BLOCK>;
+void *seg_kernel(bool paper) {
+  return paper ? (void *)k_cfr_seg<T, BLOCK, true> : (void *)k_cfr_seg<T, BLOCK, false>;
 }
 
 }  // namespace
@@ -771,9 +990,10 @@ int plan_build(pasur_plan *pl, const pasur_fgt *const *fgts, const pasur_cfr_sta
   PASUR_TRY_HIP(hipMemcpyAsync(pl->d_ks, ks.data(), sizeof(IterK) * ks.size(),
                                hipMemcpyHostToDevice, s));
   PASUR_TRY_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
-  void *kern = pl->block == 256   ? seg_kernel<T, 256>()
-               : pl->block == 512 ? seg_kernel<T, 512>()
-                                  : seg_kernel<T, 1024>();
+  const bool paper = paper_variant(p->variant, p->rm_mode);
+  void *kern = pl->block == 256   ? seg_kernel<T, 256>(paper)
+               : pl->block == 512 ? seg_kernel<T, 512>(paper)
+                                  : seg_kernel<T, 1024>(paper);
   PASUR_TRY_HIP(hipFuncSetAttribute((const void *)kern,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)pl->lds_bytes));
@@ -782,7 +1002,9 @@ int plan_build(pasur_plan *pl, const pasur_fgt *const *fgts, const pasur_cfr_sta
 
 template <class T, int BLOCK>
 void plan_launch(const pasur_plan *pl, int64_t t0, int n_iters, hipStream_t s) {
-  k_cfr_seg<T, BLOCK><<<(unsigned)pl->n_segs, BLOCK, pl->lds_bytes, s>>>(
+  auto kern = paper_variant(pl->variant, pl->rm_mode) ? k_cfr_seg<T, BLOCK, true>
+                                                      : k_cfr_seg<T, BLOCK, false>;
+  kern<<<(unsigned)pl->n_segs, BLOCK, pl->lds_bytes, s>>>(
       (const ItemDesc<T> *)pl->d_items, pl->d_segs, pl->d_ks + (t0 - pl->t_first), n_iters,
       pl->variant, pl->rm_mode, pl->eps, pl->lds_bytes);
 }
