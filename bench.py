@@ -182,9 +182,11 @@ def bench_batched(args):
 
 
 def bench_full(args):
-    """All six rounds of seeded deal --seed from the initial deal (survey
-    config 3): build and unfold every round, then DCFR round by round from
-    round 6 backward (--iters per round, default 1000), with exploitability."""
+    """All six rounds of seeded deal --full-seed from the initial deal: build
+    and unfold every round, then DCFR round by round from round 6 backward
+    (--iters per round, default 1000), with exploitability.  The default
+    deal, seed 40, is the largest full game among seeds 1-64 (8.5e8 FGT
+    nodes; the paper reports about 1e9 per deck on average)."""
     import torch
     import paper_2508_06559_amd as pa
     import synth
@@ -192,7 +194,7 @@ def bench_full(args):
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
     iters = 1000 if args.iters == 2000 else args.iters
-    deck, roots = synth.full_game_root(args.seed)
+    deck, roots = synth.full_game_root(args.full_seed)
     params = pa.paper_params(block=args.block)
     times = []
     for k in range(args.warmup + args.steps):
@@ -218,10 +220,60 @@ def bench_full(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"full game of seeded deal {args.seed}: 6 rounds, "
+           "config": {"workload": f"full game of seeded deal {args.full_seed}: 6 rounds, "
                                   f"{sum(sum(n) for n in sizes)} nodes, {iters} DCFR iterations per round",
                       "state": args.state, "round_sizes": [sum(n) for n in sizes],
                       "build_seconds": times[-1][1], "exploitability_points": ex, "game_value": V0}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_paper_scale(args):
+    """Full games of --deals seeded deals (seeds 1..N) solved together: every
+    round of every game built and unfolded, then one persistent launch per
+    round over all games (a batched plan), 1000 DCFR iterations per round.
+    With the default 32 deals this is about 10^9 FGT nodes, the paper's
+    average per deck, resident in HBM at once."""
+    import torch
+    import paper_2508_06559_amd as pa
+    import synth
+
+    dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
+    iters = 1000 if args.iters == 2000 else args.iters
+    probs = [synth.full_game_root(s) for s in range(1, args.deals + 1)]
+    free0, total = torch.cuda.mem_get_info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = pa.BatchSolver(probs, 0, iters, dtype=dtype)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    used = free0 - torch.cuda.mem_get_info()[0]
+    per_deal = [sum(sum(rr.fgt.n) for rr in sv.rounds) for sv in b.deals]
+    nodes = sum(per_deal)
+    edges = b.edges()
+    log(f"[bench] paper scale: {args.deals} full games, {nodes} nodes, built in {build_s:.1f} s, "
+        f"{used / 2**30:.1f} GiB of HBM")
+    for w in range(args.warmup):
+        b.solve()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        b.solve()
+        torch.cuda.synchronize()
+        log(f"[bench] step {k + 1}/{args.steps} done ({time.perf_counter() - t0:.1f} s)")
+    el = time.perf_counter() - t0
+    ex = [float(((x[0] - x[1]) / 2).max().item()) for x in b.exploitability()[:2]]
+    b.free()
+    out = {"metric": METRIC, "value": edges * iters * args.steps / el, "unit": "node-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"paper scale: full games of {args.deals} seeded deals (seeds 1-"
+                                  f"{args.deals}) solved as one batch, {nodes} FGT nodes, {iters} DCFR "
+                                  f"iterations per round",
+                      "state": args.state, "nodes": nodes, "nodes_per_deal": per_deal,
+                      "hbm_bytes_in_use": used,
+                      "build_seconds": build_s, "exploitability_points_first_deals": ex}}
     print(json.dumps(out), flush=True)
 
 
@@ -252,10 +304,10 @@ def bench_warm(args):
     b.record()
     b.synchronize()
     train_ms = a.elapsed_time(b)
-    per_row = 2 * (160 * 256 + 256 * 256 + 256 * 2)
+    per_row = 2 * (learn.N_IN * 256 + 256 * 256 + 256 * 2)
     train_tflops = 3 * per_row * rows / (train_ms * 1e-3) / 1e12
     hist += learn.train(model, units, args.epochs - 1, seed=0, log=log)
-    big = torch.zeros((1 << 20, 160), dtype=torch.int16, device="cuda")
+    big = torch.zeros((1 << 20, learn.N_IN), dtype=torch.int16, device="cuda")
     model.forward(big, big.shape[0])
     a.record()
     for _ in range(5):
@@ -266,11 +318,17 @@ def bench_warm(args):
     del big
     grid = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
     test = [synth.two_round_root(s) for s in range(20000, 20000 + args.test_deals)]
+    levels = [int(x) for x in args.warm_levels.split(",")]
     res = {"plain": [], "warm": []}
+    res.update({f"warm_levels_{L}": [] for L in levels[1:]})
     ex0 = {"uniform": [], "network": []}
     for k, (deck, roots) in enumerate(test):
         res["plain"].append(learn.seconds_to_target(deck, 4, roots, 1e-3, grid, None))
-        res["warm"].append(learn.seconds_to_target(deck, 4, roots, 1e-3, grid, model))
+        res["warm"].append(learn.seconds_to_target(deck, 4, roots, 1e-3, grid, model,
+                                                   learn.WarmParams(max_level=levels[0])))
+        for L in levels[1:]:
+            res[f"warm_levels_{L}"].append(learn.seconds_to_target(
+                deck, 4, roots, 1e-3, grid, model, learn.WarmParams(max_level=L)))
         if k < 32:
             ex0["uniform"].append(learn.initial_profile_exploitability(deck, roots, None))
             ex0["network"].append(learn.initial_profile_exploitability(deck, roots, model))
@@ -291,11 +349,12 @@ def bench_warm(args):
         "n_gpus": 1, "steps": len(test), "warmup": 0, "ms_per_step": sw["median_seconds"] * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"learned warm start: MLP 160-256-256-2 trained on DCFR solutions of "
+        "config": {"workload": f"learned warm start: MLP 192-256-256-2 trained on DCFR solutions of "
                                f"{len(train)} seeded two-round deals ({rows} rows, {args.epochs} epochs); "
                                f"seconds to exploitability 1e-3 on {len(test)} held-out deals, "
                                f"iteration grid {list(grid)}",
-                   "plain": sp, "warm": sw,
+                   "plain": sp, "warm": sw, "warm_levels": levels[0],
+                   "other_warm_levels": {k: summ(v) for k, v in res.items() if k.startswith("warm_levels_")},
                    "speedup_median_seconds": sp["median_seconds"] / sw["median_seconds"],
                    "initial_profile_exploitability_median": {k: float(np.median(v)) for k, v in ex0.items()},
                    "final_train_loss": hist[-1], "data_seconds": data_s},
@@ -318,13 +377,18 @@ def main():
     ap.add_argument("--sched", choices=["root", "level", "root-global"], default="root")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game", "copy"],
+    ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game",
+                                           "paper-scale", "copy"],
                     default="two-round",
                     help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
     ap.add_argument("--train-deals", type=int, default=512)
     ap.add_argument("--test-deals", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--deals", type=int, default=32, help="paper-scale: number of full games")
+    ap.add_argument("--full-seed", type=int, default=40, help="full-game: the seeded deal")
+    ap.add_argument("--warm-levels", default="8",
+                    help="warm-start: comma list of max_level values (levels 1..L predicted); the first is reported")
     ap.add_argument("--schedule-json", default=None, help="where the batched autotuner writes its schedule")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -343,6 +407,8 @@ def main():
         return bench_warm(args)
     if args.workload == "full-game":
         return bench_full(args)
+    if args.workload == "paper-scale":
+        return bench_paper_scale(args)
     if args.workload == "copy":
         # calibration for hardware byte counters: a plain device copy of a
         # known size (256 MiB read + 256 MiB written per launch, 4 launches)

@@ -243,14 +243,16 @@ int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
 
 /* ---- a13: learned warm start ------------------------------------------------
  * Not in the paper (its learned model is an XGBoost regressor on infoset
- * rows).  A 160-256-256-2 MLP: input = the child node's card state (Alex's
- * hand, Bob's hand, pool as 3 x 52 bits) and inherited score (ca/7, cb/7,
- * d/16, +1/-1/0 bonus owner); two ReLU hidden layers of 256; outputs a
+ * rows).  A 192-256-256-2 MLP: input = the child node's card state (Alex's
+ * hand, Bob's hand, pool as 3 x 52 bits), inherited score (ca/7, cb/7, d/16,
+ * +1/-1/0 bonus owner), the round's running score so far (clubs /13, last
+ * picker, points /10, Surs of each side), a one-hot of the level and zero
+ * padding (layout in pasur_edge_features); two ReLU hidden layers of 256; outputs a
  * policy logit (softmax over siblings = predicted average strategy) and a
  * node value.  Weights are row-major [in][out]; BF16 arrays are raw 16-bit
  * words.  All GEMMs run on MFMA (BF16 x BF16 -> FP32). */
 typedef struct {
-  const uint16_t *W1; const float *b1; /* [160][256], [256] */
+  const uint16_t *W1; const float *b1; /* [192][256], [256] */
   const uint16_t *W2; const float *b2; /* [256][256], [256] */
   const uint16_t *W3; const float *b3; /* [256][2], [2] */
 } pasur_mlp_weights;
@@ -264,7 +266,7 @@ typedef struct {
 int pasur_gemm_bf16(int M, int N, int K, const uint16_t *A, int64_t sar, int64_t sac,
                     const uint16_t *B, int64_t sbr, int64_t sbc, float *Cf, uint16_t *Cb,
                     int64_t ldc, const float *bias, int relu, void *stream);
-/* Forward for M rows of X [M][160] (BF16): H1, H2 [M][256] (BF16, after
+/* Forward for M rows of X [M][192] (BF16): H1, H2 [M][256] (BF16, after
  * ReLU), Y [M][2] (FP32: logit, value). */
 int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
                       uint16_t *H1, uint16_t *H2, float *Y, void *stream);
@@ -283,9 +285,13 @@ int pasur_mlp_loss(const float *Y, const float *target_sigma, const float *targe
 /* Adam on an FP32 master array; refreshes its BF16 copy when w_bf16 != NULL. */
 int pasur_adam_step(float *w, const float *g, float *m, float *v, uint16_t *w_bf16, int64_t n,
                     float lr, float beta1, float beta2, float eps, int64_t step, void *stream);
-/* Feature rows (BF16 [n][160]) of FGT nodes of `level`: the nodes d_edges[i]
+/* Feature rows (BF16 [n][192]) of FGT nodes of `level`: the nodes d_edges[i]
  * (device) or, with d_edges NULL, all n = n[level] nodes in order.  `gt` must
- * be the game tree `fgt` was unfolded from. */
+ * be the game tree `fgt` was unfolded from.  Columns: 0..51 Alex's hand,
+ * 52..103 Bob's hand, 104..155 pool (card bits); 156..159 ca/7, cb/7, d/16,
+ * bonus owner +1/-1/0; 160..166 the GT node's running score: Acl/13, Bcl/13,
+ * last picker +1 (Alex) / -1 (Bob) / 0, Apt/10, Asr, Bpt/10, Bsr; 167+level = 1;
+ * other columns 0. */
 int pasur_edge_features(const pasur_gt *gt, const pasur_fgt *fgt, int level,
                         const int32_t *d_edges, int64_t n, uint16_t *d_X, void *stream);
 /* Training sample: decision parents (two or more children) on level-1 kept
@@ -301,6 +307,15 @@ int pasur_sample_parents(const pasur_fgt *fgt, int level, uint64_t seed, double 
  * discounts treat the warm start as earlier iterations. */
 int pasur_cfr_warm_init(const pasur_fgt *fgt, const pasur_cfr_state *st, int level,
                         const float *Y, float kappa_r, float kappa_s, void *stream);
+/* The warm start of a whole round in one call (after pasur_cfr_init): the
+ * feature rows of every node of levels 1..max_level (one launch), the MLP
+ * forward pass over all of them, and sigma / R / Sbar of those levels as in
+ * pasur_cfr_warm_init (one launch); deeper levels keep their initial state.
+ * `gt` must be the game tree `fgt` was unfolded from.  Uses stream-ordered
+ * scratch (rows x (192 + 2 x 256) BF16 + rows x 2 FP32). */
+int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt, const pasur_cfr_state *st,
+                           const pasur_mlp_weights *w, int max_level, float kappa_r,
+                           float kappa_s, void *stream);
 
 /* Training-data helpers: dst[i] = (float)src[idx[i]] (idx NULL: src[i]) for
  * a `dtype` array; dst[i] = src[i] + add for int32 offsets. */

@@ -1,7 +1,7 @@
 """FP64 reference of the warm-start MLP (test infrastructure only).
 
-A plain numpy definition of the network the HIP path trains: 160 inputs
-(three 52-card masks and four score features), two ReLU layers of 256, two
+A plain numpy definition of the network the HIP path trains: 192 inputs
+(card masks, score features, padding), two ReLU layers of 256, two
 outputs (policy logit, value); loss = per-parent cross-entropy of the
 softmax of the logits over siblings against the target strategy (averaged
 over parents) + value_weight/2 squared value error (averaged over rows).
@@ -15,6 +15,9 @@ pin the backward pass against finite differences).
 from __future__ import annotations
 
 import numpy as np
+
+
+N_IN = 192
 
 
 def bf16_round(x) -> np.ndarray:
@@ -36,7 +39,7 @@ def _q(x, on):
 
 
 def forward(W, X, bf16=True):
-    """W = (W1, b1, W2, b2, W3, b3); X [M, 160].  Returns (H1, H2, Y) with H1,
+    """W = (W1, b1, W2, b2, W3, b3); X [M, N_IN].  Returns (H1, H2, Y) with H1,
     H2 the post-ReLU activations as fed to the next layer."""
     W1, b1, W2, b2, W3, b3 = W
     Xq = _q(X, bf16)
@@ -85,7 +88,7 @@ def backward(W, X, H1, H2, dY, bf16=True):
 
 def init_weights(rng, scale=1.0):
     """He-initialised weights (FP64)."""
-    W1 = rng.normal(0, np.sqrt(2.0 / 160), (160, 256)) * scale
+    W1 = rng.normal(0, np.sqrt(2.0 / N_IN), (N_IN, 256)) * scale
     W2 = rng.normal(0, np.sqrt(2.0 / 256), (256, 256)) * scale
     W3 = rng.normal(0, np.sqrt(1.0 / 256), (256, 2)) * scale
     return [W1, np.zeros(256), W2, np.zeros(256), W3, np.zeros(2)]

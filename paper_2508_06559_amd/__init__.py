@@ -100,6 +100,7 @@ def lib():
         L.pasur_sample_parents.argtypes = [vp, i32, C.c_uint64, C.c_double, vp, vp,
                                            C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
         L.pasur_cfr_warm_init.argtypes = [vp, vp, i32, vp, C.c_float, C.c_float, vp]
+        L.pasur_warm_start_round.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, vp]
         L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
         L.pasur_shift_i32.argtypes = [vp, i64, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
@@ -425,6 +426,13 @@ def sample_parents(fgt: UnfoldedTree, level: int, seed: int, keep_prob: float, s
 def cfr_warm_init(st: CfrState, level: int, Y, kappa_r: float, kappa_s: float, stream=None):
     _check(lib().pasur_cfr_warm_init(st.fgt.h, C.byref(st.c), level, _p(Y), kappa_r, kappa_s,
                                      _stream(stream)), "pasur_cfr_warm_init")
+
+
+def warm_start_round(gt: GameTree, st: CfrState, w: MlpWeights, max_level: int, kappa_r: float,
+                     kappa_s: float, stream=None):
+    _check(lib().pasur_warm_start_round(gt.h, st.fgt.h, C.byref(st.c), C.byref(w), max_level,
+                                        kappa_r, kappa_s, _stream(stream)),
+           "pasur_warm_start_round")
 
 
 def gather_f32(src, dtype: int, idx, n: int, dst, stream=None):

@@ -1,5 +1,5 @@
-// pasur_mlp.hip -- the learned warm start: a 160-256-256-2 MLP over card
-// bitmasks and the inherited score, trained on the average strategies and
+// pasur_mlp.hip -- the learned warm start: a 192-256-256-2 MLP over card
+// bitmasks, the inherited score and the score of the round so far, trained on the average strategies and
 // node values that the DCFR kernels produce, and used to initialise DCFR on
 // new deals.  GEMMs run on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16:
 // BF16 operands, FP32 accumulation).
@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 using namespace pasur;
 
@@ -15,7 +16,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 namespace {
 
-constexpr int kIn = 160, kHid = 256, kOut = 2;
+constexpr int kIn = 192, kHid = 256, kOut = 2;
 constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // 80-byte LDS rows keep 16-byte alignment
 
 struct GemmArgs {
@@ -136,21 +137,25 @@ __global__ void k_f32_to_bf16(const float *__restrict__ x, int64_t n, __bf16 *__
   if (i < n) y[i] = (__bf16)x[i];
 }
 
-// Features of FGT edges (the child node's card state and score): Alex's
-// hand, Bob's hand and the pool as three 52-bit masks, then ca/7, cb/7,
-// d/16 and +1/-1/0 for the 7-club bonus owner.  One row of 160 BF16 values
-// per edge.
+// Features of FGT edges (the child node's card state and score), one row of
+// 192 BF16 values per edge:
+//   0..155   Alex's hand, Bob's hand and the pool as three 52-bit masks;
+//   156..159 inherited score: ca/7, cb/7, d/16, +1/-1/0 for the 7-club bonus
+//            owner (Alex/Bob/none);
+//   160..166 the round so far (the GT node's running score): Alex's and
+//            Bob's clubs /13, last picker +1/-1/0 (Alex/Bob/none), Alex's
+//            points /10 and Surs, Bob's points /10 and Surs;
+//   167..175 one-hot of the node's level (0..8);
+//   176..191 zero.
 struct HandCards {
   uint8_t card[8];
 };
 
-__global__ void k_features(int64_t n, const int32_t *__restrict__ edges, const int32_t *__restrict__ f_gt,
-                           const int32_t *__restrict__ f_sid, const uint64_t *__restrict__ pool,
-                           const uint8_t *__restrict__ hands, const int8_t *__restrict__ tab,
-                           HandCards hc, __bf16 *__restrict__ X) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t q = edges ? edges[i] : (int32_t)i;
+__device__ void feature_row(int32_t q, const int32_t *__restrict__ f_gt,
+                            const int32_t *__restrict__ f_sid, const uint64_t *__restrict__ pool,
+                            const uint8_t *__restrict__ hands, const int8_t *__restrict__ rs,
+                            const int8_t *__restrict__ tab, int level, const HandCards &hc,
+                            __bf16 *__restrict__ row) {
   const int32_t g = f_gt[q];
   const uint8_t h = hands[g];
   uint64_t ha = 0, hb = 0;
@@ -159,7 +164,6 @@ __global__ void k_features(int64_t n, const int32_t *__restrict__ edges, const i
     if ((h >> (4 + b)) & 1) hb |= 1ull << hc.card[4 + b];
   }
   const uint64_t p = pool[g];
-  __bf16 *row = X + i * kIn;
   const __bf16 one = (__bf16)1.f, zero = (__bf16)0.f;
   for (int c = 0; c < 52; ++c) {
     row[c] = ((ha >> c) & 1) ? one : zero;
@@ -171,6 +175,48 @@ __global__ void k_features(int64_t n, const int32_t *__restrict__ edges, const i
   row[157] = (__bf16)((float)s[1] / 7.f);
   row[158] = (__bf16)((float)s[2] / 16.f);
   row[159] = (__bf16)(s[3] == 1 ? 1.f : (s[3] == 2 ? -1.f : 0.f));
+  const int8_t *r = rs + 8 * (int64_t)g;  // Acl, Bcl, last picker, Apt, Asr, Bpt, Bsr
+  row[160] = (__bf16)((float)r[0] / 13.f);
+  row[161] = (__bf16)((float)r[1] / 13.f);
+  row[162] = (__bf16)(r[2] == 1 ? 1.f : (r[2] == 2 ? -1.f : 0.f));
+  row[163] = (__bf16)((float)r[3] / 10.f);
+  row[164] = (__bf16)(float)r[4];
+  row[165] = (__bf16)((float)r[5] / 10.f);
+  row[166] = (__bf16)(float)r[6];
+  for (int c = 167; c < kIn; ++c) row[c] = zero;
+  row[167 + level] = one;
+}
+
+__global__ void k_features(int64_t n, const int32_t *__restrict__ edges, const int32_t *__restrict__ f_gt,
+                           const int32_t *__restrict__ f_sid, const uint64_t *__restrict__ pool,
+                           const uint8_t *__restrict__ hands, const int8_t *__restrict__ rs,
+                           const int8_t *__restrict__ tab, int level, HandCards hc,
+                           __bf16 *__restrict__ X) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  feature_row(edges ? edges[i] : (int32_t)i, f_gt, f_sid, pool, hands, rs, tab, level, hc,
+              X + i * kIn);
+}
+
+// Feature rows of every node of levels 1..nl, level by level (row off[l-1] +
+// q for node q of level l).
+struct FeatLevels {
+  const int32_t *f_gt[9], *f_sid[9];
+  const uint64_t *pool[9];
+  const uint8_t *hands[9];
+  const int8_t *rs[9];
+  int64_t off[9];  // off[l-1] = first row of level l; off[nl] = rows
+  int nl;
+};
+
+__global__ void k_features_levels(FeatLevels F, const int8_t *__restrict__ tab, HandCards hc,
+                                  __bf16 *__restrict__ X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F.off[F.nl]) return;
+  int l = 1;
+  while (l < F.nl && i >= F.off[l]) ++l;
+  feature_row((int32_t)(i - F.off[l - 1]), F.f_gt[l], F.f_sid[l], F.pool[l], F.hands[l], F.rs[l],
+              tab, l, hc, X + i * kIn);
 }
 
 // Policy / value loss gradient.  seg[p]..seg[p+1] are the rows (edges) of
@@ -234,6 +280,39 @@ __global__ void k_warm_init(int64_t np, const int32_t *__restrict__ cb, const fl
     sigma[q] = (T)s;
     R[q] = (T)(kappa_r * s);
     Sbar[q] = (T)(kappa_s * s);
+  }
+}
+
+// The same for the children of every node of levels 0..nl-1 in one launch:
+// parent j of level l is node j - poff[l]; its children's logits are rows
+// yoff[l] + child index of Y.
+template <class T>
+struct WarmLevels {
+  const int32_t *cb[9];
+  T *sigma[9], *R[9], *Sbar[9];  // of the child level l+1
+  int64_t poff[9], yoff[9];
+  int nl;
+};
+
+template <class T>
+__global__ void k_warm_init_levels(WarmLevels<T> W, const float *__restrict__ Y, float kappa_r,
+                                   float kappa_s) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= W.poff[W.nl]) return;
+  int l = 0;
+  while (l + 1 < W.nl && j >= W.poff[l + 1]) ++l;
+  const int64_t h = j - W.poff[l];
+  const int32_t b = W.cb[l][h], e = W.cb[l][h + 1];
+  const float *y = Y + 2 * W.yoff[l];
+  double mx = -INFINITY;
+  for (int32_t q = b; q < e; ++q) mx = fmax(mx, (double)y[2 * q]);
+  double z = 0.0;
+  for (int32_t q = b; q < e; ++q) z += exp((double)y[2 * q] - mx);
+  for (int32_t q = b; q < e; ++q) {
+    const double sv = exp((double)y[2 * q] - mx) / z;
+    W.sigma[l][q] = (T)sv;
+    W.R[l][q] = (T)(kappa_r * sv);
+    W.Sbar[l][q] = (T)(kappa_s * sv);
   }
 }
 
@@ -471,7 +550,7 @@ extern "C" int pasur_edge_features(const pasur_gt *gt, const pasur_fgt *fgt, int
   for (int b = 0; b < 8; ++b) hc.card[b] = gt->deck[4 + 8 * gt->round + b];
   k_features<<<blocks(n), 256, 0, (hipStream_t)stream>>>(
       n, d_edges, fgt->gt[level], fgt->sid[level], gt->pool[level], gt->hands[level],
-      fgt->score_tab, hc, (__bf16 *)d_X);
+      (const int8_t *)gt->rs[level], fgt->score_tab, level, hc, (__bf16 *)d_X);
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
 }
@@ -569,4 +648,94 @@ extern "C" int pasur_shift_i32(const int32_t *src, int64_t n, int32_t add, int32
   k_shift<<<blocks(n), 256, 0, (hipStream_t)stream>>>(src, n, add, dst);
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
+}
+
+extern "C" int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt,
+                                      const pasur_cfr_state *st, const pasur_mlp_weights *w,
+                                      int max_level, float kappa_r, float kappa_s, void *stream) {
+  if (!gt || !fgt || !st || !w) {
+    set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  if (max_level < 1 || max_level > 8) {
+    set_error("max_level %d outside 1..8", max_level);
+    return PASUR_E_RANGE;
+  }
+  if (gt->n[0] == 0 || fgt->round != gt->round) {
+    set_error("the game tree does not belong to this unfolded tree");
+    return PASUR_E_INVAL;
+  }
+  if (st->dtype != PASUR_F32 && st->dtype != PASUR_F64) {
+    set_error("unknown dtype %d", st->dtype);
+    return PASUR_E_RANGE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  FeatLevels F;
+  std::memset(&F, 0, sizeof(F));
+  F.nl = max_level;
+  int64_t rows = 0;
+  for (int l = 1; l <= max_level; ++l) {
+    F.off[l - 1] = rows;
+    F.f_gt[l] = fgt->gt[l];
+    F.f_sid[l] = fgt->sid[l];
+    F.pool[l] = gt->pool[l];
+    F.hands[l] = gt->hands[l];
+    F.rs[l] = (const int8_t *)gt->rs[l];
+    rows += fgt->n[l];
+  }
+  F.off[max_level] = rows;
+  if (rows == 0) return PASUR_OK;
+  if (rows > INT32_MAX) {
+    set_error("too many rows for one forward pass");
+    return PASUR_E_RANGE;
+  }
+  HandCards hc;
+  for (int b = 0; b < 8; ++b) hc.card[b] = gt->deck[4 + 8 * gt->round + b];
+  __bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr;
+  float *Y = nullptr;
+  hipError_t e = hipMallocAsync((void **)&X, sizeof(__bf16) * (size_t)rows * kIn, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&H1, sizeof(__bf16) * (size_t)rows * kHid, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&H2, sizeof(__bf16) * (size_t)rows * kHid, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&Y, sizeof(float) * (size_t)rows * kOut, s);
+  int rc = PASUR_OK;
+  if (e != hipSuccess) {
+    set_error("warm start workspace: %s", hipGetErrorString(e));
+    rc = PASUR_E_NOMEM;
+  }
+  if (!rc) {
+    k_features_levels<<<blocks(rows), 256, 0, s>>>(F, fgt->score_tab, hc, X);
+    rc = pasur_mlp_forward(w, (const uint16_t *)X, rows, (uint16_t *)H1, (uint16_t *)H2, Y, s);
+  }
+  if (!rc) {
+    auto launch = [&](auto *tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      WarmLevels<T> W;
+      std::memset(&W, 0, sizeof(W));
+      W.nl = max_level;
+      int64_t p = 0;
+      for (int l = 0; l < max_level; ++l) {
+        W.cb[l] = fgt->child_begin[l];
+        W.sigma[l] = (T *)st->sigma[l + 1];
+        W.R[l] = (T *)st->R[l + 1];
+        W.Sbar[l] = (T *)st->Sbar[l + 1];
+        W.poff[l] = p;
+        W.yoff[l] = F.off[l];
+        p += fgt->n[l];
+      }
+      W.poff[max_level] = p;
+      k_warm_init_levels<T><<<blocks(p), 256, 0, s>>>(W, Y, kappa_r, kappa_s);
+    };
+    if (st->dtype == PASUR_F32) launch((float *)nullptr);
+    else launch((double *)nullptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error("warm start: %s", hipGetErrorString(e));
+      rc = PASUR_E_HIP;
+    }
+  }
+  (void)hipFreeAsync(X, s);
+  (void)hipFreeAsync(H1, s);
+  (void)hipFreeAsync(H2, s);
+  (void)hipFreeAsync(Y, s);
+  return rc;
 }

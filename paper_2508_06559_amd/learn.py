@@ -23,10 +23,10 @@ import numpy as np
 from . import (PASUR_F32, PASUR_F64, MlpGrads, MlpWeights, CfrState, adam_step, average_strategy,
                cfr_init, cfr_iterate, cfr_warm_init, edge_features, gather_f32, leaf_utilities,
                mlp_backward, mlp_forward, mlp_loss, paper_params, round_values, sample_parents,
-               shift_i32, _torch)
+               shift_i32, warm_start_round as _warm_start_round, _torch)
 from .solver import SubgameSolver
 
-N_IN, N_HID, N_OUT = 160, 256, 2
+N_IN, N_HID, N_OUT = 192, 256, 2
 
 
 def _bf16_bits(x: np.ndarray) -> np.ndarray:
@@ -39,7 +39,7 @@ def _bf16_bits(x: np.ndarray) -> np.ndarray:
 @dataclass
 class Unit:
     """One training unit: sampled parents of one round of one deal."""
-    X: object      # [rows, 160] BF16 bits (int16)
+    X: object      # [rows, N_IN] BF16 bits (int16)
     seg: object    # [parents + 1] int32 row offsets
     tsig: object   # [rows] float32 target average strategy
     tval: object   # [rows] float32 target node value
@@ -48,7 +48,7 @@ class Unit:
 
 
 class WarmStartMLP:
-    """160-256-256-2 MLP; FP32 master weights with BF16 copies for the GEMMs."""
+    """192-256-256-2 MLP; FP32 master weights with BF16 copies for the GEMMs."""
 
     def __init__(self, seed: int = 0):
         torch = _torch()
@@ -155,8 +155,16 @@ def make_units(solver: SubgameSolver, seed: int, parents_per_level: int = 400) -
     return units
 
 
-def warm_start_round(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float):
-    """Predict every level's logits and seed sigma, R and Sbar (after cfr_init)."""
+def warm_start_round(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float,
+                     max_level: int = 8):
+    """Predict the logits of levels 1..max_level and seed sigma, R and Sbar
+    (after cfr_init): one libpasur call (features, forward pass, warm init)."""
+    _warm_start_round(rr.gt, rr.state, model.weights(), max_level, kappa_r, kappa_s)
+
+
+def warm_start_round_by_level(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float):
+    """The same as warm_start_round with max_level 8, one level at a time
+    through the per-level calls (kept as a cross-check)."""
     torch = _torch()
     f = rr.fgt
     for l in range(1, 9):
@@ -173,10 +181,12 @@ class WarmParams:
     predicted profile); t_virtual: iterations the seeds stand for.  The
     default uses the prediction as the first iterate only (seeds 0, t0 = 1):
     on held-out two-round deals seeding regrets or averages with a profile
-    this exploitable slowed convergence, while starting from it did not."""
+    this exploitable slowed convergence, while starting from it did not.
+    max_level: the levels whose strategies are predicted (1..max_level)."""
     kappa_r: float = 0.0
     kappa_s: float = 0.0
     t_virtual: int = 0
+    max_level: int = 8
 
 
 def solve_subgame(deck, start_round: int, roots, iters: int, dtype: int = PASUR_F32,
@@ -194,7 +204,7 @@ def solve_subgame(deck, start_round: int, roots, iters: int, dtype: int = PASUR_
         cfr_init(rr.state)
         t0 = 1
         if model is not None:
-            warm_start_round(model, rr, warm.kappa_r, warm.kappa_s)
+            warm_start_round(model, rr, warm.kappa_r, warm.kappa_s, warm.max_level)
             t0 = warm.t_virtual + 1
         cfr_iterate(rr.state, iters, params, t0=t0)
         average_strategy(rr.state)

@@ -40,7 +40,7 @@ def test_warm_init_sets_softmax_of_logits(trained):
     pa.cfr_init(rr.state)
     l = 2
     n = rr.fgt.n[l]
-    X = torch.empty((n, 160), dtype=torch.int16, device="cuda")
+    X = torch.empty((n, learn.N_IN), dtype=torch.int16, device="cuda")
     pa.edge_features(rr.gt, rr.fgt, l, None, n, X)
     Y = to_np(model.forward(X, n)).astype(np.float64)
     pa.cfr_warm_init(rr.state, l, model.forward(X, n), 0.5, 2.0)
@@ -73,3 +73,37 @@ def test_network_profile_beats_uniform_start(trained):
           f"iterations to 1e-3 plain {it_p} warm {it_w}", flush=True)
     assert np.median(ex_n) < np.median(ex_u)
     assert all(i is not None for i in it_p + it_w)
+
+
+@pytest.mark.parametrize("max_level", [8, 3])
+def test_round_warm_start_matches_per_level_calls(trained, max_level):
+    """The one-call round warm start (features of all levels, one forward
+    pass, one initialisation launch) sets exactly what the per-level calls
+    set on levels 1..max_level and leaves deeper levels as cfr_init left them."""
+    pa = require_gpu()
+    import torch
+    from paper_2508_06559_amd import learn
+    model, _ = trained
+    deck, roots = synth.two_round_root(20003)
+    sv = pa.SubgameSolver(deck, 4, roots, keep_gt=True)
+    rr = sv.rounds[1]
+    got = pa.CfrState(rr.fgt, pa.PASUR_F64)
+    ref = pa.CfrState(rr.fgt, pa.PASUR_F64)
+    pa.cfr_init(got)
+    pa.cfr_init(ref)
+    init = [None] + [to_np(x).copy() for x in ref.sigma[1:]]
+    rr.state = ref
+    learn.warm_start_round_by_level(model, rr, 0.5, 2.0)
+    rr.state = got
+    learn.warm_start_round(model, rr, 0.5, 2.0, max_level)
+    torch.cuda.synchronize()
+    for l in range(1, 9):
+        g_s, g_r, g_b = to_np(got.sigma[l]), to_np(got.R[l]), to_np(got.Sbar[l])
+        if l <= max_level:
+            assert np.array_equal(g_s, to_np(ref.sigma[l])), l
+            assert np.array_equal(g_r, to_np(ref.R[l])), l
+            assert np.array_equal(g_b, to_np(ref.Sbar[l])), l
+        else:
+            assert np.array_equal(g_s, init[l]), l
+            assert not g_r.any() and not g_b.any(), l
+    sv.free()

@@ -54,8 +54,8 @@ def make_problem(seed, n_par=300):
     fan = rng.integers(1, 6, n_par)
     seg = np.concatenate([[0], np.cumsum(fan)]).astype(np.int32)
     M = int(seg[-1])
-    X = rng.integers(0, 2, (M, 160)).astype(np.float64)
-    X[:, 156:] = rng.normal(0, 0.5, (M, 4))
+    X = rng.integers(0, 2, (M, omlp.N_IN)).astype(np.float64)
+    X[:, 156:167] = rng.normal(0, 0.5, (M, 11))
     X = omlp.bf16_round(X)
     tsig = np.concatenate([rng.dirichlet(np.ones(k)) for k in fan]).astype(np.float32)
     tval = rng.normal(0, 3, M).astype(np.float32)
@@ -114,7 +114,7 @@ def test_features_encode_state_and_score():
     rr = s.rounds[0]
     l = 3
     n = rr.fgt.n[l]
-    X = torch.empty((n, 160), dtype=torch.int16, device="cuda")
+    X = torch.empty((n, omlp.N_IN), dtype=torch.int16, device="cuda")
     pa.edge_features(rr.gt, rr.fgt, l, None, n, X)
     torch.cuda.synchronize()
     Xf = from_bf16(X)
@@ -123,16 +123,21 @@ def test_features_encode_state_and_score():
     tab = rr.fgt.read(pa.FGT_SCORE_TAB)
     pool = rr.gt.read(pa.GT_POOL, l)
     hands = rr.gt.read(pa.GT_HANDS, l)
+    rs = rr.gt.read(pa.GT_RS, l)
     a, b = synth.round_hands(deck, 5)
     for i in range(0, n, max(1, n // 50)):
         t = g[i]
         ha = [a[k] for k in range(4) if (hands[t] >> k) & 1]
         hb = [b[k] for k in range(4) if (hands[t] >> (4 + k)) & 1]
-        want = np.zeros(160)
+        want = np.zeros(omlp.N_IN)
         want[ha] = 1
         want[[52 + c for c in hb]] = 1
         want[[104 + c for c in range(52) if (int(pool[t]) >> c) & 1]] = 1
         ca, cb, d, bo = tab[sid[i]]
-        want[156:] = omlp.bf16_round([ca / 7, cb / 7, d / 16, {0: 0, 1: 1, 2: -1}[int(bo)]])
+        want[156:160] = omlp.bf16_round([ca / 7, cb / 7, d / 16, {0: 0, 1: 1, 2: -1}[int(bo)]])
+        acl, bcl, lp, apt, asr, bpt, bsr = (int(v) for v in rs[t][:7])
+        want[160:167] = omlp.bf16_round([acl / 13, bcl / 13, {0: 0, 1: 1, 2: -1}[lp],
+                                         apt / 10, asr, bpt / 10, bsr])
+        want[167 + l] = 1
         assert np.array_equal(Xf[i], want), i
     s.free()

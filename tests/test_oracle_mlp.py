@@ -22,8 +22,8 @@ def _problem(rng, n_par=7):
     fan = rng.integers(1, 5, n_par)
     seg = np.concatenate([[0], np.cumsum(fan)])
     M = int(seg[-1])
-    X = rng.integers(0, 2, (M, 160)).astype(np.float64)
-    X[:, 156:] = rng.normal(0, 0.5, (M, 4))
+    X = rng.integers(0, 2, (M, mlp.N_IN)).astype(np.float64)
+    X[:, 156:167] = rng.normal(0, 0.5, (M, 11))
     tsig = np.concatenate([rng.dirichlet(np.ones(k)) for k in fan])
     tval = rng.normal(0, 3, M)
     return X, seg, tsig, tval
