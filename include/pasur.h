@@ -270,6 +270,12 @@ int pasur_gemm_bf16(int M, int N, int K, const uint16_t *A, int64_t sar, int64_t
  * ReLU), Y [M][2] (FP32: logit, value). */
 int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
                       uint16_t *H1, uint16_t *H2, float *Y, void *stream);
+/* Inference only: Y [M][2] (FP32) for M rows of X [M][192] (BF16), the same
+ * arithmetic as pasur_mlp_forward (H1, H2 rounded to BF16; FP32 accumulation
+ * in another order) in one fused launch that keeps H1 and H2 on chip.  Uses
+ * stream-ordered scratch for the transposed weights (~220 KB). */
+int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M, float *Y,
+                    void *stream);
 /* Gradients of the loss with respect to the weights given dY [M][2] (FP32);
  * dY is rounded to BF16 for the GEMMs.  Uses stream-ordered scratch. */
 int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X, const uint16_t *H1,
@@ -312,7 +318,8 @@ int pasur_cfr_warm_init(const pasur_fgt *fgt, const pasur_cfr_state *st, int lev
  * forward pass over all of them, and sigma / R / Sbar of those levels as in
  * pasur_cfr_warm_init (one launch); deeper levels keep their initial state.
  * `gt` must be the game tree `fgt` was unfolded from.  Uses stream-ordered
- * scratch (rows x (192 + 2 x 256) BF16 + rows x 2 FP32). */
+ * scratch (rows x 192 BF16 + rows x 2 FP32); the forward pass is
+ * pasur_mlp_infer. */
 int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt, const pasur_cfr_state *st,
                            const pasur_mlp_weights *w, int max_level, float kappa_r,
                            float kappa_s, void *stream);

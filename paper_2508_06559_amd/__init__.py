@@ -101,6 +101,7 @@ def lib():
                                            C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
         L.pasur_cfr_warm_init.argtypes = [vp, vp, i32, vp, C.c_float, C.c_float, vp]
         L.pasur_warm_start_round.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, vp]
+        L.pasur_mlp_infer.argtypes = [vp, vp, i64, vp, vp]
         L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
         L.pasur_shift_i32.argtypes = [vp, i64, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
@@ -392,6 +393,10 @@ def gemm_bf16(M, N, K, A, sar, sac, B, sbr, sbc, Cf=None, Cb=None, ldc=None, bia
 def mlp_forward(w: MlpWeights, X, M, H1, H2, Y, stream=None):
     _check(lib().pasur_mlp_forward(C.byref(w), _p(X), M, _p(H1), _p(H2), _p(Y), _stream(stream)),
            "pasur_mlp_forward")
+
+
+def mlp_infer(w: MlpWeights, X, M, Y, stream=None):
+    _check(lib().pasur_mlp_infer(C.byref(w), _p(X), M, _p(Y), _stream(stream)), "pasur_mlp_infer")
 
 
 def mlp_backward(w: MlpWeights, X, H1, H2, dY, M, g: MlpGrads, stream=None):

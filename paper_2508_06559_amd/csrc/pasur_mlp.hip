@@ -318,6 +318,117 @@ __global__ void k_warm_init_levels(WarmLevels<T> W, const float *__restrict__ Y,
 
 inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// ---------------------------------------------------------------------------
+// Fused inference: Y = (relu(relu(X W1 + b1) W2 + b2)) W3 + b3 for a tile of
+// 128 rows per workgroup, H1 and H2 kept in LDS (rounded to BF16 as in
+// pasur_mlp_forward).  The MFMA computes each layer transposed, D = W^T A^T:
+// the weights (pre-transposed to [out][in], contiguous in K) are the A
+// operand, loaded from global memory (L2-resident, shared by all
+// workgroups) 16 bytes per lane and prefetched one K step ahead; the
+// activations (row-major in LDS, contiguous in K) are the B operand.  A
+// 16x16 result tile then holds four consecutive output features of one row
+// per lane, which store as one 8-byte LDS write.  Wave w owns output
+// features 64w..64w+63 for all 128 rows (4 x 8 tiles of 16x16x32).
+// The last layer (256 -> 2) is a plain FP32 dot product per (row, output),
+// in feature order.
+constexpr int IM = 128;                 // rows per workgroup
+constexpr int XS = kIn + 8, HS = kHid + 8;  // LDS row strides (bf16), 16-byte aligned
+
+__global__ void __launch_bounds__(256) k_mlp_infer(int M, const __bf16 *__restrict__ X,
+                                                   const __bf16 *__restrict__ W1t,
+                                                   const float *__restrict__ b1,
+                                                   const __bf16 *__restrict__ W2t,
+                                                   const float *__restrict__ b2,
+                                                   const __bf16 *__restrict__ W3,
+                                                   const float *__restrict__ b3,
+                                                   float *__restrict__ Y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __bf16 *Xs = reinterpret_cast<__bf16 *>(smem);          // [IM][XS]
+  __bf16 *Hs = Xs + IM * XS;                               // [IM][HS]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * IM;
+  // X tile -> LDS (16-byte pieces; rows past M are zero)
+  for (int e = tid; e < IM * (kIn / 8); e += 256) {
+    const int r = e / (kIn / 8), c = (e % (kIn / 8)) * 8;
+    bf16x8 v;
+    if (m0 + r < M) v = *reinterpret_cast<const bf16x8 *>(X + (int64_t)(m0 + r) * kIn + c);
+    else
+      for (int i = 0; i < 8; ++i) v[i] = (__bf16)0.f;
+    *reinterpret_cast<bf16x8 *>(Xs + r * XS + c) = v;
+  }
+  __syncthreads();
+  const int n_base = wave * 64;        // this wave's output features
+  const int lr = lane & 15, lk = 8 * (lane >> 4);
+  auto layer = [&](const __bf16 *__restrict__ Wt, int K, const __bf16 *As, int as,
+                   const float *__restrict__ bias) {
+    f32x4 acc[4][8];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 wcur[4], wnext[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      wcur[a] = *reinterpret_cast<const bf16x8 *>(Wt + (int64_t)(n_base + 16 * a + lr) * K + lk);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      if (k0 + 32 < K) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          wnext[a] = *reinterpret_cast<const bf16x8 *>(Wt + (int64_t)(n_base + 16 * a + lr) * K +
+                                                       k0 + 32 + lk);
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bf16x8 x = *reinterpret_cast<const bf16x8 *>(As + (16 * b + lr) * as + k0 + lk);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[a], x, acc[a][b], 0, 0, 0);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) wcur[a] = wnext[a];
+    }
+    __syncthreads();  // every wave has read As before Hs is (over)written
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int n = n_base + 16 * a + 4 * (lane >> 4);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int m = 16 * b + lr;
+        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+        bf16x4 h;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = (__bf16)fmaxf(acc[a][b][i] + bias[n + i], 0.f);
+        *reinterpret_cast<bf16x4 *>(Hs + m * HS + n) = h;
+      }
+    }
+    __syncthreads();
+  };
+  layer(W1t, kIn, Xs, XS, b1);   // H1 in Hs
+  layer(W2t, kHid, Hs, HS, b2);  // H2 in Hs
+  // last layer: thread t -> row t / 2, output t % 2
+  const int r = tid >> 1, o = tid & 1;
+  if (m0 + r < M) {
+    float y = 0.f;
+    for (int n = 0; n < kHid; n += 8) {
+      const bf16x8 h = *reinterpret_cast<const bf16x8 *>(Hs + r * HS + n);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) y += (float)h[i] * (float)W3[(n + i) * kOut + o];
+    }
+    Y[(int64_t)(m0 + r) * kOut + o] = y + b3[o];
+  }
+}
+
+constexpr size_t kInferLds = sizeof(__bf16) * (size_t)IM * (XS + HS);
+
+// W [K][N] (row-major) -> Wt [N][K]
+__global__ void k_transpose_bf16(const __bf16 *__restrict__ W, int K, int N, __bf16 *__restrict__ Wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K * N) return;
+  const int k = i / N, n = i % N;
+  Wt[(int64_t)n * K + k] = W[i];
+}
+
+
 template <class T>
 __global__ void k_gather(const T *__restrict__ src, const int32_t *__restrict__ idx, int64_t n,
                          float *__restrict__ dst) {
@@ -691,11 +802,9 @@ extern "C" int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt,
   }
   HandCards hc;
   for (int b = 0; b < 8; ++b) hc.card[b] = gt->deck[4 + 8 * gt->round + b];
-  __bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr;
+  __bf16 *X = nullptr;
   float *Y = nullptr;
   hipError_t e = hipMallocAsync((void **)&X, sizeof(__bf16) * (size_t)rows * kIn, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&H1, sizeof(__bf16) * (size_t)rows * kHid, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&H2, sizeof(__bf16) * (size_t)rows * kHid, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&Y, sizeof(float) * (size_t)rows * kOut, s);
   int rc = PASUR_OK;
   if (e != hipSuccess) {
@@ -704,7 +813,7 @@ extern "C" int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt,
   }
   if (!rc) {
     k_features_levels<<<blocks(rows), 256, 0, s>>>(F, fgt->score_tab, hc, X);
-    rc = pasur_mlp_forward(w, (const uint16_t *)X, rows, (uint16_t *)H1, (uint16_t *)H2, Y, s);
+    rc = pasur_mlp_infer(w, (const uint16_t *)X, rows, Y, s);
   }
   if (!rc) {
     auto launch = [&](auto *tag) {
@@ -734,8 +843,41 @@ extern "C" int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt,
     }
   }
   (void)hipFreeAsync(X, s);
-  (void)hipFreeAsync(H1, s);
-  (void)hipFreeAsync(H2, s);
   (void)hipFreeAsync(Y, s);
   return rc;
+}
+
+extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
+                               float *Y, void *stream) {
+  if (!w || !X || !Y || M < 0 || M > INT32_MAX) {
+    set_error("bad MLP inference arguments");
+    return PASUR_E_INVAL;
+  }
+  if (M == 0) return PASUR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  __bf16 *Wt = nullptr;
+  hipError_t e = hipMallocAsync((void **)&Wt, sizeof(__bf16) * (size_t)(kIn + kHid) * kHid, s);
+  if (e != hipSuccess) {
+    set_error("MLP inference workspace: %s", hipGetErrorString(e));
+    return PASUR_E_NOMEM;
+  }
+  __bf16 *W1t = Wt, *W2t = Wt + (size_t)kIn * kHid;
+  k_transpose_bf16<<<blocks(kIn * kHid), 256, 0, s>>>((const __bf16 *)w->W1, kIn, kHid, W1t);
+  k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid, W2t);
+  e = hipFuncSetAttribute((const void *)k_mlp_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kInferLds);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(Wt, s);
+    set_error("MLP inference LDS: %s", hipGetErrorString(e));
+    return PASUR_E_HIP;
+  }
+  k_mlp_infer<<<(unsigned)((M + IM - 1) / IM), 256, kInferLds, s>>>(
+      (int)M, (const __bf16 *)X, W1t, w->b1, W2t, w->b2, (const __bf16 *)w->W3, w->b3, Y);
+  e = hipGetLastError();
+  (void)hipFreeAsync(Wt, s);
+  if (e != hipSuccess) {
+    set_error("MLP inference: %s", hipGetErrorString(e));
+    return PASUR_E_HIP;
+  }
+  return PASUR_OK;
 }

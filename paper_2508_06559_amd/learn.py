@@ -22,7 +22,7 @@ import numpy as np
 
 from . import (PASUR_F32, PASUR_F64, MlpGrads, MlpWeights, CfrState, adam_step, average_strategy,
                cfr_init, cfr_iterate, cfr_warm_init, edge_features, gather_f32, leaf_utilities,
-               mlp_backward, mlp_forward, mlp_loss, paper_params, round_values, sample_parents,
+               mlp_backward, mlp_forward, mlp_infer, mlp_loss, paper_params, round_values, sample_parents,
                shift_i32, warm_start_round as _warm_start_round, _torch)
 from .solver import SubgameSolver
 
@@ -171,7 +171,8 @@ def warm_start_round_by_level(model: WarmStartMLP, rr, kappa_r: float, kappa_s: 
         n = f.n[l]
         X = torch.empty((n, N_IN), dtype=torch.int16, device="cuda")
         edge_features(rr.gt, f, l, None, n, X)
-        Y = model.forward(X, n)
+        Y = torch.empty((n, N_OUT), dtype=torch.float32, device="cuda")
+        mlp_infer(model.weights(), X, n, Y)
         cfr_warm_init(rr.state, l, Y, kappa_r, kappa_s)
 
 

@@ -141,3 +141,38 @@ def test_features_encode_state_and_score():
         want[167 + l] = 1
         assert np.array_equal(Xf[i], want), i
     s.free()
+
+
+@pytest.mark.parametrize("M", [1, 127, 128, 129, 1000, 4099])
+def test_mlp_infer_matches_oracle_and_forward(M):
+    """The fused inference kernel against the oracle's BF16-rounded forward
+    pass (ragged row counts around the 128-row tile) and against the
+    three-GEMM forward pass of the same weights."""
+    pa = require_gpu()
+    from paper_2508_06559_amd import learn
+    import torch
+    rng = np.random.default_rng(M)
+    W = omlp.init_weights(rng)
+    W[1] = rng.normal(0, 0.1, 256)
+    W[3] = rng.normal(0, 0.1, 256)
+    W[5] = rng.normal(0, 0.1, 2)
+    W = [np.asarray(w, np.float32).astype(np.float64) for w in W]
+    X = rng.integers(0, 2, (M, omlp.N_IN)).astype(np.float64)
+    X[:, 156:167] = rng.normal(0, 0.5, (M, 11))
+    X = omlp.bf16_round(X)
+    model = learn.WarmStartMLP(0)
+    model.set_weights(W)
+    dX = bf16_tensor(X)
+    Y = torch.empty((M, 2), dtype=torch.float32, device="cuda")
+    pa.mlp_infer(model.weights(), dX, M, Y)
+    b = model._buffers(M)
+    pa.mlp_forward(model.weights(), dX, M, b["H1"], b["H2"], b["Y"])
+    torch.cuda.synchronize()
+    _, H2o, Yo = omlp.forward(W, X, bf16=True)
+    Yi = to_np(Y).astype(np.float64)
+    Yf = to_np(b["Y"][:M]).astype(np.float64)
+    scale = np.abs(Yo).max() + 1
+    assert np.abs(Yi - Yo).max() <= 1e-2 * scale
+    # same BF16 activations as the forward pass up to FP32 accumulation order
+    assert np.abs(Yi - Yf).max() <= 1e-2 * scale
+    assert np.median(np.abs(Yi - Yf)) <= 1e-4 * scale
