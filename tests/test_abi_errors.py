@@ -1,0 +1,130 @@
+"""Argument checking at the C boundary, on the CPU: every call below is
+rejected by the library's host-side checks (documented error codes, a
+message from pasur_last_error) before any HIP runtime call, so no GPU is
+needed."""
+import ctypes as C
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2508_06559_amd", "libpasur.so")
+E_INVAL, E_RANGE = -1, -2
+DUMMY = C.c_void_p(8)  # a non-null pointer the checks never dereference
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libpasur.so is not built: run __graft_entry__.build()")
+    L = C.CDLL(LIB)
+    L.pasur_last_error.restype = C.c_char_p
+    return L
+
+
+def expect(L, rc, code, words):
+    assert rc == code
+    msg = L.pasur_last_error().decode()
+    assert all(w in msg for w in words), msg
+
+
+def deck(values=None):
+    return (C.c_uint8 * 52)(*(values if values is not None else range(52)))
+
+
+def test_build_round_tree_checks(lib):
+    out = C.c_void_p()
+    vp = C.c_void_p
+    f = lib.pasur_build_round_tree
+    f.argtypes = [vp, C.c_int, vp, C.c_int64, C.POINTER(vp), vp]
+    expect(lib, f(deck(), 0, DUMMY, 1, None, None), E_INVAL, ["out_gt"])
+    expect(lib, f(deck(), 6, DUMMY, 1, C.byref(out), None), E_RANGE, ["round 6"])
+    expect(lib, f(deck(), -1, DUMMY, 1, C.byref(out), None), E_RANGE, ["round -1"])
+    expect(lib, f(None, 0, DUMMY, 1, C.byref(out), None), E_INVAL, ["deck is NULL"])
+    bad = list(range(52))
+    bad[7] = 3  # card 3 twice
+    expect(lib, f(deck(bad), 0, DUMMY, 1, C.byref(out), None), E_INVAL, ["permutation", "slot 7"])
+    bad = list(range(52))
+    bad[0] = 52  # not a card
+    expect(lib, f(deck(bad), 0, DUMMY, 1, C.byref(out), None), E_INVAL, ["slot 0"])
+    expect(lib, f(deck(), 0, None, 1, C.byref(out), None), E_INVAL, ["root"])
+    expect(lib, f(deck(), 0, DUMMY, 0, C.byref(out), None), E_INVAL, ["root"])
+    assert out.value is None  # nothing is handed out on failure
+
+
+class State(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("sigma", C.c_void_p * 9), ("R", C.c_void_p * 9),
+                ("Sbar", C.c_void_p * 9), ("reachA", C.c_void_p * 9),
+                ("reachB", C.c_void_p * 9), ("u", C.c_void_p * 9), ("vacc", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("variant", C.c_int), ("rm_mode", C.c_int), ("alpha", C.c_double),
+                ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double),
+                ("schedule", C.c_int), ("block", C.c_int), ("seg_nodes", C.c_int)]
+
+
+def full_state(dtype=0):
+    st = State()
+    st.dtype = dtype
+    for arr in (st.sigma, st.R, st.Sbar, st.reachA, st.reachB, st.u):
+        for l in range(9):
+            arr[l] = 8
+    st.vacc = 8
+    return st
+
+
+def test_cfr_checks(lib):
+    vp = C.c_void_p
+    it = lib.pasur_cfr_iterate
+    it.argtypes = [vp, vp, vp, C.c_int64, C.c_int, vp]
+    p = Params(0, 0, 1.5, 0.0, 2.0, 1e-8, 0, 0, 0)
+    expect(lib, it(None, C.byref(full_state()), C.byref(p), 1, 10, None), E_INVAL, ["null"])
+    expect(lib, it(DUMMY, C.byref(full_state(7)), C.byref(p), 1, 10, None), E_RANGE, ["dtype 7"])
+    st = full_state()
+    st.u[3] = None
+    expect(lib, it(DUMMY, C.byref(st), C.byref(p), 1, 10, None), E_INVAL, ["u[3]"])
+    expect(lib, it(DUMMY, C.byref(full_state()), None, 1, 10, None), E_INVAL, ["params"])
+    expect(lib, it(DUMMY, C.byref(full_state()), C.byref(p), 0, 10, None), E_RANGE, ["t0"])
+    expect(lib, it(DUMMY, C.byref(full_state()), C.byref(p), 1, -1, None), E_RANGE, ["n_iters"])
+    for bad in (Params(3, 0, 1.5, 0, 2, 1e-8, 0, 0, 0), Params(0, 2, 1.5, 0, 2, 1e-8, 0, 0, 0)):
+        expect(lib, it(DUMMY, C.byref(full_state()), C.byref(bad), 1, 10, None), E_RANGE,
+               ["variant"])
+    for bad in (Params(0, 0, 1.5, 0, 2, 1e-8, 5, 0, 0), Params(0, 0, 1.5, 0, 2, 1e-8, 0, 300, 0)):
+        expect(lib, it(DUMMY, C.byref(full_state()), C.byref(bad), 1, 10, None), E_RANGE,
+               ["schedule or block"])
+    pc = lib.pasur_plan_create
+    pc.argtypes = [vp, vp, C.c_int, vp, C.c_int64, C.c_int64, C.POINTER(vp), vp]
+    out = C.c_void_p()
+    expect(lib, pc(None, DUMMY, 1, C.byref(p), 1, 10, C.byref(out), None), E_INVAL, ["null"])
+    expect(lib, pc(DUMMY, DUMMY, 0, C.byref(p), 1, 10, C.byref(out), None), E_INVAL, ["empty"])
+    expect(lib, pc(DUMMY, DUMMY, 1, C.byref(p), 0, 10, C.byref(out), None), E_RANGE, ["t_first"])
+    expect(lib, pc(DUMMY, DUMMY, 1, C.byref(p), 5, 4, C.byref(out), None), E_RANGE, ["t_first"])
+
+
+def test_mlp_checks(lib):
+    vp = C.c_void_p
+    g = lib.pasur_gemm_bf16
+    g.argtypes = [C.c_int, C.c_int, C.c_int, vp, C.c_int64, C.c_int64, vp, C.c_int64, C.c_int64,
+                  vp, vp, C.c_int64, vp, C.c_int, vp]
+    expect(lib, g(-1, 4, 4, DUMMY, 4, 1, DUMMY, 4, 1, DUMMY, None, 4, None, 0, None), E_INVAL, ["GEMM"])
+    expect(lib, g(4, 4, 0, DUMMY, 4, 1, DUMMY, 4, 1, DUMMY, None, 4, None, 0, None), E_INVAL, ["GEMM"])
+    expect(lib, g(4, 4, 4, DUMMY, 4, 1, DUMMY, 4, 1, None, None, 4, None, 0, None), E_INVAL, ["GEMM"])
+    fw = lib.pasur_mlp_forward
+    fw.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp]
+    expect(lib, fw(None, DUMMY, 4, DUMMY, DUMMY, DUMMY, None), E_INVAL, ["forward"])
+    expect(lib, fw(DUMMY, DUMMY, -1, DUMMY, DUMMY, DUMMY, None), E_INVAL, ["forward"])
+    inf = lib.pasur_mlp_infer
+    inf.argtypes = [vp, vp, C.c_int64, vp, vp]
+    expect(lib, inf(DUMMY, None, 4, DUMMY, None), E_INVAL, ["inference"])
+    expect(lib, inf(DUMMY, DUMMY, 1 << 40, DUMMY, None), E_INVAL, ["inference"])
+    ws = lib.pasur_warm_start_round
+    ws.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, vp]
+    expect(lib, ws(None, DUMMY, DUMMY, DUMMY, 4, 0.0, 0.0, None), E_INVAL, ["null"])
+    expect(lib, ws(DUMMY, DUMMY, DUMMY, DUMMY, 9, 0.0, 0.0, None), E_RANGE, ["max_level 9"])
+    expect(lib, ws(DUMMY, DUMMY, DUMMY, DUMMY, 0, 0.0, 0.0, None), E_RANGE, ["max_level 0"])
+    ad = lib.pasur_adam_step
+    ad.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                   C.c_int64, vp]
+    expect(lib, ad(DUMMY, DUMMY, DUMMY, DUMMY, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None),
+           E_INVAL, ["Adam"])
