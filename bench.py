@@ -309,10 +309,10 @@ def bench_warm(args):
     hist += learn.train(model, units, args.epochs - 1, seed=0, log=log)
     big = torch.zeros((1 << 20, learn.N_IN), dtype=torch.int16, device="cuda")
     Yb = torch.empty((big.shape[0], 2), dtype=torch.float32, device="cuda")
-    pa.mlp_infer(model.weights(), big, big.shape[0], Yb)
+    pa.mlp_infer(model.infer_weights(), big, big.shape[0], Yb)
     a.record()
     for _ in range(5):
-        pa.mlp_infer(model.weights(), big, big.shape[0], Yb)
+        pa.mlp_infer(model.infer_weights(), big, big.shape[0], Yb)
     b.record()
     b.synchronize()
     inf_tflops = 5 * per_row * big.shape[0] / (a.elapsed_time(b) * 1e-3) / 1e12

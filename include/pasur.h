@@ -255,6 +255,10 @@ typedef struct {
   const uint16_t *W1; const float *b1; /* [192][256], [256] */
   const uint16_t *W2; const float *b2; /* [256][256], [256] */
   const uint16_t *W3; const float *b3; /* [256][2], [2] */
+  /* Optional (may be NULL): W1 and W2 transposed to [256][192] and [256][256]
+   * (pasur_mlp_transpose), used by pasur_mlp_infer instead of transposing
+   * into scratch on every call. */
+  const uint16_t *W1t, *W2t;
 } pasur_mlp_weights;
 typedef struct {
   float *dW1, *db1, *dW2, *db2, *dW3, *db3; /* FP32, same shapes */
@@ -276,6 +280,8 @@ int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
  * stream-ordered scratch for the transposed weights (~220 KB). */
 int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M, float *Y,
                     void *stream);
+/* W1t = W1^T [256][192], W2t = W2^T [256][256] (BF16, caller-owned). */
+int pasur_mlp_transpose(const pasur_mlp_weights *w, uint16_t *W1t, uint16_t *W2t, void *stream);
 /* Gradients of the loss with respect to the weights given dY [M][2] (FP32);
  * dY is rounded to BF16 for the GEMMs.  Uses stream-ordered scratch. */
 int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X, const uint16_t *H1,
@@ -318,11 +324,15 @@ int pasur_cfr_warm_init(const pasur_fgt *fgt, const pasur_cfr_state *st, int lev
  * forward pass over all of them, and sigma / R / Sbar of those levels as in
  * pasur_cfr_warm_init (one launch); deeper levels keep their initial state.
  * `gt` must be the game tree `fgt` was unfolded from.  Uses stream-ordered
- * scratch (rows x 192 BF16 + rows x 2 FP32); the forward pass is
- * pasur_mlp_infer. */
+ * the caller's workspace when it is large enough, else stream-ordered scratch
+ * (rows x 192 BF16 + rows x 2 FP32); the forward pass is pasur_mlp_infer. */
 int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt, const pasur_cfr_state *st,
                            const pasur_mlp_weights *w, int max_level, float kappa_r,
-                           float kappa_s, void *stream);
+                           float kappa_s, void *workspace, int64_t workspace_bytes,
+                           void *stream);
+/* Bytes of device workspace pasur_warm_start_round needs for max_level (a
+ * smaller or NULL workspace makes it allocate stream-ordered scratch). */
+int64_t pasur_warm_start_workspace_bytes(const pasur_fgt *fgt, int max_level);
 
 /* Training-data helpers: dst[i] = (float)src[idx[i]] (idx NULL: src[i]) for
  * a `dtype` array; dst[i] = src[i] + add for int32 offsets. */

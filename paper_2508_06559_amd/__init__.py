@@ -100,8 +100,12 @@ def lib():
         L.pasur_sample_parents.argtypes = [vp, i32, C.c_uint64, C.c_double, vp, vp,
                                            C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
         L.pasur_cfr_warm_init.argtypes = [vp, vp, i32, vp, C.c_float, C.c_float, vp]
-        L.pasur_warm_start_round.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, vp]
+        L.pasur_warm_start_round.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, vp, i64,
+                                             vp]
+        L.pasur_warm_start_workspace_bytes.restype = i64
+        L.pasur_warm_start_workspace_bytes.argtypes = [vp, i32]
         L.pasur_mlp_infer.argtypes = [vp, vp, i64, vp, vp]
+        L.pasur_mlp_transpose.argtypes = [vp, vp, vp, vp]
         L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
         L.pasur_shift_i32.argtypes = [vp, i64, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
@@ -370,7 +374,7 @@ class Plan:
 
 class MlpWeights(C.Structure):
     _fields_ = [("W1", C.c_void_p), ("b1", C.c_void_p), ("W2", C.c_void_p), ("b2", C.c_void_p),
-                ("W3", C.c_void_p), ("b3", C.c_void_p)]
+                ("W3", C.c_void_p), ("b3", C.c_void_p), ("W1t", C.c_void_p), ("W2t", C.c_void_p)]
 
 
 class MlpGrads(C.Structure):
@@ -433,11 +437,21 @@ def cfr_warm_init(st: CfrState, level: int, Y, kappa_r: float, kappa_s: float, s
                                      _stream(stream)), "pasur_cfr_warm_init")
 
 
+def warm_start_workspace_bytes(fgt: UnfoldedTree, max_level: int) -> int:
+    return int(lib().pasur_warm_start_workspace_bytes(fgt.h, max_level))
+
+
 def warm_start_round(gt: GameTree, st: CfrState, w: MlpWeights, max_level: int, kappa_r: float,
-                     kappa_s: float, stream=None):
+                     kappa_s: float, workspace=None, stream=None):
+    nbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     _check(lib().pasur_warm_start_round(gt.h, st.fgt.h, C.byref(st.c), C.byref(w), max_level,
-                                        kappa_r, kappa_s, _stream(stream)),
+                                        kappa_r, kappa_s, _p(workspace), nbytes, _stream(stream)),
            "pasur_warm_start_round")
+
+
+def mlp_transpose(w: MlpWeights, W1t, W2t, stream=None):
+    _check(lib().pasur_mlp_transpose(C.byref(w), _p(W1t), _p(W2t), _stream(stream)),
+           "pasur_mlp_transpose")
 
 
 def gather_f32(src, dtype: int, idx, n: int, dst, stream=None):

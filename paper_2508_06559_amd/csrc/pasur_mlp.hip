@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 using namespace pasur;
@@ -17,6 +18,8 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 namespace {
 
 constexpr int kIn = 192, kHid = 256, kOut = 2;
+constexpr int kMaxDevices = 64;
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // 80-byte LDS rows keep 16-byte alignment
 
 struct GemmArgs {
@@ -761,9 +764,27 @@ extern "C" int pasur_shift_i32(const int32_t *src, int64_t n, int32_t add, int32
   return PASUR_OK;
 }
 
+namespace {
+int64_t warm_rows(const pasur_fgt *fgt, int max_level) {
+  int64_t rows = 0;
+  for (int l = 1; l <= max_level; ++l) rows += fgt->n[l];
+  return rows;
+}
+int64_t warm_bytes(int64_t rows) {
+  return (int64_t)align_up((size_t)rows * kIn * sizeof(__bf16), 256) +
+         (int64_t)align_up((size_t)rows * kOut * sizeof(float), 256);
+}
+}  // namespace
+
+extern "C" int64_t pasur_warm_start_workspace_bytes(const pasur_fgt *fgt, int max_level) {
+  if (!fgt || max_level < 1 || max_level > 8) return -1;
+  return warm_bytes(warm_rows(fgt, max_level));
+}
+
 extern "C" int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt,
                                       const pasur_cfr_state *st, const pasur_mlp_weights *w,
-                                      int max_level, float kappa_r, float kappa_s, void *stream) {
+                                      int max_level, float kappa_r, float kappa_s,
+                                      void *workspace, int64_t workspace_bytes, void *stream) {
   if (!gt || !fgt || !st || !w) {
     set_error("null argument");
     return PASUR_E_INVAL;
@@ -804,8 +825,15 @@ extern "C" int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt,
   for (int b = 0; b < 8; ++b) hc.card[b] = gt->deck[4 + 8 * gt->round + b];
   __bf16 *X = nullptr;
   float *Y = nullptr;
-  hipError_t e = hipMallocAsync((void **)&X, sizeof(__bf16) * (size_t)rows * kIn, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&Y, sizeof(float) * (size_t)rows * kOut, s);
+  const bool own = !workspace || workspace_bytes < warm_bytes(rows);
+  hipError_t e = hipSuccess;
+  if (own) {
+    e = hipMallocAsync((void **)&X, sizeof(__bf16) * (size_t)rows * kIn, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&Y, sizeof(float) * (size_t)rows * kOut, s);
+  } else {
+    X = (__bf16 *)workspace;
+    Y = (float *)((char *)workspace + align_up((size_t)rows * kIn * sizeof(__bf16), 256));
+  }
   int rc = PASUR_OK;
   if (e != hipSuccess) {
     set_error("warm start workspace: %s", hipGetErrorString(e));
@@ -842,9 +870,26 @@ extern "C" int pasur_warm_start_round(const pasur_gt *gt, const pasur_fgt *fgt,
       rc = PASUR_E_HIP;
     }
   }
-  (void)hipFreeAsync(X, s);
-  (void)hipFreeAsync(Y, s);
+  if (own) {
+    (void)hipFreeAsync(X, s);
+    (void)hipFreeAsync(Y, s);
+  }
   return rc;
+}
+
+extern "C" int pasur_mlp_transpose(const pasur_mlp_weights *w, uint16_t *W1t, uint16_t *W2t,
+                                   void *stream) {
+  if (!w || !w->W1 || !w->W2 || !W1t || !W2t) {
+    set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  k_transpose_bf16<<<blocks(kIn * kHid), 256, 0, s>>>((const __bf16 *)w->W1, kIn, kHid,
+                                                      (__bf16 *)W1t);
+  k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid,
+                                                       (__bf16 *)W2t);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
 }
 
 extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
@@ -855,26 +900,42 @@ extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, in
   }
   if (M == 0) return PASUR_OK;
   hipStream_t s = (hipStream_t)stream;
-  __bf16 *Wt = nullptr;
-  hipError_t e = hipMallocAsync((void **)&Wt, sizeof(__bf16) * (size_t)(kIn + kHid) * kHid, s);
-  if (e != hipSuccess) {
-    set_error("MLP inference workspace: %s", hipGetErrorString(e));
-    return PASUR_E_NOMEM;
+  // the kernel's LDS exceeds the default limit: raise it once per device
+  static std::once_flag lds_once[kMaxDevices];
+  static hipError_t lds_err[kMaxDevices];
+  int dev = 0;
+  PASUR_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d beyond the supported %d", dev, kMaxDevices);
+    return PASUR_E_RANGE;
   }
-  __bf16 *W1t = Wt, *W2t = Wt + (size_t)kIn * kHid;
-  k_transpose_bf16<<<blocks(kIn * kHid), 256, 0, s>>>((const __bf16 *)w->W1, kIn, kHid, W1t);
-  k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid, W2t);
-  e = hipFuncSetAttribute((const void *)k_mlp_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)kInferLds);
-  if (e != hipSuccess) {
-    (void)hipFreeAsync(Wt, s);
-    set_error("MLP inference LDS: %s", hipGetErrorString(e));
+  std::call_once(lds_once[dev], [&] {
+    lds_err[dev] = hipFuncSetAttribute((const void *)k_mlp_infer,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInferLds);
+  });
+  if (lds_err[dev] != hipSuccess) {
+    set_error("MLP inference LDS: %s", hipGetErrorString(lds_err[dev]));
     return PASUR_E_HIP;
+  }
+  __bf16 *Wt = nullptr;
+  const __bf16 *W1t = (const __bf16 *)w->W1t, *W2t = (const __bf16 *)w->W2t;
+  hipError_t e = hipSuccess;
+  if (!W1t || !W2t) {
+    e = hipMallocAsync((void **)&Wt, sizeof(__bf16) * (size_t)(kIn + kHid) * kHid, s);
+    if (e != hipSuccess) {
+      set_error("MLP inference workspace: %s", hipGetErrorString(e));
+      return PASUR_E_NOMEM;
+    }
+    W1t = Wt;
+    W2t = Wt + (size_t)kIn * kHid;
+    k_transpose_bf16<<<blocks(kIn * kHid), 256, 0, s>>>((const __bf16 *)w->W1, kIn, kHid, Wt);
+    k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid,
+                                                         Wt + (size_t)kIn * kHid);
   }
   k_mlp_infer<<<(unsigned)((M + IM - 1) / IM), 256, kInferLds, s>>>(
       (int)M, (const __bf16 *)X, W1t, w->b1, W2t, w->b2, (const __bf16 *)w->W3, w->b3, Y);
   e = hipGetLastError();
-  (void)hipFreeAsync(Wt, s);
+  if (Wt) (void)hipFreeAsync(Wt, s);
   if (e != hipSuccess) {
     set_error("MLP inference: %s", hipGetErrorString(e));
     return PASUR_E_HIP;

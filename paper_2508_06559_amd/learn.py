@@ -23,7 +23,8 @@ import numpy as np
 from . import (PASUR_F32, PASUR_F64, MlpGrads, MlpWeights, CfrState, adam_step, average_strategy,
                cfr_init, cfr_iterate, cfr_warm_init, edge_features, gather_f32, leaf_utilities,
                mlp_backward, mlp_forward, mlp_infer, mlp_loss, paper_params, round_values, sample_parents,
-               shift_i32, warm_start_round as _warm_start_round, _torch)
+               shift_i32, mlp_transpose, warm_start_round as _warm_start_round,
+               warm_start_workspace_bytes, _torch)
 from .solver import SubgameSolver
 
 N_IN, N_HID, N_OUT = 192, 256, 2
@@ -65,6 +66,10 @@ class WarmStartMLP:
         self.g = [torch.zeros_like(t) for t in self.master]
         self.step = 0
         self._bufs = {}
+        self._version = 0      # bumped whenever the BF16 weights change
+        self._tversion = -1    # version the transposed copies were made from
+        self._wt = None
+        self._ws = None
 
     def set_weights(self, W: Sequence[np.ndarray]):
         """Load FP32 weights (W1, b1, W2, b2, W3, b3) and their BF16 copies."""
@@ -72,11 +77,33 @@ class WarmStartMLP:
         self.master = [torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda") for a in W]
         self.bf = {k: torch.from_numpy(_bf16_bits(np.asarray(W[k], np.float32)).copy()).cuda()
                    for k in (0, 2, 4)}
+        self._version += 1
 
     def weights(self) -> MlpWeights:
         m, b = self.master, self.bf
         return MlpWeights(b[0].data_ptr(), m[1].data_ptr(), b[2].data_ptr(), m[3].data_ptr(),
-                          b[4].data_ptr(), m[5].data_ptr())
+                          b[4].data_ptr(), m[5].data_ptr(), None, None)
+
+    def infer_weights(self) -> MlpWeights:
+        """Weights with transposed W1/W2 copies for pasur_mlp_infer, refreshed
+        when the weights changed since they were made."""
+        torch = self.torch
+        if self._wt is None:
+            self._wt = (torch.empty((N_HID, N_IN), dtype=torch.int16, device="cuda"),
+                        torch.empty((N_HID, N_HID), dtype=torch.int16, device="cuda"))
+        if self._tversion != self._version:
+            mlp_transpose(self.weights(), self._wt[0], self._wt[1])
+            self._tversion = self._version
+        w = self.weights()
+        w.W1t, w.W2t = self._wt[0].data_ptr(), self._wt[1].data_ptr()
+        return w
+
+    def workspace(self, nbytes: int):
+        """A reused device buffer of at least nbytes (grown by doubling)."""
+        if self._ws is None or self._ws.numel() < nbytes:
+            cap = max(nbytes, 2 * (self._ws.numel() if self._ws is not None else 0))
+            self._ws = self.torch.empty(cap, dtype=self.torch.uint8, device="cuda")
+        return self._ws
 
     def grads(self) -> MlpGrads:
         g = self.g
@@ -114,6 +141,7 @@ class WarmStartMLP:
         for k in range(6):
             adam_step(self.master[k], self.g[k], self.m[k], self.v[k], self.bf.get(k), lr,
                       betas[0], betas[1], eps, self.step)
+        self._version += 1
         return loss
 
     def state_dict(self):
@@ -158,8 +186,10 @@ def make_units(solver: SubgameSolver, seed: int, parents_per_level: int = 400) -
 def warm_start_round(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float,
                      max_level: int = 8):
     """Predict the logits of levels 1..max_level and seed sigma, R and Sbar
-    (after cfr_init): one libpasur call (features, forward pass, warm init)."""
-    _warm_start_round(rr.gt, rr.state, model.weights(), max_level, kappa_r, kappa_s)
+    (after cfr_init): one libpasur call (features, fused forward pass, warm
+    init) with the model's cached transposed weights and reused workspace."""
+    ws = model.workspace(warm_start_workspace_bytes(rr.fgt, max_level))
+    _warm_start_round(rr.gt, rr.state, model.infer_weights(), max_level, kappa_r, kappa_s, ws)
 
 
 def warm_start_round_by_level(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float):

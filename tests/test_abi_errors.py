@@ -119,10 +119,10 @@ def test_mlp_checks(lib):
     expect(lib, inf(DUMMY, None, 4, DUMMY, None), E_INVAL, ["inference"])
     expect(lib, inf(DUMMY, DUMMY, 1 << 40, DUMMY, None), E_INVAL, ["inference"])
     ws = lib.pasur_warm_start_round
-    ws.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, vp]
-    expect(lib, ws(None, DUMMY, DUMMY, DUMMY, 4, 0.0, 0.0, None), E_INVAL, ["null"])
-    expect(lib, ws(DUMMY, DUMMY, DUMMY, DUMMY, 9, 0.0, 0.0, None), E_RANGE, ["max_level 9"])
-    expect(lib, ws(DUMMY, DUMMY, DUMMY, DUMMY, 0, 0.0, 0.0, None), E_RANGE, ["max_level 0"])
+    ws.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, vp, C.c_int64, vp]
+    expect(lib, ws(None, DUMMY, DUMMY, DUMMY, 4, 0.0, 0.0, None, 0, None), E_INVAL, ["null"])
+    expect(lib, ws(DUMMY, DUMMY, DUMMY, DUMMY, 9, 0.0, 0.0, None, 0, None), E_RANGE, ["max_level 9"])
+    expect(lib, ws(DUMMY, DUMMY, DUMMY, DUMMY, 0, 0.0, 0.0, None, 0, None), E_RANGE, ["max_level 0"])
     ad = lib.pasur_adam_step
     ad.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
                    C.c_int64, vp]

@@ -165,11 +165,15 @@ def test_mlp_infer_matches_oracle_and_forward(M):
     dX = bf16_tensor(X)
     Y = torch.empty((M, 2), dtype=torch.float32, device="cuda")
     pa.mlp_infer(model.weights(), dX, M, Y)
+    # with the model's cached transposed weights: the same result
+    Y2 = torch.empty((M, 2), dtype=torch.float32, device="cuda")
+    pa.mlp_infer(model.infer_weights(), dX, M, Y2)
     b = model._buffers(M)
     pa.mlp_forward(model.weights(), dX, M, b["H1"], b["H2"], b["Y"])
     torch.cuda.synchronize()
     _, H2o, Yo = omlp.forward(W, X, bf16=True)
     Yi = to_np(Y).astype(np.float64)
+    assert np.array_equal(Yi, to_np(Y2).astype(np.float64))
     Yf = to_np(b["Y"][:M]).astype(np.float64)
     scale = np.abs(Yo).max() + 1
     assert np.abs(Yi - Yo).max() <= 1e-2 * scale
