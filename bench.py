@@ -30,17 +30,24 @@ METRIC = "CFR node-updates/s at 1 GPU; secs to exploitability 1e-3, warm-start v
 # while the kernel source is unchanged.
 TRAFFIC = {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
            "sha256": "3d61e3c8630a33e8b5152bc8be7c4d7ff42bdc0c6cc21da5b4dd3fdf34ca4ac8",
-           "bytes_per_launch": 4.53e6}
+           # average per k_cfr_seg launch, two-round subgame of deal 1 (two launches)
+           "two-round": 4.53e6,
+           # the batched solve's largest launch (round 6 of all 64 deals)
+           "batched": 1.226e12}
 
 
-def counted_traffic(args):
+def counted_traffic(args, workload="two-round"):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (copy
+    calibrated), valid only for the kernel source they were taken on."""
     import hashlib
     path = os.path.join(ROOT, TRAFFIC["source"])
     with open(path, "rb") as fh:
         same = hashlib.sha256(fh.read()).hexdigest() == TRAFFIC["sha256"]
-    if same and args.state == "f32" and args.sched == "root" and args.block in (0, 1024):
-        return TRAFFIC["bytes_per_launch"]
-    return None
+    if not same or args.state != "f32":
+        return None
+    if workload == "two-round" and (args.sched != "root" or args.block not in (0, 1024)):
+        return None
+    return TRAFFIC[workload]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -173,7 +180,7 @@ def bench_batched(args):
         "roofline": {"bound": "hbm", "kernel": f"k_cfr_seg ({'float' if T == 4 else 'double'} state), "
                                              f"largest launch",
                      "achieved": db / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": db / dt / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": db / dt / 1e9 / HBM_PEAK_GBS, "traffic": counted_traffic(args, "batched"),
                      "avg_launch_us": dt * 1e6, "algorithmic_bytes_per_launch": db,
                      "all_sweeps_GBs": tot_b / tot_t / 1e9},
     }

@@ -97,6 +97,11 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       }
 }
 
+int gemm(GemmArgs g, int splits, hipStream_t s);
+
+// out[n] = sum over rows of X[m][n] (part: kColChunks * N floats of scratch)
+void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStream_t s);
+
 int gemm(GemmArgs g, int splits, hipStream_t s) {
   dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)splits);
   k_gemm<<<grid, 256, 0, s>>>(g);
@@ -115,14 +120,20 @@ __global__ void k_split_sum(const float *__restrict__ part, int splits, int64_t 
   out[i] = s;
 }
 
-// Column sums of a row-major [M, N] FP32 matrix (bias gradients), one thread
-// per column, rows in order.
-__global__ void k_col_sum(const float *__restrict__ X, int64_t M, int N, float *__restrict__ out) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
+// Column sums of a row-major [M, N] FP32 matrix (bias gradients) in two
+// deterministic passes: block (x, y) sums rows y*chunk .. of 64 columns
+// (consecutive threads, consecutive columns) into part[y][n]; k_split_sum
+// then adds the kColChunks partials of each column in order.
+constexpr int kColChunks = 128;
+
+__global__ void k_col_sum_part(const float *__restrict__ X, int64_t M, int N, int64_t chunk,
+                               float *__restrict__ part) {
+  const int n = blockIdx.x * 64 + threadIdx.x;
   if (n >= N) return;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min(M, r0 + chunk);
   float s = 0.f;
-  for (int64_t m = 0; m < M; ++m) s += X[m * N + n];
-  out[n] = s;
+  for (int64_t m = r0; m < r1; ++m) s += X[m * N + n];
+  part[(int64_t)blockIdx.y * N + n] = s;
 }
 
 // dH = G * (H > 0) for ReLU layers, FP32 in, BF16 out (also FP32 copy).
@@ -320,6 +331,12 @@ __global__ void k_warm_init_levels(WarmLevels<T> W, const float *__restrict__ Y,
 }
 
 inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStream_t s) {
+  const int64_t chunk = (M + kColChunks - 1) / kColChunks;
+  k_col_sum_part<<<dim3((unsigned)((N + 63) / 64), kColChunks), 64, 0, s>>>(X, M, N, chunk, part);
+  k_split_sum<<<blocks(N), 256, 0, s>>>(part, kColChunks, N, out);
+}
 
 // ---------------------------------------------------------------------------
 // Fused inference: Y = (relu(relu(X W1 + b1) W2 + b2)) W3 + b3 for a tile of
@@ -566,7 +583,7 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     st = dW((const __bf16 *)H2, kHid, dYb, kOut, gr->dW3);
   }
   if (!st) {
-    k_col_sum<<<1, 64, 0, s>>>(dY, m, kOut, gr->db3);
+    col_sum(dY, m, kOut, part, gr->db3, s);
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.M = m; g.N = kHid; g.K = kOut;
@@ -581,7 +598,7 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     st = dW((const __bf16 *)H1, kHid, G2b, kHid, gr->dW2);
   }
   if (!st) {
-    k_col_sum<<<blocks(kHid, 64), 64, 0, s>>>(G2f, m, kHid, gr->db2);
+    col_sum(G2f, m, kHid, part, gr->db2, s);
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.M = m; g.N = kHid; g.K = kHid;
@@ -596,7 +613,7 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     st = dW((const __bf16 *)X, kIn, G1b, kHid, gr->dW1);
   }
   if (!st) {
-    k_col_sum<<<blocks(kHid, 64), 64, 0, s>>>(G1f, m, kHid, gr->db1);
+    col_sum(G1f, m, kHid, part, gr->db1, s);
     e = hipGetLastError();
     if (e != hipSuccess) {
       set_error("MLP backward: %s", hipGetErrorString(e));
