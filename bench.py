@@ -1,15 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark: full-width DCFR node-updates/s on one MI355X.
 
-One step = the whole hot path on one seeded two-round subgame (the last two
-rounds of deal 1, every round-6 card state times every inherited score):
-build both rounds' game trees, unfold them, link the leaves to next-round
-roots, leaf utilities, 2000 DCFR iterations per round (last round first),
-average strategies, round values passed backward, and the composed
-exploitability of the average strategies.  Inputs are resident on the GPU
-before the timed region; K steps are timed between device synchronisations.
+Default workload (two-round): one step = the whole hot path on one seeded
+two-round subgame (the last two rounds of deal 1, every round-6 card state
+times every inherited score): build both rounds' game trees, unfold them,
+link the leaves to next-round roots, leaf utilities, 2000 DCFR iterations
+per round (last round first), average strategies, round values passed
+backward, and the composed exploitability of the average strategies.
+Inputs are resident on the GPU before the timed region; K steps are timed
+between device synchronisations.  Other workloads (--workload): batched (64
+deals in one persistent launch per round, HIP-graph replay), full-game (all
+six rounds of one deal), paper-scale (32 full games as one batch),
+warm-start (learned warm start vs plain DCFR), copy (counter calibration).
 
-Prints one JSON line ("Measurement").
+Prints one JSON line: the metric and its value, the step time, the
+dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
+against the MI355X peak, with counter-measured HBM traffic when recorded
+for this kernel source) and, for the default workload, the FP64 CPU
+oracle's rate on the host (cpu_baseline).
 """
 import argparse
 import json
@@ -26,7 +34,7 @@ METRIC = "CFR node-updates/s at 1 GPU; secs to exploitability 1e-3, warm-start v
 
 # HBM bytes per k_cfr_seg launch of the two-round workload (FP32 state, default
 # schedule) from rocprofv3 FETCH_SIZE / WRITE_SIZE counters, scaled by a
-# plain-copy calibration (profiles/k_cfr_seg_two_round_seed1.md).  Valid only
+# plain-copy calibration (the counter summaries under profiles/).  Valid only
 # while the kernel source is unchanged.
 TRAFFIC = {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
            "sha256": "3d61e3c8630a33e8b5152bc8be7c4d7ff42bdc0c6cc21da5b4dd3fdf34ca4ac8",
@@ -416,8 +424,8 @@ def main():
     ap.add_argument("--schedule-json", default=None, help="where the batched autotuner writes its schedule")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this solver is a single-GPU build "
-              "(see DESIGN.md, 'More than one GPU'); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver shards by roots across GPUs only "
+              "by design, it is not built for several; rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -12,7 +12,8 @@ SOURCES = ["pasur_util.hip", "pasur_tree.hip", "pasur_cfr.hip", "pasur_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
-    # packed FP32 instructions stay off ("Build")
+    # no packed FP32 instructions (the compiler would otherwise form them from
+    # plain float and float2 code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]

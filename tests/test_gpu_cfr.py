@@ -6,7 +6,7 @@ the oracle's operation order, so in practice they agree exactly).
 FP32 state: root values must match within 1e-5; strategies are checked for
 validity (simplex) and quality (exploitability), because ties between
 equally good actions make the split of probability among them depend on
-rounding ("Parity")."""
+rounding (FP32 rounding noise in the regrets exceeds the regret floor)."""
 import numpy as np
 import pytest
 
