@@ -207,6 +207,9 @@ extern __shared__ __align__(16) unsigned char g_lds[];
 // parent (0)
 __shared__ int g_kmax[9];
 __shared__ int g_chunked[9];
+// g_fold[p] = 1: every node of level p has exactly one child, and the up
+// phase of level p+1 is folded into that of level p (no barrier of its own)
+__shared__ int g_fold[9];
 
 // Byte layout of one segment's state in LDS (shared by host sizing and
 // device carving).  Level l occupies one block starting at base[l]: its T
@@ -342,16 +345,55 @@ __device__ __forceinline__ double update_parent(const AS &sg, const AR &Rr, cons
   return uh;
 }
 
+// FindUtility of node q of level F-1 whose only child c is on level F, as
+// update_parent does it for one child: u(q) = 0 + sigma(c) u(c), the regret
+// and average-sum updates of c; sigma(c) stays 1 (max(R, eps) / itself, or
+// 1/k when that sum is 0).  Stores u(q) and returns it as the parent
+// update will read it back (rounded to T).
+template <class T, int F, class SubT>
+__device__ __forceinline__ double fold_single(const SubT &S, int q, const IterK &ik, int variant) {
+  const int mover = (F - 1) & 1;
+  const double sgn = mover == 0 ? 1.0 : -1.0;
+  const int c = (int)S.cbl(F - 1)[q] - S.cb_sub(F - 1);
+  const double opp = mover == 0 ? (double)S.rb(F - 1)[q] : (double)S.ra(F - 1)[q];
+  const double own = mover == 0 ? (double)S.ra(F - 1)[q] : (double)S.rb(F - 1)[q];
+  const T sc = S.sg(F)[c], ucT = S.uu(F)[c], rc = S.Rr(F)[c], bc = S.Sb(F)[c];
+  const double uq = 0.0 + (double)sc * (double)ucT;
+  const double r = sgn * opp * ((double)ucT - uq);
+  double Rq = (double)rc;
+  if (variant == PASUR_DCFR) {
+    const double d = Rq > 0.0 ? ik.dpos : ik.dneg;
+    Rq = d * Rq + r;
+  } else if (variant == PASUR_CFR_PLUS) {
+    Rq = Rq + r;
+    if (Rq < 0.0) Rq = 0.0;
+  } else {
+    Rq = Rq + r;
+  }
+  double add = own * (double)sc;
+  if (variant == PASUR_CFR_PLUS) add *= ik.avg_t;
+  S.Rr(F)[c] = (T)Rq;
+  S.Sb(F)[c] = (T)(ik.avg_w * (double)bc + add);
+  S.sg(F)[c] = (T)1.0;
+  const T uqT = (T)uq;
+  S.uu(F - 1)[q] = uqT;
+  return (double)uqT;
+}
+
 // FindUtility for the parents h0, h0+nt, ... of level l-1 (children on level l).
 template <class T, int L, class SubT>
 __device__ __forceinline__ void up_one(const SubT &S, const IterK &k, int variant, int rm_mode,
-                                       double eps, double &vacc_reg) {
+                                       double eps, double &vacc_reg, bool fold = false) {
   const int mover = (L - 1) & 1;
   int t0 = threadIdx.x;
   asm volatile("" : "+v"(t0));  // per-lane start stays inside the phase (see opaque)
   for (int h = t0; h < S.cnt[L - 1]; h += blockDim.x) {
     const int b = (int)S.cbl(L - 1)[h] - S.cb_sub(L - 1);
     const int e = (int)S.cbl(L - 1)[h + 1] - S.cb_sub(L - 1);
+    if constexpr (L <= 7) {
+      if (fold)
+        for (int q = b; q < e; ++q) (void)fold_single<T, L + 1>(S, q, k, variant);
+    }
     const double opp = mover == 0 ? (double)S.rb(L - 1)[h] : (double)S.ra(L - 1)[h];
     const double own = mover == 0 ? (double)S.ra(L - 1)[h] : (double)S.rb(L - 1)[h];
     const double uh = update_parent<T>(S.sg(L), S.Rr(L), S.Sb(L), S.uu(L), b, e, mover, opp,
@@ -418,7 +460,8 @@ __device__ __forceinline__ int wave_max(int x) {
 // The last child of each group writes the parent's utility.
 template <class T, int L, class SubT>
 __device__ __forceinline__ void up_chunked(const SubT &S, const IterK &ik, int variant,
-                                           int rm_mode, double eps, double &vacc_reg) {
+                                           int rm_mode, double eps, double &vacc_reg,
+                                           bool fold = false) {
   const int mover = (L - 1) & 1;
   const double sgn = mover == 0 ? 1.0 : -1.0;
   const int lane = (int)(threadIdx.x & 63), nw = (int)(blockDim.x >> 6);
@@ -432,7 +475,17 @@ __device__ __forceinline__ void up_chunked(const SubT &S, const IterK &ik, int v
     const bool valid = c0 + lane < c1;
     const int q = valid ? c0 + lane : c1 - 1;
     const int h = (int)S.par(L)[q] - S.par_sub(L);
-    const T sq = S.sg(L)[q], uq = S.uu(L)[q], rq = S.Rr(L)[q], bq = S.Sb(L)[q];
+    const T sq = S.sg(L)[q], rq = S.Rr(L)[q], bq = S.Sb(L)[q];
+    T uq = (T)0;
+    if constexpr (L <= 7) {
+      if (fold) {
+        if (valid) uq = (T)fold_single<T, L + 1>(S, q, ik, variant);
+      } else {
+        uq = S.uu(L)[q];
+      }
+    } else {
+      uq = S.uu(L)[q];
+    }
     const int b = (int)S.cbl(L - 1)[h] - S.cb_sub(L - 1);
     const int e = (int)S.cbl(L - 1)[h + 1] - S.cb_sub(L - 1);
     const double opp = mover == 0 ? (double)S.rb(L - 1)[h] : (double)S.ra(L - 1)[h];
@@ -474,10 +527,12 @@ template <class T, int L, class SubT>
 __device__ __forceinline__ void up_phase(const SubT &S, const IterK &k, int variant, int rm_mode,
                                          double eps, double &vacc_reg) {
   if constexpr (SubT::chunked()) {
+    if (L >= 2 && g_fold[L - 1]) return;  // done by the phase of level L-1
+    const bool fold = L <= 7 && g_fold[L];
     if (g_chunked[L])
-      up_chunked<T, L>(S, k, variant, rm_mode, eps, vacc_reg);
+      up_chunked<T, L>(S, k, variant, rm_mode, eps, vacc_reg, fold);
     else
-      up_one<T, L>(S, k, variant, rm_mode, eps, vacc_reg);
+      up_one<T, L>(S, k, variant, rm_mode, eps, vacc_reg, fold);
   } else {
     up_one<T, L>(S, k, variant, rm_mode, eps, vacc_reg);
   }
@@ -619,6 +674,19 @@ __device__ __forceinline__ void seg_in_lds(const ItemDesc<T> &D, int j0, int nro
       const int x = c * stride;
       S.chk(l)[c] = (uint16_t)(x < cnt[l] ? (int)S.cbl(l - 1)[S.par(l)[x]] : cnt[l]);
     }
+  }
+  // A level whose nodes all have one child folds into the phase above it when
+  // that phase keeps the extra work parallel (one lane per child, or one
+  // child per parent), one level at a time: the absorbing phase is not
+  // itself folded.  Measured: folding into a one-lane-per-parent phase with
+  // larger fan-out serialises the folded updates and costs more than the
+  // barrier it saves.
+  if (tid == 0) {
+    for (int l = 0; l <= 8; ++l) g_fold[l] = 0;
+    for (int f = 8; f >= 2; --f)
+      if (g_kmax[f] == 1 && cnt[f] > 0 && !g_fold[f] &&
+          (g_chunked[f - 1] || g_kmax[f - 1] == 1))
+        g_fold[f - 1] = 1;
   }
   __syncthreads();
   double unused = 0.0;
@@ -858,7 +926,7 @@ int iterate_t(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_par
 constexpr uint32_t kLdsPerWorkgroup = 160 * 1024;
 // static LDS: the global-memory path's pointer table and index offsets, the
 // per-level sibling-group statistics
-constexpr uint32_t kStaticLds = 8 * 9 * sizeof(void *) + 4 * 9 * sizeof(int) + 64;
+constexpr uint32_t kStaticLds = 8 * 9 * sizeof(void *) + 5 * 9 * sizeof(int) + 64;
 
 inline bool paper_variant(int variant, int rm_mode) {
   return variant == PASUR_DCFR && rm_mode == PASUR_RM_FLOOR;
