@@ -37,9 +37,9 @@ METRIC = "CFR node-updates/s at 1 GPU; secs to exploitability 1e-3, warm-start v
 # plain-copy calibration (the counter summaries under profiles/).  Valid only
 # while the kernel source is unchanged.
 TRAFFIC = {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
-           "sha256": "3d61e3c8630a33e8b5152bc8be7c4d7ff42bdc0c6cc21da5b4dd3fdf34ca4ac8",
+           "sha256": "8a5ddb5c77265daad665dce4f88b4a8561c5daf99c8fbfcfc7c9ae652406889c",
            # average per k_cfr_seg launch, two-round subgame of deal 1 (two launches)
-           "two-round": 4.53e6,
+           "two-round": 4.60e6,
            # the batched solve's largest launch (round 6 of all 64 deals)
            "batched": 1.226e12}
 
