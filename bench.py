@@ -11,7 +11,8 @@ Inputs are resident on the GPU before the timed region; K steps are timed
 between device synchronisations.  Other workloads (--workload): batched (64
 deals in one persistent launch per round, HIP-graph replay), full-game (all
 six rounds of one deal), paper-scale (32 full games as one batch),
-warm-start (learned warm start vs plain DCFR), copy (counter calibration).
+warm-start (learned warm start vs plain DCFR), selfplay (games/s and fair
+values on a solved full game), copy (counter calibration).
 
 Prints one JSON line: the metric and its value, the step time, the
 dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
@@ -398,6 +399,85 @@ def bench_warm(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_selfplay(args):
+    """Self-play on the solved full game of seeded deal --full-seed: after an
+    untimed build and solve (--iters per round, default 1000), one step
+    plays --games games in each of three matchups (average strategy vs
+    average strategy, average strategy vs uniform random, uniform random vs
+    average strategy), one pasur_selfplay launch per matchup.  Reports
+    games/s, each matchup's fair value (fraction of games Alex wins) and
+    mean margin, and the exact expected margins of the played profiles."""
+    import torch
+    import paper_2508_06559_amd as pa
+    import synth
+
+    dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
+    iters = 1000 if args.iters == 2000 else args.iters
+    deck, roots = synth.full_game_root(args.full_seed)
+    stream = torch.cuda.Stream()
+    s = pa.SubgameSolver(deck, 0, roots, dtype=dtype, stream=stream)
+    s.solve(iters, pa.paper_params(block=args.block))
+    torch.cuda.synchronize()
+    v_ss = float(s.exploitability()[2][0].item())
+    S, U = pa.PLAY_SIGMA_BAR, pa.PLAY_UNIFORM
+    matchups = {"avg_vs_avg": (S, S), "avg_vs_uniform": (S, U), "uniform_vs_avg": (U, S)}
+    n = args.games
+    margin = {k: torch.empty(n, dtype=torch.int32, device="cuda") for k in matchups}
+    fgts = [rr.fgt for rr in s.rounds]
+    sbars = [rr.state.sigma_bar for rr in s.rounds]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(matchups))]
+    kernel_ms = []
+
+    def play(k, timed):
+        for i, (name, (p_a, p_b)) in enumerate(matchups.items()):
+            ev[2 * i].record(stream)
+            pa.selfplay(fgts, sbars, dtype, 0, n, 1000 * k + i, p_a, p_b, margin[name], stream)
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        if timed:
+            kernel_ms.extend(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(len(matchups)))
+        log(f"[bench] self-play step {k + 1} done")
+
+    for k in range(args.warmup):
+        play(k, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        play(k, True)
+    el = time.perf_counter() - t0
+    stats = {}
+    for name in matchups:
+        m = margin[name].double()
+        stats[name] = {"fair_value": float((m > 0).double().mean().item()),
+                       "mean_margin": float(m.mean().item()),
+                       "stderr": float(m.std().item() / np.sqrt(n))}
+    stats["avg_vs_avg"]["exact_expected_margin"] = v_ss
+    rounds = len(fgts)
+    # algorithmic bytes per game: the path's index reads (a child-begin pair
+    # per level, a leaf score and a link per round) and the margin written;
+    # average-strategy reads come on top and depend on the policy
+    per_game = rounds * (8 * 8 + 4) + (rounds - 1) * 4 + 4
+    dt = float(np.mean(kernel_ms)) * 1e-3
+    achieved = per_game * n / dt / 1e9
+    sizes = s.sizes()
+    s.free()
+    out = {"metric": "self-play games/s at 1 GPU", "value": 3 * n * args.steps / el,
+           "unit": "games/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"self-play on the solved full game of seeded deal {args.full_seed} "
+                                  f"({sum(sum(x) for x in sizes)} nodes, {iters} DCFR iterations per "
+                                  f"round): {n} games per matchup, 3 matchups per step",
+                      "state": args.state, "matchups": stats},
+           "roofline": {"bound": "hbm", "kernel": "k_selfplay (one thread per game, dependent "
+                                                  "child-begin gathers down one path)",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "bytes_per_game": per_game, "kernel_ms_per_launch": dt * 1e3,
+                        "dependent_gathers_per_game": rounds * 8}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -410,7 +490,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game",
-                                           "paper-scale", "copy"],
+                                           "paper-scale", "selfplay", "copy"],
                     default="two-round",
                     help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
@@ -418,6 +498,7 @@ def main():
     ap.add_argument("--test-deals", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--deals", type=int, default=32, help="paper-scale: number of full games")
+    ap.add_argument("--games", type=int, default=1 << 24, help="selfplay: games per matchup")
     ap.add_argument("--full-seed", type=int, default=40, help="full-game: the seeded deal")
     ap.add_argument("--warm-levels", default="3,2,4,8",
                     help="warm-start: comma list of max_level values (levels 1..L predicted); the first is reported")
@@ -441,6 +522,8 @@ def main():
         return bench_full(args)
     if args.workload == "paper-scale":
         return bench_paper_scale(args)
+    if args.workload == "selfplay":
+        return bench_selfplay(args)
     if args.workload == "copy":
         # calibration for hardware byte counters: a plain device copy of a
         # known size (256 MiB read + 256 MiB written per launch, 4 launches)

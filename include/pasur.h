@@ -241,6 +241,25 @@ int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
                       void *const sigma[9], int mode, double *d_out,
                       void *stream);
 
+/* ---- f2: self-play (section "Experimental Evaluation") ---------------------
+ * n_games independent games on one solved subgame, one GPU thread each, from
+ * root `root` of the first round: at each decision the player to move (Alex
+ * at even levels) samples one child, by inverse CDF of the average strategy
+ * (sigma_bar[r*9 + l], levels 1..8 of round slot r, dtype as the solver
+ * state) or uniformly; at a round's last level the game adds the leaf's
+ * round points (PASUR_FGT_LEAF_BASE) and continues at the linked next-round
+ * root.  d_margin[g] = Alex's points minus Bob's over the rounds played; the
+ * fair value is the fraction of games with margin > 0.  Draw i = g*64 +
+ * round_slot*8 + level of a counter-based SplitMix64 stream (the published
+ * finaliser of seed + (i+1)*0x9E3779B97F4A7C15) gives u = (z >> 11) / 2^53;
+ * the sampled child is the first whose running FP64 sum of sigma_bar exceeds
+ * u * total (uniform: floor(u * k)); forced moves draw nothing.  fgts are
+ * consecutive rounds ending at the subgame's last round. */
+enum { PASUR_PLAY_SIGMA_BAR = 0, PASUR_PLAY_UNIFORM = 1 };
+int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds, const void *const *sigma_bar,
+                   int dtype, int root, int64_t n_games, uint64_t seed, int policy_a,
+                   int policy_b, int32_t *d_margin, void *stream);
+
 /* ---- a13: learned warm start ------------------------------------------------
  * Not in the paper (its learned model is an XGBoost regressor on infoset
  * rows).  A 192-256-256-2 MLP: input = the child node's card state (Alex's

@@ -106,6 +106,7 @@ def lib():
         L.pasur_warm_start_workspace_bytes.argtypes = [vp, i32]
         L.pasur_mlp_infer.argtypes = [vp, vp, i64, vp, vp]
         L.pasur_mlp_transpose.argtypes = [vp, vp, vp, vp]
+        L.pasur_selfplay.argtypes = [vp, i32, vp, i32, i32, i64, C.c_uint64, i32, i32, vp, vp]
         L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
         L.pasur_shift_i32.argtypes = [vp, i64, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
@@ -452,6 +453,24 @@ def warm_start_round(gt: GameTree, st: CfrState, w: MlpWeights, max_level: int, 
 def mlp_transpose(w: MlpWeights, W1t, W2t, stream=None):
     _check(lib().pasur_mlp_transpose(C.byref(w), _p(W1t), _p(W2t), _stream(stream)),
            "pasur_mlp_transpose")
+
+
+PLAY_SIGMA_BAR, PLAY_UNIFORM = 0, 1
+
+
+def selfplay(fgts, sigma_bars, dtype: int, root: int, n_games: int, seed: int, policy_a: int,
+             policy_b: int, margin, stream=None):
+    """fgts: UnfoldedTree of consecutive rounds; sigma_bars[r][l] (l = 1..8)
+    device tensors of the average strategies; margin: int32 device tensor of
+    n_games entries (pasur_selfplay)."""
+    n = len(fgts)
+    hs = (C.c_void_p * n)(*[f.h for f in fgts])
+    sb = (C.c_void_p * (9 * n))()
+    for r in range(n):
+        for l in range(1, 9):
+            sb[9 * r + l] = _p(sigma_bars[r][l])
+    _check(lib().pasur_selfplay(hs, n, sb, dtype, root, n_games, seed & ((1 << 64) - 1), policy_a,
+                                policy_b, _p(margin), _stream(stream)), "pasur_selfplay")
 
 
 def gather_f32(src, dtype: int, idx, n: int, dst, stream=None):

@@ -1,0 +1,164 @@
+// pasur_play.hip -- self-play with average strategies: the paper's way of
+// estimating a deal's fair value (section "Experimental Evaluation").  One
+// thread per game walks the unfolded trees of a solved subgame from a root:
+// at each decision the player to move samples one child (inverse CDF of the
+// average strategy, or uniformly at random); at a round's last level the
+// game adds the leaf's round points and continues at the linked next-round
+// root.  Random numbers come from a counter-based SplitMix64 stream, so any
+// game can be replayed on its own.
+#include "pasur_internal.hpp"
+
+#include <cstring>
+
+using namespace pasur;
+
+namespace {
+
+constexpr int kMaxRounds = 6;
+
+struct PlayRound {
+  const int32_t *cb[8];
+  const void *sbar[9];
+  const int32_t *link;
+  const int16_t *base;
+};
+
+struct PlayArgs {
+  PlayRound r[kMaxRounds];
+  int n_rounds, dtype, policy[2], root;
+  uint64_t seed;
+  int64_t n_games;
+};
+
+// The i-th output of SplitMix64 started at `seed` (its state after i + 1
+// steps, through the generator's finaliser), as a double in [0, 1).
+__device__ inline double splitmix_uniform(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Index of the sampled child among k (k >= 2) whose average strategy is
+// p[0..k-1]: the first whose running sum (FP64, in child order) exceeds
+// u * total; uniform choice when the policy is uniform or the total is 0.
+template <class T>
+__device__ inline int choose(double u, const T *__restrict__ p, int k, int policy) {
+  const int uni = min((int)(u * (double)k), k - 1);
+  if (policy == PASUR_PLAY_UNIFORM) return uni;
+  double total = 0.0;
+  for (int c = 0; c < k; ++c) total += (double)p[c];
+  if (!(total > 0.0)) return uni;
+  const double x = u * total;
+  double acc = 0.0;
+  int last = 0;
+  for (int c = 0; c < k; ++c) {
+    const double pc = (double)p[c];
+    acc += pc;
+    if (pc > 0.0) last = c;
+    if (acc > x) return c;
+  }
+  return last;
+}
+
+template <class T>
+__global__ void k_selfplay(PlayArgs a, int32_t *__restrict__ margin) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.n_games) return;
+  int32_t q = a.root;
+  int32_t m = 0;
+  for (int r = 0; r < a.n_rounds; ++r) {
+    const PlayRound &R = a.r[r];
+    for (int l = 0; l < 8; ++l) {
+      const int32_t b = R.cb[l][q], e = R.cb[l][q + 1];
+      const int k = e - b;
+      int c = 0;
+      if (k > 1) {
+        const double u = splitmix_uniform(a.seed, (uint64_t)g * 64u + (uint64_t)(r * 8 + l));
+        c = choose<T>(u, reinterpret_cast<const T *>(R.sbar[l + 1]) + b, k, a.policy[l & 1]);
+      }
+      q = b + c;
+    }
+    m += R.base[q];
+    if (r + 1 < a.n_rounds) q = R.link[q];
+  }
+  margin[g] = m;
+}
+
+}  // namespace
+
+extern "C" int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds,
+                              const void *const *sigma_bar, int dtype, int root,
+                              int64_t n_games, uint64_t seed, int policy_a, int policy_b,
+                              int32_t *d_margin, void *stream) {
+  if (!fgts || !sigma_bar || !d_margin || n_games < 0) {
+    set_error("null argument or negative game count");
+    return PASUR_E_INVAL;
+  }
+  if (n_rounds < 1 || n_rounds > kMaxRounds) {
+    set_error("n_rounds %d outside 1..%d", n_rounds, kMaxRounds);
+    return PASUR_E_RANGE;
+  }
+  if (dtype != PASUR_F32 && dtype != PASUR_F64) {
+    set_error("unknown dtype %d", dtype);
+    return PASUR_E_RANGE;
+  }
+  for (int p : {policy_a, policy_b}) {
+    if (p != PASUR_PLAY_SIGMA_BAR && p != PASUR_PLAY_UNIFORM) {
+      set_error("unknown policy %d", p);
+      return PASUR_E_RANGE;
+    }
+  }
+  PlayArgs a;
+  std::memset(&a, 0, sizeof(a));
+  for (int r = 0; r < n_rounds; ++r) {
+    const pasur_fgt *f = fgts[r];
+    if (!f) {
+      set_error("fgts[%d] is NULL", r);
+      return PASUR_E_INVAL;
+    }
+    if (r > 0 && f->round != fgts[r - 1]->round + 1) {
+      set_error("rounds must be consecutive");
+      return PASUR_E_INVAL;
+    }
+    if (r + 1 < n_rounds && f->round == 5) {
+      set_error("round 5 is the last round");
+      return PASUR_E_INVAL;
+    }
+    for (int l = 0; l < 8; ++l) a.r[r].cb[l] = f->child_begin[l];
+    for (int l = 1; l <= 8; ++l) {
+      a.r[r].sbar[l] = sigma_bar[r * 9 + l];
+      if (!a.r[r].sbar[l]) {
+        set_error("sigma_bar[%d][%d] is NULL", r, l);
+        return PASUR_E_INVAL;
+      }
+    }
+    if ((r + 1 < n_rounds && !f->link) || !f->leaf_base) {
+      set_error("tree of round %d has no %s", f->round, f->leaf_base ? "link table" : "leaf scores");
+      return PASUR_E_INVAL;
+    }
+    a.r[r].link = f->link;
+    a.r[r].base = f->leaf_base;
+  }
+  if (root < 0 || root >= fgts[0]->n[0]) {
+    set_error("root %d outside 0..%lld", root, (long long)fgts[0]->n[0] - 1);
+    return PASUR_E_RANGE;
+  }
+  if (n_games == 0) return PASUR_OK;
+  a.n_rounds = n_rounds;
+  a.dtype = dtype;
+  a.policy[0] = policy_a;
+  a.policy[1] = policy_b;
+  a.root = root;
+  a.seed = seed;
+  a.n_games = n_games;
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned grid = (unsigned)((n_games + 255) / 256);
+  if (dtype == PASUR_F32)
+    k_selfplay<float><<<grid, 256, 0, s>>>(a, d_margin);
+  else
+    k_selfplay<double><<<grid, 256, 0, s>>>(a, d_margin);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}

@@ -12,7 +12,8 @@ from __future__ import annotations
 from dataclasses import dataclass
 from typing import List, Optional
 
-from . import (PASUR_F32, PASUR_F64, TV_BR_A, TV_BR_B, TV_EXPECT, V_ITERATE_MEAN, CfrState,
+from . import (PASUR_F32, PASUR_F64, PLAY_SIGMA_BAR, TV_BR_A, TV_BR_B, TV_EXPECT, V_ITERATE_MEAN,
+               CfrState, selfplay,
                Plan, UnfoldedTree, average_strategy, build_round_tree, cfr_init, cfr_iterate,
                leaf_utilities, paper_params, round_values, roots_to_device, tree_values,
                unfold_scores, _torch)
@@ -92,6 +93,20 @@ class SubgameSolver:
                 V = res
             out[mode] = V
         return out[TV_BR_A], out[TV_BR_B], out[TV_EXPECT]
+
+    def selfplay(self, n_games: int, seed: int, policy_a: int = PLAY_SIGMA_BAR,
+                 policy_b: int = PLAY_SIGMA_BAR, root: int = 0, strategies=None):
+        """Margins (Alex minus Bob, int32 device tensor) of n_games self-play
+        games from start-round root `root` (pasur_selfplay).  A non-uniform
+        player samples from the solved average strategies, or from
+        `strategies[r][l]` (per round, levels 1..8, the solver's dtype: any
+        per-edge strategy, e.g. a network's prediction) when given."""
+        torch = self.torch
+        margin = torch.empty(max(n_games, 1), dtype=torch.int32, device="cuda")
+        sb = strategies if strategies is not None else [rr.state.sigma_bar for rr in self.rounds]
+        selfplay([rr.fgt for rr in self.rounds], sb, self.dtype, root, n_games, seed, policy_a,
+                 policy_b, margin, self.stream)
+        return margin[:n_games]
 
     def free(self):
         for rr in self.rounds:

@@ -128,3 +128,23 @@ def test_mlp_checks(lib):
                    C.c_int64, vp]
     expect(lib, ad(DUMMY, DUMMY, DUMMY, DUMMY, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None),
            E_INVAL, ["Adam"])
+
+
+def test_selfplay_checks(lib):
+    vp = C.c_void_p
+    f = lib.pasur_selfplay
+    f.argtypes = [vp, C.c_int, vp, C.c_int, C.c_int, C.c_int64, C.c_uint64, C.c_int, C.c_int,
+                  vp, vp]
+    trees = (vp * 2)(8, 8)
+    nulls = (vp * 2)(None, None)
+    sb = (vp * 18)(*([8] * 18))
+    expect(lib, f(None, 1, sb, 0, 0, 4, 1, 0, 0, DUMMY, None), E_INVAL, ["null"])
+    expect(lib, f(trees, 1, None, 0, 0, 4, 1, 0, 0, DUMMY, None), E_INVAL, ["null"])
+    expect(lib, f(trees, 1, sb, 0, 0, 4, 1, 0, 0, None, None), E_INVAL, ["null"])
+    expect(lib, f(trees, 1, sb, 0, 0, -1, 1, 0, 0, DUMMY, None), E_INVAL, ["negative"])
+    expect(lib, f(trees, 0, sb, 0, 0, 4, 1, 0, 0, DUMMY, None), E_RANGE, ["n_rounds 0"])
+    expect(lib, f(trees, 7, sb, 0, 0, 4, 1, 0, 0, DUMMY, None), E_RANGE, ["n_rounds 7"])
+    expect(lib, f(trees, 1, sb, 5, 0, 4, 1, 0, 0, DUMMY, None), E_RANGE, ["dtype 5"])
+    expect(lib, f(trees, 1, sb, 0, 0, 4, 1, 2, 0, DUMMY, None), E_RANGE, ["policy 2"])
+    expect(lib, f(trees, 1, sb, 0, 0, 4, 1, 0, -1, DUMMY, None), E_RANGE, ["policy -1"])
+    expect(lib, f(nulls, 2, sb, 0, 0, 4, 1, 0, 0, DUMMY, None), E_INVAL, ["fgts[0] is NULL"])
