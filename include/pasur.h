@@ -260,6 +260,34 @@ int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds, const void *const
                    int dtype, int root, int64_t n_games, uint64_t seed, int policy_a,
                    int policy_b, int32_t *d_margin, void *stream);
 
+/* ---- f3: external-sampling CFR (section "External Sampling") ---------------
+ * n_iters iterations of external-sampling CFR on one round (the state as
+ * pasur_cfr_init leaves it, u[8] = leaf utilities), continuing after t0
+ * iterations.  An iteration is a pass for Alex, then one for Bob.  In p's
+ * pass the opponent keeps one action per reached node, drawn from its
+ * current strategy (CodeSnippet ExternalSampling: one multinomial draw per
+ * node), and adds that strategy to the average sums Sbar of its children;
+ * p keeps every action.  From the last level up, a reached node of p takes
+ * u = sum of sigma * u over its children, adds u(child) - u to each child's
+ * regret R (u - u(child) for Bob; values are Alex minus Bob) and
+ * regret-matches its children's sigma with `rm_mode` / `eps` as in
+ * pasur_cfr_params; a reached opponent node takes its kept child's value.
+ * Sums are plain (sampling weights cancel); no discounting.  The draw of
+ * the node h of level l in p's pass (p = 0 Alex, 1 Bob) of iteration t
+ * (1-based) is index (2(t-1) + p) * N + off[l] + h of the counter-based
+ * SplitMix64 stream of `seed` (as pasur_selfplay), N = n[0] + ... + n[7],
+ * off[l] = n[0] + ... + n[l-1]; the kept child is the first whose running
+ * FP64 sum of sigma exceeds u * total, and a node with one child draws
+ * nothing.  Values u of unreached nodes are left as they were.  The average
+ * strategy is pasur_average_strategy's normalisation of Sbar.
+ * `workspace` (device, caller-owned) holds one int32 per node of levels
+ * 0..7: pasur_es_workspace_bytes(fgt) bytes (negative on error).  Calls on
+ * one workspace must not overlap.  Asynchronous on `stream`. */
+int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt);
+int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0,
+                     int64_t n_iters, uint64_t seed, int rm_mode, double eps,
+                     void *workspace, int64_t workspace_bytes, void *stream);
+
 /* ---- a13: learned warm start ------------------------------------------------
  * Not in the paper (its learned model is an XGBoost regressor on infoset
  * rows).  A 192-256-256-2 MLP: input = the child node's card state (Alex's

@@ -107,6 +107,9 @@ def lib():
         L.pasur_mlp_infer.argtypes = [vp, vp, i64, vp, vp]
         L.pasur_mlp_transpose.argtypes = [vp, vp, vp, vp]
         L.pasur_selfplay.argtypes = [vp, i32, vp, i32, i32, i64, C.c_uint64, i32, i32, vp, vp]
+        L.pasur_es_workspace_bytes.restype = i64
+        L.pasur_es_workspace_bytes.argtypes = [vp]
+        L.pasur_es_iterate.argtypes = [vp, vp, i64, i64, C.c_uint64, i32, C.c_double, vp, i64, vp]
         L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
         L.pasur_shift_i32.argtypes = [vp, i64, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
@@ -285,6 +288,8 @@ class CfrState:
         self.c = st
         self.sb_ptrs = (C.c_void_p * 9)(*([None] + [t.data_ptr() for t in self.sigma_bar[1:]]))
         self.t = 1
+        self.es_t = 0
+        self.es_ws = None
 
     def bytes(self) -> int:
         ts = [*self.sigma[1:], *self.R[1:], *self.Sbar[1:], *self.reachA[:8], *self.reachB[:8],
@@ -301,6 +306,7 @@ def leaf_utilities(fgt: UnfoldedTree, d_V_next, dtype: int, d_out, stream=None):
 def cfr_init(st: CfrState, stream=None):
     _check(lib().pasur_cfr_init(st.fgt.h, C.byref(st.c), _stream(stream)), "pasur_cfr_init")
     st.t = 1
+    st.es_t = 0
 
 
 def cfr_iterate(st: CfrState, n_iters: int, params: Optional[CfrParams] = None, t0: Optional[int] = None,
@@ -456,6 +462,29 @@ def mlp_transpose(w: MlpWeights, W1t, W2t, stream=None):
 
 
 PLAY_SIGMA_BAR, PLAY_UNIFORM = 0, 1
+
+
+def es_workspace_bytes(fgt: UnfoldedTree) -> int:
+    n = lib().pasur_es_workspace_bytes(fgt.h)
+    if n < 0:
+        _check(int(n), "pasur_es_workspace_bytes")
+    return int(n)
+
+
+def es_iterate(st: CfrState, n_iters: int, seed: int, rm_mode: int = RM_FLOOR, eps: float = 1e-8,
+               t0: Optional[int] = None, stream=None):
+    """n_iters external-sampling CFR iterations on st (pasur_es_iterate),
+    continuing after st.es_t iterations (or t0); the pick workspace is kept
+    on the state."""
+    torch = _torch()
+    nb = es_workspace_bytes(st.fgt)
+    if st.es_ws is None or st.es_ws.numel() < max(nb, 1):
+        st.es_ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    t = st.es_t if t0 is None else t0
+    _check(lib().pasur_es_iterate(st.fgt.h, C.byref(st.c), t, n_iters, seed & ((1 << 64) - 1),
+                                  rm_mode, eps, _p(st.es_ws), st.es_ws.numel(), _stream(stream)),
+           "pasur_es_iterate")
+    st.es_t = t + n_iters
 
 
 def selfplay(fgts, sigma_bars, dtype: int, root: int, n_games: int, seed: int, policy_a: int,

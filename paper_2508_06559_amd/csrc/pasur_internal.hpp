@@ -74,6 +74,40 @@ __host__ __device__ inline void score_unkey(uint32_t k, int *ca, int *cb,
   *d = (int)(k & 0xFF) - 128;
 }
 
+// Sampling shared by self-play and external-sampling CFR.
+// The i-th output of SplitMix64 started at `seed` (its state after i + 1
+// steps, through the generator's finaliser), as a double in [0, 1).
+__device__ inline double splitmix_uniform(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Index of the sampled child among k (k >= 2) whose average strategy is
+// p[0..k-1]: the first whose running sum (FP64, in child order) exceeds
+// u * total; uniform choice when the policy is uniform or the total is 0.
+template <class T>
+__device__ inline int choose(double u, const T *__restrict__ p, int k, int policy) {
+  const int uni = min((int)(u * (double)k), k - 1);
+  if (policy == PASUR_PLAY_UNIFORM) return uni;
+  double total = 0.0;
+  for (int c = 0; c < k; ++c) total += (double)p[c];
+  if (!(total > 0.0)) return uni;
+  const double x = u * total;
+  double acc = 0.0;
+  int last = 0;
+  for (int c = 0; c < k; ++c) {
+    const double pc = (double)p[c];
+    acc += pc;
+    if (pc > 0.0) last = c;
+    if (acc > x) return c;
+  }
+  return last;
+}
+
+
 }  // namespace pasur
 
 // Round game tree, device arrays per level.
