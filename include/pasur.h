@@ -280,13 +280,21 @@ int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds, const void *const
  * FP64 sum of sigma exceeds u * total, and a node with one child draws
  * nothing.  Values u of unreached nodes are left as they were.  The average
  * strategy is pasur_average_strategy's normalisation of Sbar.
- * `workspace` (device, caller-owned) holds one int32 per node of levels
- * 0..7: pasur_es_workspace_bytes(fgt) bytes (negative on error).  Calls on
- * one workspace must not overlap.  Asynchronous on `stream`. */
+ * Schedules (bit-identical results): PASUR_ES_FRONTIER, one persistent
+ * launch for all iterations, each workgroup running a run of consecutive
+ * roots and visiting only the reached nodes (per-level frontier lists);
+ * PASUR_ES_LEVEL, two launches per level and pass over every node.
+ * roots_per_wg: consecutive roots per workgroup of the frontier schedule
+ * (0 = about 4096 tree nodes per workgroup, at least one root).
+ * `workspace` (device, caller-owned) holds two int32 per node of levels
+ * 0..7 (picks and frontier lists): pasur_es_workspace_bytes(fgt) bytes
+ * (negative on error).  Calls on one workspace must not overlap.
+ * Asynchronous on `stream`. */
+enum { PASUR_ES_FRONTIER = 0, PASUR_ES_LEVEL = 1 };
 int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt);
 int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0,
-                     int64_t n_iters, uint64_t seed, int rm_mode, double eps,
-                     void *workspace, int64_t workspace_bytes, void *stream);
+                     int64_t n_iters, uint64_t seed, int rm_mode, double eps, int schedule,
+                     int roots_per_wg, void *workspace, int64_t workspace_bytes, void *stream);
 
 /* ---- a13: learned warm start ------------------------------------------------
  * Not in the paper (its learned model is an XGBoost regressor on infoset

@@ -17,10 +17,20 @@
 // node takes the value of its kept child.  Sampling weights cancel in this
 // scheme, so all sums are plain.
 //
-// Level-synchronous: one launch per level and direction, one thread per
-// node; every launch reads the previous level's picks, so the mask never
-// needs compacting.  Arithmetic is FP64 in registers with the state stored
-// as float or double, in the same order as the definition above.
+// Two schedules give bit-identical results (every update is per node and
+// in a fixed order, whatever order nodes are visited in):
+//  - frontier (default): one persistent launch for all iterations.  Roots
+//    are independent, so each workgroup takes a run of consecutive roots and
+//    runs every iteration on them alone.  Per pass it keeps, for each level,
+//    the list of its reached nodes (the frontier) in global scratch: the
+//    reached nodes of level l + 1 are appended while level l draws (one LDS
+//    counter per level, reserved once per wave), and the up sweep visits the
+//    frontiers only.  Work per pass is proportional to the reached nodes
+//    (about one opponent action in k per opponent level), not the tree.
+//  - level: one launch per level and direction with one thread per node of
+//    the level, reading the previous level's picks (no compaction).
+// Arithmetic is FP64 in registers with the state stored as float or double,
+// in the same order as the definition above.
 #include "pasur_internal.hpp"
 
 #include <cmath>
@@ -47,40 +57,33 @@ struct EsLevel {
   double eps;
 };
 
+// Down step of a reached node h of level l in p's pass: its pick, and for
+// an opponent node the average-sum update and the draw.  Returns the first
+// kept child and sets *k to the number of kept children.
 template <class T>
-__global__ void k_es_down(EsLevel a) {
-  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= a.n) return;
-  bool reached = true;
-  if (a.l > 0) {
-    const int32_t pk = a.pick_up[a.par[h]];
-    reached = pk == kAll || pk == (int32_t)h;
+__device__ __forceinline__ int32_t down_node(const EsLevel &a, int64_t h, int *k) {
+  const int32_t b = a.cb[h], e = a.cb[h + 1];
+  if ((a.l & 1) == a.p) {
+    a.pick[h] = kAll;
+    *k = e - b;
+    return b;
   }
-  int32_t out = kNone;
-  if (reached) {
-    if ((a.l & 1) == a.p) {
-      out = kAll;
-    } else {
-      const int32_t b = a.cb[h], e = a.cb[h + 1];
-      const T *sg = reinterpret_cast<const T *>(a.sigma);
-      T *sb = reinterpret_cast<T *>(a.Sbar);
-      for (int32_t c = b; c < e; ++c) sb[c] = (T)((double)sb[c] + (double)sg[c]);
-      int j = 0;
-      if (e - b > 1)
-        j = choose<T>(splitmix_uniform(a.seed, a.base + (uint64_t)h), sg + b, e - b,
-                      PASUR_PLAY_SIGMA_BAR);
-      out = b + j;
-    }
-  }
-  a.pick[h] = out;
+  const T *sg = reinterpret_cast<const T *>(a.sigma);
+  T *sb = reinterpret_cast<T *>(a.Sbar);
+  for (int32_t c = b; c < e; ++c) sb[c] = (T)((double)sb[c] + (double)sg[c]);
+  int j = 0;
+  if (e - b > 1)
+    j = choose<T>(splitmix_uniform(a.seed, a.base + (uint64_t)h), sg + b, e - b,
+                  PASUR_PLAY_SIGMA_BAR);
+  a.pick[h] = b + j;
+  *k = 1;
+  return b + j;
 }
 
+// Up step of a reached node h of level l (its pick set by the down sweep).
 template <class T>
-__global__ void k_es_up(EsLevel a) {
-  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= a.n) return;
+__device__ __forceinline__ void up_node(const EsLevel &a, int64_t h) {
   const int32_t pk = a.pick[h];
-  if (pk == kNone) return;
   const T *uc = reinterpret_cast<const T *>(a.u_c);
   T *ul = reinterpret_cast<T *>(a.u_l);
   if (pk != kAll) {
@@ -111,35 +114,174 @@ __global__ void k_es_up(EsLevel a) {
 }
 
 template <class T>
+__global__ void k_es_down(EsLevel a) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= a.n) return;
+  if (a.l > 0) {
+    const int32_t pk = a.pick_up[a.par[h]];
+    if (pk != kAll && pk != (int32_t)h) {
+      a.pick[h] = kNone;
+      return;
+    }
+  }
+  int k;
+  (void)down_node<T>(a, h, &k);
+}
+
+template <class T>
+__global__ void k_es_up(EsLevel a) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= a.n) return;
+  if (a.pick[h] == kNone) return;
+  up_node<T>(a, h);
+}
+
+// ---- frontier schedule -------------------------------------------------------
+
+struct EsSegArgs {
+  EsLevel lv[8];               // seed, base (level offset only), l, rm_mode, eps set; p per pass
+  const int32_t *root_off[9];  // level-l node range of each root
+  int32_t *front;              // frontier lists, level l at off[l] (like the picks)
+  int64_t off[9];
+  int64_t n_roots, n_iters, t0;
+  uint64_t N;
+  int roots_per_wg;
+};
+
+// Exclusive offset of this lane's k items in a wave-wide reservation of
+// *counter (LDS); every lane of the wave must call it.
+__device__ __forceinline__ int wave_reserve(int k, int *counter) {
+  int x = k;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if ((int)(threadIdx.x & 63) >= d) x += y;
+  }
+  const int total = __shfl(x, 63, 64);
+  int base = 0;
+  if ((threadIdx.x & 63) == 63 && total > 0) base = atomicAdd(counter, total);
+  base = __shfl(base, 63, 64);
+  return base + x - k;
+}
+
+template <class T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_es_frontier(EsSegArgs a) {
+  __shared__ int cnt[9];
+  __shared__ int64_t seg[9];  // where this workgroup's frontier of each level starts
+  const int64_t r0 = (int64_t)blockIdx.x * a.roots_per_wg;
+  const int64_t r1 = r0 + a.roots_per_wg < a.n_roots ? r0 + a.roots_per_wg : a.n_roots;
+  if (threadIdx.x < 9) seg[threadIdx.x] = a.off[threadIdx.x] + a.root_off[threadIdx.x][r0];
+  for (int64_t it = 0; it < a.n_iters; ++it) {
+    const uint64_t t = (uint64_t)(a.t0 + it + 1);
+    for (int p = 0; p < 2; ++p) {
+      const uint64_t pass_base = (2 * (t - 1) + (uint64_t)p) * a.N;
+      __syncthreads();  // the previous pass has finished with the counters
+      if (threadIdx.x < 9) cnt[threadIdx.x] = 0;
+      __syncthreads();
+#pragma unroll
+      for (int l = 0; l < 8; ++l) {
+        EsLevel lv = a.lv[l];
+        lv.p = p;
+        lv.base = pass_base + (uint64_t)a.off[l];
+        const int m = l == 0 ? (int)(r1 - r0) : cnt[l];
+        for (int i0 = 0; i0 < m; i0 += BLOCK) {
+          const int i = i0 + (int)threadIdx.x;
+          int k = 0;
+          int32_t first = 0;
+          if (i < m) {
+            const int64_t h = l == 0 ? r0 + i : (int64_t)a.front[seg[l] + i];
+            first = down_node<T>(lv, h, &k);
+          }
+          if (l < 7) {
+            const int pos = wave_reserve(k, &cnt[l + 1]);
+            int32_t *dst = a.front + seg[l + 1] + pos;
+            for (int j = 0; j < k; ++j) dst[j] = first + j;
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int l = 7; l >= 0; --l) {
+        EsLevel lv = a.lv[l];
+        lv.p = p;
+        const int m = l == 0 ? (int)(r1 - r0) : cnt[l];
+        for (int i = (int)threadIdx.x; i < m; i += BLOCK) {
+          const int64_t h = l == 0 ? r0 + i : (int64_t)a.front[seg[l] + i];
+          up_node<T>(lv, h);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+void fill_levels(EsLevel lv[8], const pasur_fgt *f, const pasur_cfr_state *st, const int64_t off[9],
+                 int32_t *picks, uint64_t seed, int rm_mode, double eps) {
+  for (int l = 0; l < 8; ++l) {
+    EsLevel &a = lv[l];
+    a.cb = f->child_begin[l];
+    a.par = l > 0 ? f->parent[l] : nullptr;
+    a.pick_up = l > 0 ? picks + off[l - 1] : nullptr;
+    a.pick = picks + off[l];
+    a.sigma = st->sigma[l + 1];
+    a.R = st->R[l + 1];
+    a.Sbar = st->Sbar[l + 1];
+    a.u_l = st->u[l];
+    a.u_c = st->u[l + 1];
+    a.n = f->n[l];
+    a.seed = seed;
+    a.base = (uint64_t)off[l];
+    a.l = l;
+    a.p = 0;
+    a.rm_mode = rm_mode;
+    a.eps = eps;
+  }
+}
+
+constexpr int kFrontierBlock = 256;
+constexpr int64_t kNodesPerWorkgroup = 4096;
+
+template <class T>
 int es_run(const pasur_fgt *f, const pasur_cfr_state *st, int64_t t0, int64_t n_iters,
-           uint64_t seed, int rm_mode, double eps, int32_t *picks, hipStream_t s) {
+           uint64_t seed, int rm_mode, double eps, int schedule, int roots_per_wg, int32_t *ws,
+           hipStream_t s) {
   int64_t off[9];
   off[0] = 0;
   for (int l = 0; l < 8; ++l) off[l + 1] = off[l] + f->n[l];
   const uint64_t N = (uint64_t)off[8];
+  int32_t *picks = ws;
+  if (f->n[0] == 0) return PASUR_OK;
+  if (schedule == PASUR_ES_FRONTIER) {
+    EsSegArgs a;
+    fill_levels(a.lv, f, st, off, picks, seed, rm_mode, eps);
+    for (int l = 0; l < 9; ++l) {
+      a.root_off[l] = f->root_off[l];
+      a.off[l] = off[l];
+    }
+    a.front = ws + N;
+    a.n_roots = f->n_roots;
+    a.n_iters = n_iters;
+    a.t0 = t0;
+    a.N = N;
+    int64_t total = 0;
+    for (int l = 0; l < 9; ++l) total += f->n[l];
+    int64_t per = kNodesPerWorkgroup * f->n_roots / (total > 0 ? total : 1);
+    if (roots_per_wg > 0) per = roots_per_wg;
+    a.roots_per_wg = (int)(per < 1 ? 1 : per > f->n_roots ? f->n_roots : per);
+    const unsigned grid = (unsigned)((f->n_roots + a.roots_per_wg - 1) / a.roots_per_wg);
+    k_es_frontier<T, kFrontierBlock><<<grid, kFrontierBlock, 0, s>>>(a);
+    PASUR_TRY_HIP(hipGetLastError());
+    return PASUR_OK;
+  }
+  EsLevel lv[8];
+  fill_levels(lv, f, st, off, picks, seed, rm_mode, eps);
   for (int64_t it = 0; it < n_iters; ++it) {
     const uint64_t t = (uint64_t)(t0 + it + 1);
     for (int p = 0; p < 2; ++p) {
       const uint64_t pass_base = (2 * (t - 1) + (uint64_t)p) * N;
-      EsLevel lv[8];
       for (int l = 0; l < 8; ++l) {
-        EsLevel &a = lv[l];
-        a.cb = f->child_begin[l];
-        a.par = l > 0 ? f->parent[l] : nullptr;
-        a.pick_up = l > 0 ? picks + off[l - 1] : nullptr;
-        a.pick = picks + off[l];
-        a.sigma = st->sigma[l + 1];
-        a.R = st->R[l + 1];
-        a.Sbar = st->Sbar[l + 1];
-        a.u_l = st->u[l];
-        a.u_c = st->u[l + 1];
-        a.n = f->n[l];
-        a.seed = seed;
-        a.base = pass_base + (uint64_t)off[l];
-        a.l = l;
-        a.p = p;
-        a.rm_mode = rm_mode;
-        a.eps = eps;
+        lv[l].p = p;
+        lv[l].base = pass_base + (uint64_t)off[l];
       }
       for (int l = 0; l < 8; ++l) {
         if (lv[l].n == 0) continue;
@@ -166,12 +308,13 @@ extern "C" int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt) {
   }
   int64_t n = 0;
   for (int l = 0; l < 8; ++l) n += fgt->n[l];
-  return n * (int64_t)sizeof(int32_t);
+  return 2 * n * (int64_t)sizeof(int32_t);
 }
 
 extern "C" int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0,
                                 int64_t n_iters, uint64_t seed, int rm_mode, double eps,
-                                void *workspace, int64_t workspace_bytes, void *stream) {
+                                int schedule, int roots_per_wg, void *workspace,
+                                int64_t workspace_bytes, void *stream) {
   if (!fgt || !st) {
     set_error("fgt or state is NULL");
     return PASUR_E_INVAL;
@@ -186,6 +329,14 @@ extern "C" int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st,
   }
   if (!(eps >= 0.0) || !std::isfinite(eps)) {
     set_error("eps must be finite and >= 0");
+    return PASUR_E_RANGE;
+  }
+  if (schedule != PASUR_ES_FRONTIER && schedule != PASUR_ES_LEVEL) {
+    set_error("unknown schedule %d", schedule);
+    return PASUR_E_RANGE;
+  }
+  if (roots_per_wg < 0) {
+    set_error("roots_per_wg %d must be >= 0", roots_per_wg);
     return PASUR_E_RANGE;
   }
   if (t0 < 0 || n_iters < 0) {
@@ -205,8 +356,10 @@ extern "C" int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st,
     return PASUR_E_INVAL;
   }
   if (n_iters == 0) return PASUR_OK;
-  int32_t *picks = reinterpret_cast<int32_t *>(workspace);
+  int32_t *ws = reinterpret_cast<int32_t *>(workspace);
   hipStream_t s = (hipStream_t)stream;
-  if (st->dtype == PASUR_F32) return es_run<float>(fgt, st, t0, n_iters, seed, rm_mode, eps, picks, s);
-  return es_run<double>(fgt, st, t0, n_iters, seed, rm_mode, eps, picks, s);
+  if (st->dtype == PASUR_F32)
+    return es_run<float>(fgt, st, t0, n_iters, seed, rm_mode, eps, schedule, roots_per_wg, ws, s);
+  return es_run<double>(fgt, st, t0, n_iters, seed, rm_mode, eps, schedule, roots_per_wg,
+                        ws, s);
 }

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 from typing import List, Optional
 
 from . import (PASUR_F32, PASUR_F64, PLAY_SIGMA_BAR, RM_FLOOR, TV_BR_A, TV_BR_B, TV_EXPECT,
-               V_ITERATE_MEAN, V_SIGMA_BAR, CfrState, es_iterate, selfplay,
+               V_ITERATE_MEAN, V_SIGMA_BAR, ES_FRONTIER, CfrState, es_iterate, selfplay,
                Plan, UnfoldedTree, average_strategy, build_round_tree, cfr_init, cfr_iterate,
                leaf_utilities, paper_params, round_values, roots_to_device, tree_values,
                unfold_scores, _torch)
@@ -76,7 +76,8 @@ class SubgameSolver:
             V = rr.V
         return self.rounds[0].V
 
-    def solve_es(self, iters: int, seed: int, rm_mode: int = RM_FLOOR, eps: float = 1e-8):
+    def solve_es(self, iters: int, seed: int, rm_mode: int = RM_FLOOR, eps: float = 1e-8,
+                 schedule: int = ES_FRONTIER):
         """Backward solve with external-sampling CFR (pasur_es_iterate):
         ``iters`` iterations per round, last round first; each round passes
         back the value of its average strategy, v(sigma-bar), as the next
@@ -88,7 +89,7 @@ class SubgameSolver:
             rr.state = st
             leaf_utilities(rr.fgt, V, self.dtype, st.u[8], self.stream)
             cfr_init(st, self.stream)
-            es_iterate(st, iters, seed, rm_mode, eps, stream=self.stream)
+            es_iterate(st, iters, seed, rm_mode, eps, schedule=schedule, stream=self.stream)
             average_strategy(st, self.stream)
             rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
             round_values(st, V_SIGMA_BAR, rr.V, self.stream)

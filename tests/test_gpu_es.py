@@ -32,8 +32,12 @@ def gpu_round(pa, deck, roots, dtype):
     return s, rr, st
 
 
-@pytest.mark.parametrize("seed,rm", [(4, "floor"), (5, "floor"), (1, "positive")])
-def test_es_matches_oracle_element_by_element(seed, rm):
+@pytest.mark.parametrize("seed,rm,schedule,per_wg", [
+    (4, "floor", "frontier", 0), (5, "floor", "level", 0), (1, "positive", "frontier", 3),
+    (4, "positive", "level", 0), (5, "floor", "frontier", 2)])
+def test_es_matches_oracle_element_by_element(seed, rm, schedule, per_wg):
+    """Both schedules; the frontier schedule also with several roots per
+    workgroup (7 roots in groups of 3 or 2: a ragged last group)."""
     pa = require_gpu()
     deck, roots = synth.last_round_roots(seed)
     f, cb, leaf = oracle_round(deck, roots)
@@ -42,11 +46,13 @@ def test_es_matches_oracle_element_by_element(seed, rm):
     rm_mode = pa.RM_FLOOR if rm == "floor" else pa.RM_POSITIVE
     iters, draw_seed = 40, 77 + seed
     # two calls (the second continues the draw stream) against one oracle call
-    pa.es_iterate(st, 15, draw_seed, rm_mode)
-    pa.es_iterate(st, iters - 15, draw_seed, rm_mode)
+    sch = pa.ES_FRONTIER if schedule == "frontier" else pa.ES_LEVEL
+    pa.es_iterate(st, 15, draw_seed, rm_mode, schedule=sch, roots_per_wg=per_wg)
+    pa.es_iterate(st, iters - 15, draw_seed, rm_mode, schedule=sch, roots_per_wg=per_wg)
     ost = es.ESState(f.n, cb)
     es.es_iterate(ost, leaf, iters, draw_seed, rm_mode=rm)
-    print(f"[es] seed {seed} ({rm}): {sum(f.n)} nodes, {iters} iterations", flush=True)
+    print(f"[es] seed {seed} ({rm}, {schedule}, {per_wg} roots per workgroup): {sum(f.n)} nodes, "
+          f"{iters} iterations", flush=True)
     for l in range(1, 9):
         for name, want in (("sigma", ost.sigma[l]), ("R", ost.R[l]), ("Sbar", ost.Sbar[l])):
             got = to_np(getattr(st, name)[l])
@@ -90,21 +96,23 @@ def test_es_fp32_converges():
 
 def test_es_full_game():
     """All six rounds of seeded deal 1 solved backward with external
-    sampling: a seed reproduces the run bit for bit, and the composed
-    exploitability of the average strategies falls as iterations grow."""
+    sampling: a seed reproduces the run bit for bit, the level-synchronous
+    schedule gives the frontier schedule's results bit for bit at this size,
+    and the composed exploitability of the average strategies falls as
+    iterations grow."""
     pa = require_gpu()
     deck, roots = synth.full_game_root(1)
     res = {}
-    for iters, seed in ((50, 1), (50, 1), (400, 1)):
+    for iters, seed, sch in ((50, 1, pa.ES_FRONTIER), (50, 1, pa.ES_LEVEL), (400, 1, pa.ES_FRONTIER)):
         s = pa.SubgameSolver(deck, 0, roots, dtype=pa.PASUR_F32)
-        s.solve_es(iters, seed)
+        s.solve_es(iters, seed, schedule=sch)
         bra, brb, v = s.exploitability()
         ex = float(((bra - brb) / 2).max().item())
-        sb = [to_np(x).copy() for x in s.rounds[0].state.sigma_bar[1:]]
+        sb = [to_np(x).copy() for rr in s.rounds for x in rr.state.sigma_bar[1:]]
         res.setdefault(iters, []).append((ex, sb, float(v[0].item())))
         print(f"[es] full game seed 1: {iters} iterations per round, exploitability {ex:.4f}, "
               f"value {float(v[0].item()):.3f}", flush=True)
         s.free()
     a, b = res[50]
-    assert all(np.array_equal(x, y) for x, y in zip(a[1], b[1]))
+    assert all(np.array_equal(x, y) for x, y in zip(a[1], b[1])) and a[2] == b[2]
     assert res[400][0][0] < 0.5 * a[0]
