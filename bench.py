@@ -12,7 +12,8 @@ between device synchronisations.  Other workloads (--workload): batched (64
 deals in one persistent launch per round, HIP-graph replay), full-game (all
 six rounds of one deal), paper-scale (32 full games as one batch),
 warm-start (learned warm start vs plain DCFR), selfplay (games/s and fair
-values on a solved full game), copy (counter calibration).
+values on a solved full game), es (external-sampling CFR on a full game),
+copy (counter calibration).
 
 Prints one JSON line: the metric and its value, the step time, the
 dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
@@ -478,6 +479,105 @@ def bench_selfplay(args):
     print(json.dumps(out), flush=True)
 
 
+def es_bytes(stats, T):
+    """Algorithmic bytes of the frontier schedule's work counters: per
+    reached node of the updated player its frontier entry (read down and
+    up), child-begin pair (down and up), pick (written, read) and value
+    written; per child of such a node a frontier append and sigma, value,
+    regret (read and written) and new sigma; per reached opponent node its
+    frontier entry (twice), child-begin pair, pick (twice), one frontier
+    append and the kept child's value read and its own written; per child of
+    an opponent node sigma read and the average sum read and written."""
+    n_t, e_t, n_o, e_o = (float(x) for x in stats)
+    return n_t * (32 + T) + e_t * (4 + 5 * T) + n_o * (28 + 2 * T) + e_o * 3 * T
+
+
+def bench_es(args):
+    """External-sampling CFR on the full game of seeded deal --full-seed:
+    each step solves all six rounds backward with --iters external-sampling
+    iterations per round (default 1000; frontier schedule, one launch per
+    round), average strategies and values of the average strategies passed
+    back, then the composed exploitability.  Reports node visits/s (reached
+    nodes of both passes), the frontier kernel's roofline from its exact work
+    counters, and full-width DCFR on the same game at a few iteration counts
+    (seconds and exploitability) for comparison."""
+    import torch
+    import paper_2508_06559_amd as pa
+    import synth
+
+    dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
+    T = 4 if args.state == "f32" else 8
+    iters = 1000 if args.iters == 2000 else args.iters
+    deck, roots = synth.full_game_root(args.full_seed)
+    stream = torch.cuda.Stream()
+    s = pa.SubgameSolver(deck, 0, roots, dtype=dtype, stream=stream)
+    sizes = s.sizes()
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+
+    def step(k, timed):
+        V = None
+        evs = []
+        for rr in reversed(s.rounds):
+            st = rr.state if rr.state is not None else pa.CfrState(rr.fgt, dtype)
+            rr.state = st
+            pa.leaf_utilities(rr.fgt, V, dtype, st.u[8], stream)
+            pa.cfr_init(st, stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            pa.es_iterate(st, iters, 1 + k, stats=stats if timed else None, stream=stream)
+            e1.record(stream)
+            evs.append((e0, e1))
+            pa.average_strategy(st, stream)
+            rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
+            pa.round_values(st, pa.V_SIGMA_BAR, rr.V, stream)
+            V = rr.V
+        torch.cuda.synchronize()
+        log(f"[bench] es step {k + 1} done")
+        return sum(a.elapsed_time(b) for a, b in evs)
+
+    for k in range(args.warmup):
+        step(k, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern_ms = sum(step(args.warmup + k, True) for k in range(args.steps))
+    el = time.perf_counter() - t0
+    bra, brb, v = s.exploitability()
+    ex = float(((bra - brb) / 2).max().item())
+    st_np = stats.cpu().numpy()
+    visits = float(st_np[0] + st_np[2])
+    nbytes = es_bytes(st_np, T)
+    achieved = nbytes / (kern_ms * 1e-3) / 1e9
+    dcfr = []
+    for it in (10, 30, 100):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.solve(it)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        a, b, _ = s.exploitability()
+        dcfr.append({"iterations": it, "seconds": dt, "exploitability": float(((a - b) / 2).max().item())})
+        log(f"[bench] dcfr {it} iterations: {dt:.3f} s")
+    s.free()
+    per_iter = visits / (args.steps * iters)
+    out = {"metric": "external-sampling CFR node visits/s at 1 GPU", "value": visits / el,
+           "unit": "node visits/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"external-sampling CFR, full game of seeded deal {args.full_seed} "
+                                  f"({sum(sum(n) for n in sizes)} nodes), {iters} iterations per round",
+                      "state": args.state, "visits_per_iteration": per_iter,
+                      "fraction_of_tree_per_iteration": per_iter / sum(sum(n) for n in sizes),
+                      "exploitability_points": ex, "game_value": float(v[0].item()),
+                      "dcfr_same_game": dcfr},
+           "roofline": {"bound": "hbm", "kernel": "k_es_frontier (persistent, one wave per run of roots, "
+                                                  "per-level frontiers of reached nodes)",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel_ms_per_step": kern_ms / args.steps, "launches_per_step": len(sizes),
+                        "work_counters": [int(x) for x in st_np]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,7 +590,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game",
-                                           "paper-scale", "selfplay", "copy"],
+                                           "paper-scale", "selfplay", "es", "copy"],
                     default="two-round",
                     help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
@@ -524,6 +624,8 @@ def main():
         return bench_paper_scale(args)
     if args.workload == "selfplay":
         return bench_selfplay(args)
+    if args.workload == "es":
+        return bench_es(args)
     if args.workload == "copy":
         # calibration for hardware byte counters: a plain device copy of a
         # known size (256 MiB read + 256 MiB written per launch, 4 launches)

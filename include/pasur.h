@@ -289,12 +289,16 @@ int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds, const void *const
  * `workspace` (device, caller-owned) holds two int32 per node of levels
  * 0..7 (picks and frontier lists): pasur_es_workspace_bytes(fgt) bytes
  * (negative on error).  Calls on one workspace must not overlap.
+ * d_stats (device, 4 uint64, or NULL; frontier schedule only) gains the
+ * work done: reached nodes of the updated player, their children, reached
+ * opponent nodes, their children (over all passes).
  * Asynchronous on `stream`. */
 enum { PASUR_ES_FRONTIER = 0, PASUR_ES_LEVEL = 1 };
 int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt);
 int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0,
                      int64_t n_iters, uint64_t seed, int rm_mode, double eps, int schedule,
-                     int roots_per_wg, void *workspace, int64_t workspace_bytes, void *stream);
+                     int roots_per_wg, void *workspace, int64_t workspace_bytes,
+                     uint64_t *d_stats, void *stream);
 
 /* ---- a13: learned warm start ------------------------------------------------
  * Not in the paper (its learned model is an XGBoost regressor on infoset

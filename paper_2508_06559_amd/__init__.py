@@ -110,7 +110,7 @@ def lib():
         L.pasur_es_workspace_bytes.restype = i64
         L.pasur_es_workspace_bytes.argtypes = [vp]
         L.pasur_es_iterate.argtypes = [vp, vp, i64, i64, C.c_uint64, i32, C.c_double, i32, i32, vp,
-                                       i64, vp]
+                                       i64, vp, vp]
         L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
         L.pasur_shift_i32.argtypes = [vp, i64, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
@@ -477,10 +477,11 @@ ES_FRONTIER, ES_LEVEL = 0, 1
 
 def es_iterate(st: CfrState, n_iters: int, seed: int, rm_mode: int = RM_FLOOR, eps: float = 1e-8,
                t0: Optional[int] = None, schedule: int = ES_FRONTIER, roots_per_wg: int = 0,
-               stream=None):
+               stats=None, stream=None):
     """n_iters external-sampling CFR iterations on st (pasur_es_iterate),
     continuing after st.es_t iterations (or t0); the pick workspace is kept
-    on the state."""
+    on the state.  stats: optional int64 device tensor of 4 counters (frontier
+    schedule) that gains the work done (see pasur_es_iterate)."""
     torch = _torch()
     nb = es_workspace_bytes(st.fgt)
     if st.es_ws is None or st.es_ws.numel() < max(nb, 1):
@@ -488,7 +489,7 @@ def es_iterate(st: CfrState, n_iters: int, seed: int, rm_mode: int = RM_FLOOR, e
     t = st.es_t if t0 is None else t0
     _check(lib().pasur_es_iterate(st.fgt.h, C.byref(st.c), t, n_iters, seed & ((1 << 64) - 1),
                                   rm_mode, eps, schedule, roots_per_wg, _p(st.es_ws), st.es_ws.numel(),
-                                  _stream(stream)),
+                                  None if stats is None else _p(stats), _stream(stream)),
            "pasur_es_iterate")
     st.es_t = t + n_iters
 

@@ -59,10 +59,12 @@ struct EsLevel {
 
 // Down step of a reached node h of level l in p's pass: its pick, and for
 // an opponent node the average-sum update and the draw.  Returns the first
-// kept child and sets *k to the number of kept children.
+// kept child and sets *k to the number of kept children and *kids to the
+// number of children.
 template <class T>
-__device__ __forceinline__ int32_t down_node(const EsLevel &a, int64_t h, int *k) {
+__device__ __forceinline__ int32_t down_node(const EsLevel &a, int64_t h, int *k, int *kids) {
   const int32_t b = a.cb[h], e = a.cb[h + 1];
+  *kids = e - b;
   if ((a.l & 1) == a.p) {
     a.pick[h] = kAll;
     *k = e - b;
@@ -124,8 +126,8 @@ __global__ void k_es_down(EsLevel a) {
       return;
     }
   }
-  int k;
-  (void)down_node<T>(a, h, &k);
+  int k, kids;
+  (void)down_node<T>(a, h, &k, &kids);
 }
 
 template <class T>
@@ -146,6 +148,7 @@ struct EsSegArgs {
   int64_t n_roots, n_iters, t0;
   uint64_t N;
   int roots_per_wg;
+  unsigned long long *stats;   // optional: visits and kept children, see pasur_es_iterate
 };
 
 // Exclusive offset of this lane's k items in a wave-wide reservation of
@@ -171,6 +174,7 @@ __global__ __launch_bounds__(BLOCK) void k_es_frontier(EsSegArgs a) {
   const int64_t r0 = (int64_t)blockIdx.x * a.roots_per_wg;
   const int64_t r1 = r0 + a.roots_per_wg < a.n_roots ? r0 + a.roots_per_wg : a.n_roots;
   if (threadIdx.x < 9) seg[threadIdx.x] = a.off[threadIdx.x] + a.root_off[threadIdx.x][r0];
+  unsigned long long n_trav = 0, e_trav = 0, n_opp = 0, e_opp = 0;
   for (int64_t it = 0; it < a.n_iters; ++it) {
     const uint64_t t = (uint64_t)(a.t0 + it + 1);
     for (int p = 0; p < 2; ++p) {
@@ -186,11 +190,18 @@ __global__ __launch_bounds__(BLOCK) void k_es_frontier(EsSegArgs a) {
         const int m = l == 0 ? (int)(r1 - r0) : cnt[l];
         for (int i0 = 0; i0 < m; i0 += BLOCK) {
           const int i = i0 + (int)threadIdx.x;
-          int k = 0;
+          int k = 0, kids = 0;
           int32_t first = 0;
           if (i < m) {
             const int64_t h = l == 0 ? r0 + i : (int64_t)a.front[seg[l] + i];
-            first = down_node<T>(lv, h, &k);
+            first = down_node<T>(lv, h, &k, &kids);
+            if ((l & 1) == p) {
+              ++n_trav;
+              e_trav += kids;
+            } else {
+              ++n_opp;
+              e_opp += kids;
+            }
           }
           if (l < 7) {
             const int pos = wave_reserve(k, &cnt[l + 1]);
@@ -212,6 +223,12 @@ __global__ __launch_bounds__(BLOCK) void k_es_frontier(EsSegArgs a) {
         __syncthreads();
       }
     }
+  }
+  if (a.stats) {
+    atomicAdd(a.stats + 0, n_trav);
+    atomicAdd(a.stats + 1, e_trav);
+    atomicAdd(a.stats + 2, n_opp);
+    atomicAdd(a.stats + 3, e_opp);
   }
 }
 
@@ -238,13 +255,13 @@ void fill_levels(EsLevel lv[8], const pasur_fgt *f, const pasur_cfr_state *st, c
   }
 }
 
-constexpr int kFrontierBlock = 256;
+constexpr int kFrontierBlock = 64;
 constexpr int64_t kNodesPerWorkgroup = 4096;
 
 template <class T>
 int es_run(const pasur_fgt *f, const pasur_cfr_state *st, int64_t t0, int64_t n_iters,
            uint64_t seed, int rm_mode, double eps, int schedule, int roots_per_wg, int32_t *ws,
-           hipStream_t s) {
+           unsigned long long *stats, hipStream_t s) {
   int64_t off[9];
   off[0] = 0;
   for (int l = 0; l < 8; ++l) off[l + 1] = off[l] + f->n[l];
@@ -268,6 +285,7 @@ int es_run(const pasur_fgt *f, const pasur_cfr_state *st, int64_t t0, int64_t n_
     int64_t per = kNodesPerWorkgroup * f->n_roots / (total > 0 ? total : 1);
     if (roots_per_wg > 0) per = roots_per_wg;
     a.roots_per_wg = (int)(per < 1 ? 1 : per > f->n_roots ? f->n_roots : per);
+    a.stats = stats;
     const unsigned grid = (unsigned)((f->n_roots + a.roots_per_wg - 1) / a.roots_per_wg);
     k_es_frontier<T, kFrontierBlock><<<grid, kFrontierBlock, 0, s>>>(a);
     PASUR_TRY_HIP(hipGetLastError());
@@ -314,7 +332,7 @@ extern "C" int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt) {
 extern "C" int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0,
                                 int64_t n_iters, uint64_t seed, int rm_mode, double eps,
                                 int schedule, int roots_per_wg, void *workspace,
-                                int64_t workspace_bytes, void *stream) {
+                                int64_t workspace_bytes, uint64_t *d_stats, void *stream) {
   if (!fgt || !st) {
     set_error("fgt or state is NULL");
     return PASUR_E_INVAL;
@@ -357,9 +375,11 @@ extern "C" int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st,
   }
   if (n_iters == 0) return PASUR_OK;
   int32_t *ws = reinterpret_cast<int32_t *>(workspace);
+  unsigned long long *stats = reinterpret_cast<unsigned long long *>(d_stats);
   hipStream_t s = (hipStream_t)stream;
   if (st->dtype == PASUR_F32)
-    return es_run<float>(fgt, st, t0, n_iters, seed, rm_mode, eps, schedule, roots_per_wg, ws, s);
+    return es_run<float>(fgt, st, t0, n_iters, seed, rm_mode, eps, schedule, roots_per_wg, ws,
+                         stats, s);
   return es_run<double>(fgt, st, t0, n_iters, seed, rm_mode, eps, schedule, roots_per_wg,
-                        ws, s);
+                        ws, stats, s);
 }

@@ -154,23 +154,23 @@ def test_es_checks(lib):
     vp = C.c_void_p
     f = lib.pasur_es_iterate
     f.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_uint64, C.c_int, C.c_double, C.c_int, C.c_int,
-                  vp, C.c_int64, vp]
+                  vp, C.c_int64, vp, vp]
     wb = lib.pasur_es_workspace_bytes
     wb.restype = C.c_int64
     wb.argtypes = [vp]
     assert wb(None) == E_INVAL
     st = full_state()
-    expect(lib, f(None, C.byref(st), 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None), E_INVAL, ["NULL"])
-    expect(lib, f(DUMMY, None, 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None), E_INVAL, ["NULL"])
-    expect(lib, f(DUMMY, C.byref(full_state(7)), 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None), E_RANGE,
+    expect(lib, f(None, C.byref(st), 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_INVAL, ["NULL"])
+    expect(lib, f(DUMMY, None, 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_INVAL, ["NULL"])
+    expect(lib, f(DUMMY, C.byref(full_state(7)), 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_RANGE,
            ["dtype 7"])
-    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 3, 1e-8, 0, 0, DUMMY, 64, None), E_RANGE, ["rm_mode 3"])
-    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, -1.0, 0, 0, DUMMY, 64, None), E_RANGE, ["eps"])
-    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, float("nan"), 0, 0, DUMMY, 64, None), E_RANGE, ["eps"])
-    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, 1e-8, 2, 0, DUMMY, 64, None), E_RANGE, ["schedule 2"])
-    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, 1e-8, 0, -1, DUMMY, 64, None), E_RANGE,
+    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 3, 1e-8, 0, 0, DUMMY, 64, None, None), E_RANGE, ["rm_mode 3"])
+    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, -1.0, 0, 0, DUMMY, 64, None, None), E_RANGE, ["eps"])
+    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, float("nan"), 0, 0, DUMMY, 64, None, None), E_RANGE, ["eps"])
+    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, 1e-8, 2, 0, DUMMY, 64, None, None), E_RANGE, ["schedule 2"])
+    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, 1e-8, 0, -1, DUMMY, 64, None, None), E_RANGE,
            ["roots_per_wg -1"])
-    expect(lib, f(DUMMY, C.byref(st), -1, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None), E_RANGE, ["t0 -1"])
-    expect(lib, f(DUMMY, C.byref(st), 0, -2, 1, 0, 1e-8, 0, 0, DUMMY, 64, None), E_RANGE, ["n_iters -2"])
+    expect(lib, f(DUMMY, C.byref(st), -1, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_RANGE, ["t0 -1"])
+    expect(lib, f(DUMMY, C.byref(st), 0, -2, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_RANGE, ["n_iters -2"])
     st.R[3] = None
-    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None), E_INVAL, ["level 3"])
+    expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_INVAL, ["level 3"])
