@@ -300,6 +300,29 @@ int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0
                      int roots_per_wg, void *workspace, int64_t workspace_bytes,
                      uint64_t *d_stats, void *stream);
 
+/* ---- f4: infoset rows (sections "Compressed Game Tensor", "Infoset Tensors")
+ * One row per FGT node of `level` (1..8): the nodes d_edges[i] (device) or,
+ * with d_edges NULL, all n = n[level] nodes in order.  `gt` must be the game
+ * tree `fgt` was unfolded from.  Row (58 int8): columns 0..51 per card (index
+ * as everywhere in this library) the compressed code of the node's game
+ * tensor for cards in play this round (held, or in the pool when the round
+ * began): Alex's history minus Bob's, where in turn i (1-based) the mover's
+ * history gains i at the card he plays and 10 i at each pool card he
+ * collects; a difference of 0 becomes 100 / 105 / 110 for a card in Alex's
+ * hand / Bob's hand / the pool, and a card out of play with 0 < |d| < 5
+ * (laid and collecting in one turn) becomes 110 + d; cards dealt earlier and
+ * out of play are -127, cards not yet dealt 0.  Columns 52..54: inherited
+ * score as Alex clubs (7 if Alex owns the 7-clubs bonus), Bob clubs (7 if
+ * Bob owns it), point difference; 55..57: round, turn (0..3) and player
+ * (0 Alex, 1 Bob) of the action leading to the node.
+ * format PASUR_INFOSET_INT8: d_out int8 [n][58]; PASUR_INFOSET_MLP: d_out
+ * BF16 [n][192], the warm-start network's input, with row / 128 in columns
+ * 0..57 and zeros after.  Asynchronous on `stream`. */
+enum { PASUR_INFOSET_INT8 = 0, PASUR_INFOSET_MLP = 1 };
+int pasur_infoset_rows(const pasur_gt *gt, const pasur_fgt *fgt, int level,
+                       const int32_t *d_edges, int64_t n, int format, void *d_out,
+                       void *stream);
+
 /* ---- a13: learned warm start ------------------------------------------------
  * Not in the paper (its learned model is an XGBoost regressor on infoset
  * rows).  A 192-256-256-2 MLP: input = the child node's card state (Alex's

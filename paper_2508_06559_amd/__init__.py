@@ -107,6 +107,7 @@ def lib():
         L.pasur_mlp_infer.argtypes = [vp, vp, i64, vp, vp]
         L.pasur_mlp_transpose.argtypes = [vp, vp, vp, vp]
         L.pasur_selfplay.argtypes = [vp, i32, vp, i32, i32, i64, C.c_uint64, i32, i32, vp, vp]
+        L.pasur_infoset_rows.argtypes = [vp, vp, i32, vp, i64, i32, vp, vp]
         L.pasur_es_workspace_bytes.restype = i64
         L.pasur_es_workspace_bytes.argtypes = [vp]
         L.pasur_es_iterate.argtypes = [vp, vp, i64, i64, C.c_uint64, i32, C.c_double, i32, i32, vp,
@@ -473,6 +474,18 @@ def es_workspace_bytes(fgt: UnfoldedTree) -> int:
 
 
 ES_FRONTIER, ES_LEVEL = 0, 1
+INFOSET_INT8, INFOSET_MLP = 0, 1
+INFOSET_WIDTH = 58
+
+
+def infoset_rows(gt: GameTree, fgt: UnfoldedTree, level: int, d_edges, n: int, out,
+                 fmt: int = INFOSET_INT8, stream=None):
+    """Infoset rows of FGT nodes of `level` (pasur_infoset_rows): out is an
+    int8 [n, 58] device tensor (INFOSET_INT8) or int16 [n, 192] holding BF16
+    network input (INFOSET_MLP); d_edges None means every node in order."""
+    _check(lib().pasur_infoset_rows(gt.h, fgt.h, level, None if d_edges is None else _p(d_edges), n,
+                                    fmt, _p(out), _stream(stream)), "pasur_infoset_rows")
+    return out
 
 
 def es_iterate(st: CfrState, n_iters: int, seed: int, rm_mode: int = RM_FLOOR, eps: float = 1e-8,

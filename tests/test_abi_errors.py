@@ -174,3 +174,16 @@ def test_es_checks(lib):
     expect(lib, f(DUMMY, C.byref(st), 0, -2, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_RANGE, ["n_iters -2"])
     st.R[3] = None
     expect(lib, f(DUMMY, C.byref(st), 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_INVAL, ["level 3"])
+
+
+def test_infoset_checks(lib):
+    vp = C.c_void_p
+    f = lib.pasur_infoset_rows
+    f.argtypes = [vp, vp, C.c_int, vp, C.c_int64, C.c_int, vp, vp]
+    expect(lib, f(None, DUMMY, 1, None, 4, 0, DUMMY, None), E_INVAL, ["null"])
+    expect(lib, f(DUMMY, None, 1, None, 4, 0, DUMMY, None), E_INVAL, ["null"])
+    expect(lib, f(DUMMY, DUMMY, 1, None, 4, 0, None, None), E_INVAL, ["null"])
+    expect(lib, f(DUMMY, DUMMY, 1, None, -1, 0, DUMMY, None), E_INVAL, ["negative"])
+    expect(lib, f(DUMMY, DUMMY, 0, None, 4, 0, DUMMY, None), E_RANGE, ["level 0"])
+    expect(lib, f(DUMMY, DUMMY, 9, None, 4, 0, DUMMY, None), E_RANGE, ["level 9"])
+    expect(lib, f(DUMMY, DUMMY, 1, None, 4, 2, DUMMY, None), E_RANGE, ["format 2"])
