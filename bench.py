@@ -13,7 +13,8 @@ deals in one persistent launch per round, HIP-graph replay), full-game (all
 six rounds of one deal), paper-scale (32 full games as one batch),
 warm-start (learned warm start vs plain DCFR), selfplay (games/s and fair
 values on a solved full game), es (external-sampling CFR on a full game),
-copy (counter calibration).
+infoset (infoset rows of a full game; strategy models on them), copy
+(counter calibration).
 
 Prints one JSON line: the metric and its value, the step time, the
 dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
@@ -578,6 +579,133 @@ def bench_es(args):
     print(json.dumps(out), flush=True)
 
 
+def infoset_bytes(level, rows):
+    """Algorithmic bytes of pasur_infoset_rows (int8 rows) for `rows` nodes
+    of `level`: the row written (58) and, read, the node's GT index and
+    score id (8), pool and hands (9), per ancestor action its played card,
+    collected mask and parent (13 each), the root's pool (8) and the score
+    entry (4)."""
+    return rows * (58 + 8 + 9 + 13 * level + 8 + 4)
+
+
+def bench_infoset(args):
+    """Infoset rows (section "Infoset Tensors") for every FGT node of the
+    full game of seeded deal --full-seed, level by level (one launch each,
+    into a reused buffer), timed with HIP events; then the paper's strategy
+    model design against the warm-start network: a network trained on
+    infoset rows, one on the edge features, and a gradient-boosted tree model
+    on infoset rows (the paper's XGBoost analogue, CPU), all on DCFR
+    solutions of --model-train-deals two-round deals, evaluated on
+    --model-test-deals held-out deals (RMSE of 100 x sigma on sampled
+    decisions, exploitability of the predicted starting profile)."""
+    import torch
+    import paper_2508_06559_amd as pa
+    from paper_2508_06559_amd import learn
+    import synth
+
+    deck, roots = synth.full_game_root(args.full_seed)
+    stream = torch.cuda.Stream()
+    s = pa.SubgameSolver(deck, 0, roots, keep_gt=True, stream=stream)
+    sizes = s.sizes()
+    nmax = max(max(n[1:]) for n in sizes)
+    out = torch.empty((nmax, pa.INFOSET_WIDTH), dtype=torch.int8, device="cuda")
+    rows_total = sum(sum(n[1:]) for n in sizes)
+    nbytes = sum(infoset_bytes(l, n[l]) for n in sizes for l in range(1, 9))
+
+    def step(k):
+        evs = []
+        for rr in s.rounds:
+            for l in range(1, 9):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                pa.infoset_rows(rr.gt, rr.fgt, l, None, rr.fgt.n[l], out, stream=stream)
+                e1.record(stream)
+                evs.append((e0, e1))
+        torch.cuda.synchronize()
+        log(f"[bench] infoset step {k + 1} done")
+        return sum(a.elapsed_time(b) for a, b in evs)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern_ms = sum(step(args.warmup + k) for k in range(args.steps))
+    el = time.perf_counter() - t0
+    s.free()
+    achieved = nbytes * args.steps / (kern_ms * 1e-3) / 1e9
+
+    res = {"metric": "infoset rows/s at 1 GPU", "value": rows_total * args.steps / el, "unit": "rows/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+           "data": "synthetic",
+           "config": {"workload": f"infoset rows of every node of the full game of seeded deal "
+                                  f"{args.full_seed} ({rows_total} rows of 58 bytes, 48 launches per step)"},
+           "roofline": {"bound": "hbm", "kernel": "k_infoset (one thread per row, history from up to "
+                                                  "eight ancestors)",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel_ms_per_step": kern_ms / args.steps,
+                        "algorithmic_bytes_per_step": nbytes}}
+    if args.no_models:
+        print(json.dumps(res), flush=True)
+        return
+
+    # strategy models
+    ntr, nte = args.model_train_deals, args.model_test_deals
+    train = [synth.two_round_root(s_) for s_ in range(30000, 30000 + ntr)]
+    test = [synth.two_round_root(s_) for s_ in range(40000, 40000 + nte)]
+    tm = time.perf_counter()
+    models = {}
+    for feats in ("edge", "infoset"):
+        units = learn.training_units(train, 500, 300, features=feats)
+        m = learn.WarmStartMLP(0)
+        hist = learn.train(m, units, args.epochs)
+        models[feats] = (m, hist[-1])
+        log(f"[bench] network on {feats} features trained: loss {hist[-1]}")
+    rows, tgt, _ = learn.infoset_dataset(train, 500, 150)
+    tree = learn.fit_tree_model(rows, tgt)
+    log(f"[bench] tree model fitted on {len(rows)} rows")
+    t_models = time.perf_counter() - tm
+
+    def net_rmse(m, feats):
+        errs = []
+        for u in learn.training_units(test, 500, 300, seed0=7, features=feats):
+            Y = m.forward(u.X, u.n_rows)[:, 0].float().cpu().numpy().astype(np.float64)
+            seg = u.seg.cpu().numpy()
+            sig = np.empty_like(Y)
+            for p in range(u.n_par):
+                z = Y[seg[p]:seg[p + 1]]
+                e = np.exp(z - z.max())
+                sig[seg[p]:seg[p + 1]] = e / e.sum()
+            errs.append(100.0 * sig - 100.0 * u.tsig.cpu().numpy())
+        e = np.concatenate(errs)
+        return float(np.sqrt(np.mean(e * e)))
+
+    trows, ttgt, tgrp = learn.infoset_dataset(test, 500, 300, seed0=7)
+    p = np.maximum(tree.predict(trows.astype(np.float32)), 0.0)
+    tot = np.bincount(tgrp, weights=p)
+    cnt = np.bincount(tgrp)
+    pos = tot[tgrp] > 0
+    sig = 100.0 * np.where(pos, p / np.where(pos, tot[tgrp], 1.0), 1.0 / cnt[tgrp])
+    tree_rmse = float(np.sqrt(np.mean((sig - ttgt) ** 2)))
+    ex = {"uniform": [], "network_edge": [], "network_infoset": [], "tree_infoset": []}
+    for deck_, roots_ in test:
+        ex["uniform"].append(learn.initial_profile_exploitability(deck_, roots_, None))
+        ex["network_edge"].append(learn.initial_profile_exploitability(deck_, roots_, models["edge"][0]))
+        ex["network_infoset"].append(learn.initial_profile_exploitability(deck_, roots_, models["infoset"][0],
+                                                                          "infoset"))
+        ex["tree_infoset"].append(learn.tree_profile_exploitability(deck_, roots_, tree))
+    cmp = {"rmse_100sigma_heldout": {"network_edge": net_rmse(models["edge"][0], "edge"),
+                                     "network_infoset": net_rmse(models["infoset"][0], "infoset"),
+                                     "tree_infoset": tree_rmse},
+           "initial_exploitability_median": {k: float(np.median(v)) for k, v in ex.items()},
+           "final_train_loss": {k: v[1] for k, v in models.items()},
+           "tree_rows": int(len(rows)), "train_deals": ntr, "test_deals": nte, "epochs": args.epochs,
+           "seconds": t_models}
+    res["config"]["models"] = cmp
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -590,7 +718,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game",
-                                           "paper-scale", "selfplay", "es", "copy"],
+                                           "paper-scale", "selfplay", "es", "infoset", "copy"],
                     default="two-round",
                     help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
@@ -598,6 +726,9 @@ def main():
     ap.add_argument("--test-deals", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--deals", type=int, default=32, help="paper-scale: number of full games")
+    ap.add_argument("--model-train-deals", type=int, default=64, help="infoset: deals the models learn from")
+    ap.add_argument("--model-test-deals", type=int, default=16, help="infoset: held-out deals")
+    ap.add_argument("--no-models", action="store_true", help="infoset: rows only, no model comparison")
     ap.add_argument("--games", type=int, default=1 << 24, help="selfplay: games per matchup")
     ap.add_argument("--full-seed", type=int, default=40, help="full-game: the seeded deal")
     ap.add_argument("--warm-levels", default="3,2,4,8",
@@ -626,6 +757,8 @@ def main():
         return bench_selfplay(args)
     if args.workload == "es":
         return bench_es(args)
+    if args.workload == "infoset":
+        return bench_infoset(args)
     if args.workload == "copy":
         # calibration for hardware byte counters: a plain device copy of a
         # known size (256 MiB read + 256 MiB written per launch, 4 launches)

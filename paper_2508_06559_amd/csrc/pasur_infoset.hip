@@ -1,7 +1,8 @@
 // pasur_infoset.hip -- infoset rows of unfolded-tree nodes (sections
 // "Compressed Game Tensor" and "Infoset Tensors").
 //
-// One thread per row.  The node's action history is read from its GT
+// One thread per row (staged in LDS, written out by the workgroup with
+// 16-byte stores).  The node's action history is read from its GT
 // ancestors (at most eight): in turn i (1-based) the mover's history gains i
 // at the card he plays and 10 i at each pool card he collects.  The card
 // states come from the node's own pool and hands.  Per card the compressed
@@ -40,72 +41,102 @@ struct InfoArgs {
 
 __device__ __forceinline__ int bit(uint64_t m, int c) { return (int)((m >> c) & 1ull); }
 
-__global__ void k_infoset(InfoArgs a) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= a.n) return;
-  const int64_t e = a.edges ? (int64_t)a.edges[q] : q;
-  int32_t g = a.fgt_gt[e];
-  const int32_t sid = a.fgt_sid[e];
-  const uint64_t pool_now = a.pool[a.level][g];
-  const uint8_t h = a.hands[a.level][g];
-  uint64_t held_a = 0, held_b = 0;
-  for (int i = 0; i < 4; ++i) {
-    if ((h >> i) & 1) held_a |= 1ull << a.card[i];
-    if ((h >> (4 + i)) & 1) held_b |= 1ull << a.card[4 + i];
-  }
-  // per turn (0..3): the card each player laid and the cards he collected
-  uint64_t lay[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  uint64_t cap[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-#pragma unroll
-  for (int k = 8; k >= 1; --k) {
-    if (k <= a.level) {
-      lay[(k - 1) & 1][(k - 1) >> 1] = 1ull << a.act_card[k][g];
-      cap[(k - 1) & 1][(k - 1) >> 1] = a.act_cap[k][g];
-      g = a.parent[k][g];
+constexpr int kBlock = 256;
+
+// Rows are built in LDS, one 58-byte row per thread; the workgroup then
+// writes its consecutive rows with 16-byte stores.  Card bytes start from
+// masks (-127 for a card dealt earlier and out of play, 0 otherwise) and
+// only the cards in play this round get a code.
+__global__ __launch_bounds__(kBlock) void k_infoset(InfoArgs a) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[kBlock * kRow];
+  const int t = (int)threadIdx.x;
+  const int64_t q0 = (int64_t)blockIdx.x * kBlock;
+  const int64_t q = q0 + t;
+  if (q < a.n) {
+    int8_t *row = lds + t * kRow;
+    const int64_t e = a.edges ? (int64_t)a.edges[q] : q;
+    int32_t g = a.fgt_gt[e];
+    const int32_t sid = a.fgt_sid[e];
+    const uint64_t pool_now = a.pool[a.level][g];
+    const uint8_t h = a.hands[a.level][g];
+    uint64_t held_a = 0, held_b = 0;
+    for (int i = 0; i < 4; ++i) {
+      if ((h >> i) & 1) held_a |= 1ull << a.card[i];
+      if ((h >> (4 + i)) & 1) held_b |= 1ull << a.card[4 + i];
     }
-  }
-  const uint64_t in_play = a.hand_a | a.hand_b | a.pool[0][g];
-  const int8_t *s = a.score_tab + 4 * (int64_t)sid;
-  const int8_t s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3];
-  int8_t *o8 = reinterpret_cast<int8_t *>(a.out) + q * kRow;
-  __bf16 *ob = reinterpret_cast<__bf16 *>(a.out) + q * kMlpIn;
-  const bool mlp = a.format == PASUR_INFOSET_MLP;
-  for (int j = 0; j < kRow; ++j) {
-    int v;
-    if (j < 52) {
-      const int c = j;
+    // per turn (0..3): the card each player laid and the cards he collected
+    uint64_t lay[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    uint64_t cap[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int k = 8; k >= 1; --k) {
+      if (k <= a.level) {
+        lay[(k - 1) & 1][(k - 1) >> 1] = 1ull << a.act_card[k][g];
+        cap[(k - 1) & 1][(k - 1) >> 1] = a.act_cap[k][g];
+        g = a.parent[k][g];
+      }
+    }
+    const uint64_t in_play = a.hand_a | a.hand_b | a.pool[0][g];
+    const uint64_t gone = a.dealt & ~in_play;
+    int16_t *row2 = reinterpret_cast<int16_t *>(row);  // rows start at even offsets
+    for (int c = 0; c < 52; c += 2) {
+      const int lo = bit(gone, c) ? 0x81 : 0, hi = bit(gone, c + 1) ? 0x81 : 0;
+      row2[c >> 1] = (int16_t)(lo | (hi << 8));
+    }
+    for (uint64_t m = in_play; m; m &= m - 1) {
+      const int c = __builtin_ctzll(m);
       int d = 0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        d += (t + 1) * (bit(lay[0][t], c) - bit(lay[1][t], c)) +
-             10 * (t + 1) * (bit(cap[0][t], c) - bit(cap[1][t], c));
-      const int state = bit(held_a, c) ? 1 : bit(held_b, c) ? 2 : bit(pool_now, c) ? 3 : 0;
+      for (int tt = 0; tt < 4; ++tt)
+        d += (tt + 1) * (bit(lay[0][tt], c) - bit(lay[1][tt], c)) +
+             10 * (tt + 1) * (bit(cap[0][tt], c) - bit(cap[1][tt], c));
       if (d == 0) {
-        d = state == 1 ? 100 : state == 2 ? 105 : state == 3 ? 110 : 0;
-      } else if (state == 0 && d > -5 && d < 5) {
+        d = bit(held_a, c) ? 100 : bit(held_b, c) ? 105 : bit(pool_now, c) ? 110 : 0;
+      } else if (!bit(held_a | held_b | pool_now, c) && d > -5 && d < 5) {
         d += 110;
       }
-      v = bit(in_play, c) ? d : bit(a.dealt, c) ? -127 : 0;
-    } else if (j == 52) {
-      v = s3 == 1 ? 7 : s0;
-    } else if (j == 53) {
-      v = s3 == 2 ? 7 : s1;
-    } else if (j == 54) {
-      v = s2;
-    } else if (j == 55) {
-      v = a.round;
-    } else if (j == 56) {
-      v = (a.level - 1) >> 1;
-    } else {
-      v = (a.level - 1) & 1;
+      row[c] = (int8_t)d;
     }
-    if (mlp)
-      ob[j] = (__bf16)((float)v * (1.0f / 128.0f));
-    else
-      o8[j] = (int8_t)v;
+    const int8_t *s = a.score_tab + 4 * (int64_t)sid;
+    const int8_t s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3];
+    row[52] = s3 == 1 ? (int8_t)7 : s0;
+    row[53] = s3 == 2 ? (int8_t)7 : s1;
+    row[54] = s2;
+    row[55] = (int8_t)a.round;
+    row[56] = (int8_t)((a.level - 1) >> 1);
+    row[57] = (int8_t)((a.level - 1) & 1);
   }
-  if (mlp)
-    for (int j = kRow; j < kMlpIn; ++j) ob[j] = (__bf16)0.0f;
+  __syncthreads();
+  const int64_t rows = a.n - q0 < kBlock ? a.n - q0 : kBlock;
+  if (a.format == PASUR_INFOSET_INT8) {
+    int8_t *dst = reinterpret_cast<int8_t *>(a.out) + q0 * kRow;
+    const int64_t bytes = rows * kRow;
+    int64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+      done = bytes & ~(int64_t)15;
+      for (int64_t i = t; i < (done >> 4); i += kBlock)
+        reinterpret_cast<uint4 *>(dst)[i] = reinterpret_cast<const uint4 *>(lds)[i];
+    }
+    for (int64_t i = done + t; i < bytes; i += kBlock) dst[i] = lds[i];
+  } else {
+    // BF16 [rows][192]: eight columns per 16-byte store, row / 128 then zeros
+    uint4 *dst = reinterpret_cast<uint4 *>(reinterpret_cast<__bf16 *>(a.out) + q0 * kMlpIn);
+    constexpr int kChunks = kMlpIn / 8;
+    for (int64_t i = t; i < rows * kChunks; i += kBlock) {
+      const int r = (int)(i / kChunks), col0 = (int)(i % kChunks) * 8;
+      uint32_t w[4];
+      for (int k = 0; k < 4; ++k) {
+        uint32_t pair = 0;
+        for (int hh = 0; hh < 2; ++hh) {
+          const int col = col0 + 2 * k + hh;
+          const float v = col < kRow ? (float)lds[r * kRow + col] * (1.0f / 128.0f) : 0.0f;
+          const __bf16 b = (__bf16)v;
+          pair |= (uint32_t)__builtin_bit_cast(uint16_t, b) << (16 * hh);
+        }
+        w[k] = pair;
+      }
+      dst[i] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
 }
 
 }  // namespace
@@ -160,8 +191,8 @@ extern "C" int pasur_infoset_rows(const pasur_gt *gt, const pasur_fgt *fgt, int 
   a.round = gt->round;
   a.format = format;
   a.out = d_out;
-  const unsigned grid = (unsigned)((n + 255) / 256);
-  k_infoset<<<grid, 256, 0, (hipStream_t)stream>>>(a);
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  k_infoset<<<grid, kBlock, 0, (hipStream_t)stream>>>(a);
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
 }

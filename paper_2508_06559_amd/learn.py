@@ -20,7 +20,8 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from . import (PASUR_F32, PASUR_F64, MlpGrads, MlpWeights, CfrState, adam_step, average_strategy,
+from . import (FGT_PARENT, INFOSET_MLP, INFOSET_WIDTH, PASUR_F32, PASUR_F64, MlpGrads, MlpWeights,
+               CfrState, adam_step, average_strategy, infoset_rows,
                cfr_init, cfr_iterate, cfr_warm_init, edge_features, gather_f32, leaf_utilities,
                mlp_backward, mlp_forward, mlp_infer, mlp_loss, paper_params, round_values, sample_parents,
                shift_i32, mlp_transpose, warm_start_round as _warm_start_round,
@@ -148,7 +149,20 @@ class WarmStartMLP:
         return [t.detach().cpu().numpy().copy() for t in self.master]
 
 
-def make_units(solver: SubgameSolver, seed: int, parents_per_level: int = 400) -> List[Unit]:
+def features_into(rr, level: int, edges, n: int, X, features: str = "edge"):
+    """Network input rows of FGT nodes of `level` (edges None: all, in
+    order): the edge features (pasur_edge_features) or the paper's infoset
+    rows scaled into the same input width (pasur_infoset_rows)."""
+    if features == "edge":
+        edge_features(rr.gt, rr.fgt, level, edges, n, X)
+    elif features == "infoset":
+        infoset_rows(rr.gt, rr.fgt, level, edges, n, X, INFOSET_MLP)
+    else:
+        raise ValueError(f"unknown feature set {features!r}")
+
+
+def make_units(solver: SubgameSolver, seed: int, parents_per_level: int = 400,
+               features: str = "edge") -> List[Unit]:
     """Training units from a solved SubgameSolver built with keep_gt=True:
     one unit per round, sampled decision parents of every level."""
     torch = _torch()
@@ -173,7 +187,7 @@ def make_units(solver: SubgameSolver, seed: int, parents_per_level: int = 400) -
         useg = torch.empty(pars + 1, dtype=torch.int32, device="cuda")
         off = poff = 0
         for l, seg, edges, npar, ne in parts:
-            edge_features(rr.gt, f, l, edges, ne, X[off:])
+            features_into(rr, l, edges, ne, X[off:], features)
             gather_f32(st.sigma_bar[l], st.dtype, edges, ne, tsig[off:])
             gather_f32(st.u[l], st.dtype, edges, ne, tval[off:])
             shift_i32(seg, npar + 1, off, useg[poff:])
@@ -192,15 +206,17 @@ def warm_start_round(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float,
     _warm_start_round(rr.gt, rr.state, model.infer_weights(), max_level, kappa_r, kappa_s, ws)
 
 
-def warm_start_round_by_level(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float):
+def warm_start_round_by_level(model: WarmStartMLP, rr, kappa_r: float, kappa_s: float,
+                              features: str = "edge"):
     """The same as warm_start_round with max_level 8, one level at a time
-    through the per-level calls (kept as a cross-check)."""
+    through the per-level calls (a cross-check, and the path for networks
+    trained on infoset rows)."""
     torch = _torch()
     f = rr.fgt
     for l in range(1, 9):
         n = f.n[l]
         X = torch.empty((n, N_IN), dtype=torch.int16, device="cuda")
-        edge_features(rr.gt, f, l, None, n, X)
+        features_into(rr, l, None, n, X, features)
         Y = torch.empty((n, N_OUT), dtype=torch.float32, device="cuda")
         mlp_infer(model.weights(), X, n, Y)
         cfr_warm_init(rr.state, l, Y, kappa_r, kappa_s)
@@ -299,29 +315,104 @@ def train(model: WarmStartMLP, units: List[Unit], epochs: int, seed: int = 0, lr
     return hist
 
 
-def training_units(problems, iters: int, parents_per_level: int = 600, seed0: int = 0):
+def training_units(problems, iters: int, parents_per_level: int = 600, seed0: int = 0,
+                   features: str = "edge"):
     """Solve every (deck, roots) two-round problem with plain DCFR and sample
     training units from the solution."""
     units = []
     for k, (deck, roots) in enumerate(problems):
         sv = SubgameSolver(deck, 4, roots, keep_gt=True)
         sv.solve(iters)
-        units += make_units(sv, seed0 + k, parents_per_level)
+        units += make_units(sv, seed0 + k, parents_per_level, features)
         sv.free()
     return units
 
 
-def initial_profile_exploitability(deck, roots, model: Optional[WarmStartMLP]):
+def initial_profile_exploitability(deck, roots, model: Optional[WarmStartMLP],
+                                   features: str = "edge"):
     """Exploitability of the profile DCFR starts from: uniform, or the
     network's prediction."""
     sv = SubgameSolver(deck, 4, roots, keep_gt=True)
     for rr in sv.rounds:
         rr.state = CfrState(rr.fgt, PASUR_F32)
         cfr_init(rr.state)
-        if model is not None:
+        if model is not None and features == "edge":
             warm_start_round(model, rr, 0.0, 0.0)
+        elif model is not None:
+            warm_start_round_by_level(model, rr, 0.0, 0.0, features)
         for l in range(1, 9):
             rr.state.sigma_bar[l].copy_(rr.state.sigma[l])
+    ex = exploitability(sv)
+    sv.free()
+    return ex
+
+
+# ---- tree-model baseline on infoset rows -------------------------------------
+# The paper fits a gradient-boosted tree model (XGBoost, RMSE, gamma = 1) to
+# 100 x sigma on 58-byte infoset rows.  XGBoost is not available here; the
+# baseline is scikit-learn's histogram gradient boosting with the squared
+# error, on the same rows and target, on the CPU.
+
+
+def infoset_dataset(problems, iters: int, parents_per_level: int = 600, seed0: int = 0):
+    """(rows int8 [N, 58], 100 x average strategy [N], parent id [N]) of
+    sampled decision parents of the solved two-round problems."""
+    torch = _torch()
+    rows, tgt, grp = [], [], []
+    gid = 0
+    for k, (deck, roots) in enumerate(problems):
+        sv = SubgameSolver(deck, 4, roots, keep_gt=True)
+        sv.solve(iters)
+        for rr in sv.rounds:
+            f, st = rr.fgt, rr.state
+            for l in range(1, 9):
+                seg = torch.empty(f.n[l - 1] + 1, dtype=torch.int32, device="cuda")
+                edges = torch.empty(f.n[l], dtype=torch.int32, device="cuda")
+                keep = min(1.0, parents_per_level / max(1, f.n[l - 1]))
+                npar, ne = sample_parents(f, l, ((seed0 + k) << 8) ^ (rr.round << 4) ^ l, keep,
+                                          seg, edges)
+                if not ne:
+                    continue
+                R = torch.empty((ne, INFOSET_WIDTH), dtype=torch.int8, device="cuda")
+                infoset_rows(rr.gt, f, l, edges, ne, R)
+                t = torch.empty(ne, dtype=torch.float32, device="cuda")
+                gather_f32(st.sigma_bar[l], st.dtype, edges, ne, t)
+                sg = seg[: npar + 1].cpu().numpy()
+                g = np.repeat(np.arange(npar), np.diff(sg)) + gid
+                gid += npar
+                rows.append(R.cpu().numpy())
+                tgt.append(100.0 * t.cpu().numpy())
+                grp.append(g)
+        sv.free()
+    return np.concatenate(rows), np.concatenate(tgt), np.concatenate(grp)
+
+
+def fit_tree_model(rows: np.ndarray, target: np.ndarray, seed: int = 0, max_iter: int = 300):
+    from sklearn.ensemble import HistGradientBoostingRegressor
+    m = HistGradientBoostingRegressor(loss="squared_error", max_iter=max_iter, learning_rate=0.1,
+                                      max_leaf_nodes=63, random_state=seed)
+    m.fit(rows.astype(np.float32), target)
+    return m
+
+
+def tree_profile_exploitability(deck, roots, tree) -> float:
+    """Exploitability of the profile the tree model predicts: 100 x sigma
+    clipped at 0 and normalised over siblings (uniform where all are 0)."""
+    torch = _torch()
+    sv = SubgameSolver(deck, 4, roots, keep_gt=True)
+    for rr in sv.rounds:
+        f = rr.fgt
+        rr.state = CfrState(f, PASUR_F32)
+        for l in range(1, 9):
+            n = f.n[l]
+            R = torch.empty((n, INFOSET_WIDTH), dtype=torch.int8, device="cuda")
+            infoset_rows(rr.gt, f, l, None, n, R)
+            p = np.maximum(tree.predict(R.cpu().numpy().astype(np.float32)), 0.0)
+            par = f.read(FGT_PARENT, l).astype(np.int64)
+            tot = np.bincount(par, weights=p, minlength=f.n[l - 1])
+            cnt = np.bincount(par, minlength=f.n[l - 1])
+            sig = np.where(tot[par] > 0, p / np.where(tot[par] > 0, tot[par], 1.0), 1.0 / cnt[par])
+            rr.state.sigma_bar[l].copy_(torch.from_numpy(sig.astype(np.float32)))
     ex = exploitability(sv)
     sv.free()
     return ex

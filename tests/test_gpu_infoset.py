@@ -92,3 +92,27 @@ def test_full_game_sampled_roots():
                 checked += hi - lo
     print(f"[infoset] full game seed 1: {checked} sampled rows identical", flush=True)
     s.free()
+
+
+def test_models_on_infoset_rows():
+    """The strategy models on infoset rows run end to end: the network
+    trains on them (loss falls), the tree model's data holds each sampled
+    decision's full average strategy (100 per parent), and the profiles both
+    models predict are valid (finite, non-negative exploitability)."""
+    pa = require_gpu()
+    from paper_2508_06559_amd import learn
+    probs = [synth.two_round_root(s) for s in range(50000, 50006)]
+    units = learn.training_units(probs, 200, 150, features="infoset")
+    m = learn.WarmStartMLP(0)
+    hist = learn.train(m, units, 4)
+    assert hist[-1][0] < hist[0][0]
+    rows, tgt, grp = learn.infoset_dataset(probs[:3], 200, 100)
+    assert rows.dtype == np.int8 and rows.shape[1] == 58 and len(rows) == len(tgt) == len(grp)
+    np.testing.assert_allclose(np.bincount(grp, weights=tgt), 100.0, atol=1e-3)
+    tree = learn.fit_tree_model(rows, tgt, max_iter=20)
+    deck, roots = synth.two_round_root(50010)
+    ex = [learn.initial_profile_exploitability(deck, roots, None),
+          learn.initial_profile_exploitability(deck, roots, m, "infoset"),
+          learn.tree_profile_exploitability(deck, roots, tree)]
+    print(f"[infoset] starting-profile exploitability uniform / network / tree: {ex}", flush=True)
+    assert all(np.isfinite(ex)) and min(ex) >= 0
