@@ -286,15 +286,18 @@ int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds, const void *const
  * PASUR_ES_LEVEL, two launches per level and pass over every node.
  * roots_per_wg: consecutive roots per workgroup of the frontier schedule
  * (0 = about 4096 tree nodes per workgroup, at least one root).
- * `workspace` (device, caller-owned) holds two int32 per node of levels
- * 0..7 (picks and frontier lists): pasur_es_workspace_bytes(fgt) bytes
- * (negative on error).  Calls on one workspace must not overlap.
+ * `workspace` (device, caller-owned, 32-byte aligned): the frontier
+ * schedule packs each node's sigma, R, Sbar and u into one record there for
+ * the call (levels 0..8) and keeps two int32 per node of levels 0..7
+ * (frontier lists and their choices); the level schedule uses one int32 per
+ * node.  pasur_es_workspace_bytes(fgt, dtype) bytes (negative on error).
+ * Calls on one workspace must not overlap.
  * d_stats (device, 4 uint64, or NULL; frontier schedule only) gains the
  * work done: reached nodes of the updated player, their children, reached
  * opponent nodes, their children (over all passes).
  * Asynchronous on `stream`. */
 enum { PASUR_ES_FRONTIER = 0, PASUR_ES_LEVEL = 1 };
-int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt);
+int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt, int dtype);
 int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0,
                      int64_t n_iters, uint64_t seed, int rm_mode, double eps, int schedule,
                      int roots_per_wg, void *workspace, int64_t workspace_bytes,

@@ -109,7 +109,7 @@ def lib():
         L.pasur_selfplay.argtypes = [vp, i32, vp, i32, i32, i64, C.c_uint64, i32, i32, vp, vp]
         L.pasur_infoset_rows.argtypes = [vp, vp, i32, vp, i64, i32, vp, vp]
         L.pasur_es_workspace_bytes.restype = i64
-        L.pasur_es_workspace_bytes.argtypes = [vp]
+        L.pasur_es_workspace_bytes.argtypes = [vp, i32]
         L.pasur_es_iterate.argtypes = [vp, vp, i64, i64, C.c_uint64, i32, C.c_double, i32, i32, vp,
                                        i64, vp, vp]
         L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
@@ -466,8 +466,8 @@ def mlp_transpose(w: MlpWeights, W1t, W2t, stream=None):
 PLAY_SIGMA_BAR, PLAY_UNIFORM = 0, 1
 
 
-def es_workspace_bytes(fgt: UnfoldedTree) -> int:
-    n = lib().pasur_es_workspace_bytes(fgt.h)
+def es_workspace_bytes(fgt: UnfoldedTree, dtype: int) -> int:
+    n = lib().pasur_es_workspace_bytes(fgt.h, dtype)
     if n < 0:
         _check(int(n), "pasur_es_workspace_bytes")
     return int(n)
@@ -496,7 +496,7 @@ def es_iterate(st: CfrState, n_iters: int, seed: int, rm_mode: int = RM_FLOOR, e
     on the state.  stats: optional int64 device tensor of 4 counters (frontier
     schedule) that gains the work done (see pasur_es_iterate)."""
     torch = _torch()
-    nb = es_workspace_bytes(st.fgt)
+    nb = es_workspace_bytes(st.fgt, st.dtype)
     if st.es_ws is None or st.es_ws.numel() < max(nb, 1):
         st.es_ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
     t = st.es_t if t0 is None else t0

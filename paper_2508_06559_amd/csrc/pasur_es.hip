@@ -139,15 +139,53 @@ __global__ void k_es_up(EsLevel a) {
 }
 
 // ---- frontier schedule -------------------------------------------------------
+// The state of a node sits in one record (the strategy, regret and average
+// sum of the edge into it, and its value), packed from the solver's arrays
+// when a call starts and unpacked when it ends: a reached node's children
+// then share one or two cache lines instead of four arrays' worth.
+
+template <class T>
+struct alignas(4 * sizeof(T)) EsRec {
+  T sg, R, Sb, u;
+};
+
+template <class T>
+__global__ void k_es_pack(int64_t n, const T *sg, const T *R, const T *Sb, const T *u,
+                          EsRec<T> *rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  EsRec<T> x;
+  x.sg = sg ? sg[i] : (T)0;
+  x.R = R ? R[i] : (T)0;
+  x.Sb = Sb ? Sb[i] : (T)0;
+  x.u = u[i];
+  rec[i] = x;
+}
+
+template <class T>
+__global__ void k_es_unpack(int64_t n, const EsRec<T> *rec, T *sg, T *R, T *Sb, T *u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const EsRec<T> x = rec[i];
+  if (sg) {
+    sg[i] = x.sg;
+    R[i] = x.R;
+    Sb[i] = x.Sb;
+  }
+  u[i] = x.u;
+}
 
 struct EsSegArgs {
-  EsLevel lv[8];               // seed, base (level offset only), l, rm_mode, eps set; p per pass
+  const int32_t *cb[8];
+  void *rec[9];                // records of each level
   const int32_t *root_off[9];  // level-l node range of each root
-  int32_t *front;              // frontier lists, level l at off[l] (like the picks)
+  int32_t *front;              // frontier lists, level l at off[l]
+  int32_t *choice;             // per frontier entry: kAll or the kept child
   int64_t off[9];
   int64_t n_roots, n_iters, t0;
-  uint64_t N;
-  int roots_per_wg;
+  uint64_t N, seed;
+  int roots_per_wg, rm_mode;
+  double eps;
   unsigned long long *stats;   // optional: visits and kept children, see pasur_es_iterate
 };
 
@@ -167,6 +205,83 @@ __device__ __forceinline__ int wave_reserve(int k, int *counter) {
   return base + x - k;
 }
 
+// Down step of reached node h of level l on records (as down_node): returns
+// the first kept child, the number kept in *k, the number of children in
+// *kids and the entry's choice in *ch.
+template <class T>
+__device__ __forceinline__ int32_t rec_down(const EsSegArgs &a, int l, int p, uint64_t base,
+                                            int64_t h, int *k, int *kids, int32_t *ch) {
+  const int32_t b = a.cb[l][h], e = a.cb[l][h + 1];
+  *kids = e - b;
+  if ((l & 1) == p) {
+    *ch = kAll;
+    *k = e - b;
+    return b;
+  }
+  EsRec<T> *rc = reinterpret_cast<EsRec<T> *>(a.rec[l + 1]);
+  const int kk = e - b;
+  int j = 0;
+  if (kk > 1) {
+    // inverse CDF of the children's strategy, as choose() does it
+    const double u = splitmix_uniform(a.seed, base + (uint64_t)h);
+    const int uni = min((int)(u * (double)kk), kk - 1);
+    double total = 0.0;
+    for (int c = b; c < e; ++c) total += (double)rc[c].sg;
+    if (!(total > 0.0)) {
+      j = uni;
+    } else {
+      const double x = u * total;
+      double acc = 0.0;
+      int last = 0;
+      j = -1;
+      for (int c = 0; c < kk; ++c) {
+        const double pc = (double)rc[b + c].sg;
+        acc += pc;
+        if (pc > 0.0) last = c;
+        if (acc > x) {
+          j = c;
+          break;
+        }
+      }
+      if (j < 0) j = last;
+    }
+  }
+  for (int c = b; c < e; ++c) rc[c].Sb = (T)((double)rc[c].Sb + (double)rc[c].sg);
+  *ch = b + j;
+  *k = 1;
+  return b + j;
+}
+
+// Up step of reached node h of level l on records (as up_node).
+template <class T>
+__device__ __forceinline__ void rec_up(const EsSegArgs &a, int l, int p, int64_t h, int32_t ch) {
+  EsRec<T> *rc = reinterpret_cast<EsRec<T> *>(a.rec[l + 1]);
+  EsRec<T> *rl = reinterpret_cast<EsRec<T> *>(a.rec[l]);
+  if (ch != kAll) {
+    rl[h].u = rc[ch].u;
+    return;
+  }
+  const int32_t b = a.cb[l][h], e = a.cb[l][h + 1];
+  double acc = 0.0;
+  for (int32_t c = b; c < e; ++c) acc += (double)rc[c].sg * (double)rc[c].u;
+  const T uh = (T)acc;
+  rl[h].u = uh;
+  const double v = (double)uh;
+  double sum = 0.0;
+  for (int32_t c = b; c < e; ++c) {
+    const double w = (double)rc[c].u;
+    const T r = (T)((double)rc[c].R + (p == 0 ? w - v : v - w));
+    rc[c].R = r;
+    sum += a.rm_mode == PASUR_RM_FLOOR ? fmax((double)r, a.eps) : fmax((double)r, 0.0);
+  }
+  const double inv_k = 1.0 / (double)(e - b);
+  for (int32_t c = b; c < e; ++c) {
+    const double x = a.rm_mode == PASUR_RM_FLOOR ? fmax((double)rc[c].R, a.eps)
+                                                 : fmax((double)rc[c].R, 0.0);
+    rc[c].sg = (T)(sum > 0.0 ? x / sum : inv_k);
+  }
+}
+
 template <class T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_es_frontier(EsSegArgs a) {
   __shared__ int cnt[9];
@@ -184,9 +299,7 @@ __global__ __launch_bounds__(BLOCK) void k_es_frontier(EsSegArgs a) {
       __syncthreads();
 #pragma unroll
       for (int l = 0; l < 8; ++l) {
-        EsLevel lv = a.lv[l];
-        lv.p = p;
-        lv.base = pass_base + (uint64_t)a.off[l];
+        const uint64_t base = pass_base + (uint64_t)a.off[l];
         const int m = l == 0 ? (int)(r1 - r0) : cnt[l];
         for (int i0 = 0; i0 < m; i0 += BLOCK) {
           const int i = i0 + (int)threadIdx.x;
@@ -194,7 +307,9 @@ __global__ __launch_bounds__(BLOCK) void k_es_frontier(EsSegArgs a) {
           int32_t first = 0;
           if (i < m) {
             const int64_t h = l == 0 ? r0 + i : (int64_t)a.front[seg[l] + i];
-            first = down_node<T>(lv, h, &k, &kids);
+            int32_t ch;
+            first = rec_down<T>(a, l, p, base, h, &k, &kids, &ch);
+            a.choice[seg[l] + i] = ch;
             if ((l & 1) == p) {
               ++n_trav;
               e_trav += kids;
@@ -213,12 +328,10 @@ __global__ __launch_bounds__(BLOCK) void k_es_frontier(EsSegArgs a) {
       }
 #pragma unroll
       for (int l = 7; l >= 0; --l) {
-        EsLevel lv = a.lv[l];
-        lv.p = p;
         const int m = l == 0 ? (int)(r1 - r0) : cnt[l];
         for (int i = (int)threadIdx.x; i < m; i += BLOCK) {
           const int64_t h = l == 0 ? r0 + i : (int64_t)a.front[seg[l] + i];
-          up_node<T>(lv, h);
+          rec_up<T>(a, l, p, h, a.choice[seg[l] + i]);
         }
         __syncthreads();
       }
@@ -260,22 +373,40 @@ constexpr int64_t kNodesPerWorkgroup = 4096;
 
 template <class T>
 int es_run(const pasur_fgt *f, const pasur_cfr_state *st, int64_t t0, int64_t n_iters,
-           uint64_t seed, int rm_mode, double eps, int schedule, int roots_per_wg, int32_t *ws,
+           uint64_t seed, int rm_mode, double eps, int schedule, int roots_per_wg, void *ws,
            unsigned long long *stats, hipStream_t s) {
   int64_t off[9];
   off[0] = 0;
   for (int l = 0; l < 8; ++l) off[l + 1] = off[l] + f->n[l];
   const uint64_t N = (uint64_t)off[8];
-  int32_t *picks = ws;
+  int32_t *picks = reinterpret_cast<int32_t *>(ws);
   if (f->n[0] == 0) return PASUR_OK;
   if (schedule == PASUR_ES_FRONTIER) {
+    // workspace: the records of levels 0..8, then the frontier lists and
+    // the entries' choices of levels 0..7
+    EsRec<T> *recs = reinterpret_cast<EsRec<T> *>(ws);
+    int64_t roff = 0;
     EsSegArgs a;
-    fill_levels(a.lv, f, st, off, picks, seed, rm_mode, eps);
+    for (int l = 0; l < 9; ++l) {
+      a.rec[l] = recs + roff;
+      const int64_t n = f->n[l];
+      if (n > 0)
+        k_es_pack<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+            n, l > 0 ? (const T *)st->sigma[l] : nullptr, l > 0 ? (const T *)st->R[l] : nullptr,
+            l > 0 ? (const T *)st->Sbar[l] : nullptr, (const T *)st->u[l], recs + roff);
+      roff += n;
+    }
+    int32_t *lists = reinterpret_cast<int32_t *>(recs + roff);
+    for (int l = 0; l < 8; ++l) a.cb[l] = f->child_begin[l];
     for (int l = 0; l < 9; ++l) {
       a.root_off[l] = f->root_off[l];
       a.off[l] = off[l];
     }
-    a.front = ws + N;
+    a.front = lists;
+    a.choice = lists + N;
+    a.seed = seed;
+    a.rm_mode = rm_mode;
+    a.eps = eps;
     a.n_roots = f->n_roots;
     a.n_iters = n_iters;
     a.t0 = t0;
@@ -288,6 +419,13 @@ int es_run(const pasur_fgt *f, const pasur_cfr_state *st, int64_t t0, int64_t n_
     a.stats = stats;
     const unsigned grid = (unsigned)((f->n_roots + a.roots_per_wg - 1) / a.roots_per_wg);
     k_es_frontier<T, kFrontierBlock><<<grid, kFrontierBlock, 0, s>>>(a);
+    for (int l = 0; l < 9; ++l) {
+      const int64_t n = f->n[l];
+      if (n > 0)
+        k_es_unpack<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+            n, reinterpret_cast<const EsRec<T> *>(a.rec[l]), l > 0 ? (T *)st->sigma[l] : nullptr,
+            l > 0 ? (T *)st->R[l] : nullptr, l > 0 ? (T *)st->Sbar[l] : nullptr, (T *)st->u[l]);
+    }
     PASUR_TRY_HIP(hipGetLastError());
     return PASUR_OK;
   }
@@ -319,14 +457,20 @@ int es_run(const pasur_fgt *f, const pasur_cfr_state *st, int64_t t0, int64_t n_
 
 }  // namespace
 
-extern "C" int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt) {
+extern "C" int64_t pasur_es_workspace_bytes(const pasur_fgt *fgt, int dtype) {
   if (!fgt) {
     set_error("fgt is NULL");
     return PASUR_E_INVAL;
   }
-  int64_t n = 0;
-  for (int l = 0; l < 8; ++l) n += fgt->n[l];
-  return 2 * n * (int64_t)sizeof(int32_t);
+  if (dtype != PASUR_F32 && dtype != PASUR_F64) {
+    set_error("unknown dtype %d", dtype);
+    return PASUR_E_RANGE;
+  }
+  int64_t n8 = 0;
+  for (int l = 0; l < 8; ++l) n8 += fgt->n[l];
+  const int64_t n9 = n8 + fgt->n[8];
+  const int64_t rec = dtype == PASUR_F32 ? (int64_t)sizeof(EsRec<float>) : (int64_t)sizeof(EsRec<double>);
+  return n9 * rec + 2 * n8 * (int64_t)sizeof(int32_t);
 }
 
 extern "C" int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0,
@@ -367,14 +511,18 @@ extern "C" int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st,
       return PASUR_E_INVAL;
     }
   }
-  const int64_t need = pasur_es_workspace_bytes(fgt);
+  const int64_t need = pasur_es_workspace_bytes(fgt, st->dtype);
   if (!workspace || workspace_bytes < need) {
     set_error("workspace of %lld bytes needed, %lld given", (long long)need,
               (long long)(workspace ? workspace_bytes : 0));
     return PASUR_E_INVAL;
   }
   if (n_iters == 0) return PASUR_OK;
-  int32_t *ws = reinterpret_cast<int32_t *>(workspace);
+  if ((reinterpret_cast<uintptr_t>(workspace) & 31) != 0) {
+    set_error("workspace must be 32-byte aligned");
+    return PASUR_E_INVAL;
+  }
+  void *ws = workspace;
   unsigned long long *stats = reinterpret_cast<unsigned long long *>(d_stats);
   hipStream_t s = (hipStream_t)stream;
   if (st->dtype == PASUR_F32)

@@ -157,8 +157,8 @@ def test_es_checks(lib):
                   vp, C.c_int64, vp, vp]
     wb = lib.pasur_es_workspace_bytes
     wb.restype = C.c_int64
-    wb.argtypes = [vp]
-    assert wb(None) == E_INVAL
+    wb.argtypes = [vp, C.c_int]
+    assert wb(None, 0) == E_INVAL
     st = full_state()
     expect(lib, f(None, C.byref(st), 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_INVAL, ["NULL"])
     expect(lib, f(DUMMY, None, 0, 1, 1, 0, 1e-8, 0, 0, DUMMY, 64, None, None), E_INVAL, ["NULL"])
