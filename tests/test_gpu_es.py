@@ -116,3 +116,15 @@ def test_es_full_game():
     a, b = res[50]
     assert all(np.array_equal(x, y) for x, y in zip(a[1], b[1])) and a[2] == b[2]
     assert res[400][0][0] < 0.5 * a[0]
+
+
+def test_es_zero_iterations_and_empty_rounds_change_nothing():
+    pa = require_gpu()
+    deck, roots = synth.last_round_roots(3)
+    s, rr, st = gpu_round(pa, deck, roots, pa.PASUR_F64)
+    before = [to_np(x).copy() for x in st.sigma[1:] + st.R[1:] + st.Sbar[1:]]
+    for sch in (pa.ES_FRONTIER, pa.ES_LEVEL):
+        pa.es_iterate(st, 0, 5, schedule=sch)
+    after = [to_np(x) for x in st.sigma[1:] + st.R[1:] + st.Sbar[1:]]
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+    s.free()

@@ -116,3 +116,17 @@ def test_models_on_infoset_rows():
           learn.tree_profile_exploitability(deck, roots, tree)]
     print(f"[infoset] starting-profile exploitability uniform / network / tree: {ex}", flush=True)
     assert all(np.isfinite(ex)) and min(ex) >= 0
+
+
+def test_empty_edge_list():
+    pa = require_gpu()
+    import torch
+    deck, roots = synth.last_round_roots(3)
+    s = pa.SubgameSolver(deck, 5, roots, keep_gt=True)
+    rr = s.rounds[0]
+    idx = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = torch.full((1, pa.INFOSET_WIDTH), 9, dtype=torch.int8, device="cuda")
+    pa.infoset_rows(rr.gt, rr.fgt, 3, idx, 0, out)
+    torch.cuda.synchronize()
+    assert (to_np(out) == 9).all()
+    s.free()

@@ -91,3 +91,22 @@ def test_full_game_mean_margin_matches_expectation():
     check((U, U), exact())
     assert m[(S, U)].std() > 0 and m[(U, U)].std() > 0
     s.free()
+
+
+def test_single_round_other_root_and_empty_call():
+    """One round (the final-round subgame of seven roots), games from root 5,
+    game by game against the oracle; zero games is a valid empty call."""
+    pa = require_gpu()
+    deck, roots = synth.last_round_roots(2)
+    s = pa.SubgameSolver(deck, 5, roots, dtype=pa.PASUR_F64)
+    s.solve(60)
+    gt = oracle.GT(deck, 5, sorted({x.pool for x in roots}))
+    f = oracle.FGT(gt, roots)
+    sb = [None] + [to_np(x).copy() for x in s.rounds[0].state.sigma_bar[1:]]
+    rounds = [{"cb": f.child_begin(), "sbar": sb, "link": None, "base": f.leaf_utilities()}]
+    for pp in ((pa.PLAY_SIGMA_BAR, pa.PLAY_UNIFORM), (pa.PLAY_UNIFORM, pa.PLAY_UNIFORM)):
+        got = to_np(s.selfplay(1500, 7, *pp, root=5)).astype(np.int64)
+        want = sp.play(rounds, 1500, 7, pp[0], pp[1], 5)
+        assert np.array_equal(got, want), pp
+    assert s.selfplay(0, 7).numel() == 0
+    s.free()
