@@ -13,8 +13,8 @@ deals in one persistent launch per round, HIP-graph replay), full-game (all
 six rounds of one deal), paper-scale (32 full games as one batch),
 warm-start (learned warm start vs plain DCFR), selfplay (games/s and fair
 values on a solved full game), es (external-sampling CFR on a full game),
-infoset (infoset rows of a full game; strategy models on them), copy
-(counter calibration).
+infoset (infoset rows of a full game; strategy models on them), mlp (the
+network's MFMA kernels alone), copy (counter calibration).
 
 Prints one JSON line: the metric and its value, the step time, the
 dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
@@ -322,8 +322,8 @@ def bench_warm(args):
     b.record()
     b.synchronize()
     train_ms = a.elapsed_time(b)
-    per_row = 2 * (learn.N_IN * 256 + 256 * 256 + 256 * 2)
-    train_tflops = 3 * per_row * rows / (train_ms * 1e-3) / 1e12
+    per_row = MLP_FWD_FLOP
+    train_tflops = MLP_TRAIN_FLOP * rows / (train_ms * 1e-3) / 1e12
     hist += learn.train(model, units, args.epochs - 1, seed=0, log=log)
     big = torch.zeros((1 << 20, learn.N_IN), dtype=torch.int16, device="cuda")
     Yb = torch.empty((big.shape[0], 2), dtype=torch.float32, device="cuda")
@@ -706,6 +706,82 @@ def bench_infoset(args):
     print(json.dumps(res), flush=True)
 
 
+MLP_FWD_FLOP = 2 * (192 * 256 + 256 * 256 + 256 * 2)          # per row
+# per row of a training step: forward, then the weight gradients of all
+# three layers and the input gradients of layers 2 and 3 (layer 1 needs none)
+MLP_TRAIN_FLOP = MLP_FWD_FLOP + 2 * 192 * 256 + 2 * (2 * 256 * 256) + 2 * (2 * 256 * 2)
+
+
+def bench_mlp(args):
+    """The warm-start network's MFMA kernels on their own, on synthetic
+    feature rows (card bits set with probability 1/4, score and level
+    columns as the feature layout fills them): --steps timed calls of the
+    fused inference (k_mlp_infer) over 2^20 rows, and --steps training steps
+    (three-GEMM forward, loss, backward, Adam) over 2^18 rows in groups of
+    four siblings, each timed with HIP events on the launch stream."""
+    import torch
+    from paper_2508_06559_amd import learn
+    import paper_2508_06559_amd as pa
+
+    rng = np.random.default_rng(5)
+
+    def rows(n):
+        x = np.zeros((n, learn.N_IN), np.float32)
+        x[:, :156] = rng.random((n, 156)) < 0.25
+        x[:, 156:167] = rng.random((n, 11)) * 2 - 1
+        x[np.arange(n), 167 + rng.integers(1, 9, n)] = 1.0
+        return torch.from_numpy(x).cuda().bfloat16().view(torch.int16)
+
+    model = learn.WarmStartMLP(0)
+    n_inf, n_tr = 1 << 20, 1 << 18
+    X = rows(n_inf)
+    Y = torch.empty((n_inf, 2), dtype=torch.float32, device="cuda")
+    w = model.infer_weights()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(args.warmup):
+        pa.mlp_infer(w, X, n_inf, Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for _ in range(args.steps):
+        pa.mlp_infer(w, X, n_inf, Y)
+    ev[1].record()
+    ev[1].synchronize()
+    el = time.perf_counter() - t0
+    inf_ms = ev[0].elapsed_time(ev[1]) / args.steps
+    inf_tf = MLP_FWD_FLOP * n_inf / (inf_ms * 1e-3) / 1e12
+
+    Xt = rows(n_tr)
+    seg = torch.arange(0, n_tr + 1, 4, dtype=torch.int32, device="cuda")
+    tsig = torch.full((n_tr,), 0.25, dtype=torch.float32, device="cuda")
+    tval = torch.from_numpy(rng.normal(0, 3, n_tr).astype(np.float32)).cuda()
+    unit = learn.Unit(Xt, seg, tsig, tval, n_tr // 4, n_tr)
+    for _ in range(args.warmup):
+        model.train_unit(unit, 1e-3)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(args.steps):
+        model.train_unit(unit, 1e-3)
+    ev[1].record()
+    ev[1].synchronize()
+    tr_ms = ev[0].elapsed_time(ev[1]) / args.steps
+    tr_tf = MLP_TRAIN_FLOP * n_tr / (tr_ms * 1e-3) / 1e12
+    out = {"metric": "warm-start MLP inference TFLOP/s at 1 GPU", "value": inf_tf, "unit": "TFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": f"192-256-256-2 MLP: fused inference over {n_inf} rows per call; "
+                                  f"training steps over {n_tr} rows",
+                      "inference_ms_per_call": inf_ms, "training_ms_per_step": tr_ms,
+                      "training_TFLOPs": tr_tf, "flop_per_row_inference": MLP_FWD_FLOP,
+                      "flop_per_row_training": MLP_TRAIN_FLOP},
+           "roofline": {"bound": "mfma", "kernel": "k_mlp_infer (three layers fused, BF16 MFMA 16x16x32, "
+                                                   "FP32 accumulate)",
+                        "achieved": inf_tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": inf_tf / 2500.0,
+                        "traffic": None}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -718,7 +794,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game",
-                                           "paper-scale", "selfplay", "es", "infoset", "copy"],
+                                           "paper-scale", "selfplay", "es", "infoset", "mlp", "copy"],
                     default="two-round",
                     help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
@@ -759,6 +835,8 @@ def main():
         return bench_es(args)
     if args.workload == "infoset":
         return bench_infoset(args)
+    if args.workload == "mlp":
+        return bench_mlp(args)
     if args.workload == "copy":
         # calibration for hardware byte counters: a plain device copy of a
         # known size (256 MiB read + 256 MiB written per launch, 4 launches)

@@ -368,7 +368,8 @@ int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M, fl
 /* W1t = W1^T [256][192], W2t = W2^T [256][256] (BF16, caller-owned). */
 int pasur_mlp_transpose(const pasur_mlp_weights *w, uint16_t *W1t, uint16_t *W2t, void *stream);
 /* Gradients of the loss with respect to the weights given dY [M][2] (FP32);
- * dY is rounded to BF16 for the GEMMs.  Uses stream-ordered scratch. */
+ * dY is rounded to BF16 for the GEMMs.  H1 and H2 must be 8-byte aligned
+ * (PASUR_E_INVAL otherwise).  Uses stream-ordered scratch. */
 int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X, const uint16_t *H1,
                        const uint16_t *H2, const float *dY, int64_t M, pasur_mlp_grads *g,
                        void *stream);

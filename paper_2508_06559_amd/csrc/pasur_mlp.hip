@@ -5,6 +5,8 @@
 // BF16 operands, FP32 accumulation).
 #include "pasur_internal.hpp"
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -13,6 +15,7 @@
 using namespace pasur;
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 namespace {
@@ -53,19 +56,50 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const __bf16 zero = (__bf16)0.f;
+  // 16-byte aligned operands and K-range starts (the fast tile loads need both)
+  const bool a_al = ((reinterpret_cast<uintptr_t>(g.A) & 15) == 0) && (kbeg & 7) == 0;
+  const bool b_al = ((reinterpret_cast<uintptr_t>(g.B) & 15) == 0) && (kbeg & 7) == 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // global -> LDS, the contiguous global direction fastest across threads
-    for (int e = tid; e < BM * BK; e += 256) {
-      int r, c;
-      if (g.sac == 1) { r = e / BK; c = e % BK; } else { c = e / BM; r = e % BM; }
-      const int m = m0 + r, k = k0 + c;
-      As[r][c] = (m < g.M && k < kend) ? g.A[m * g.sar + k * g.sac] : zero;
+    // global -> LDS.  A full tile whose contiguous global direction is K
+    // takes one 16-byte load per thread straight into its LDS row; one whose
+    // contiguous direction is the rows (columns of B) takes a 16-byte load of
+    // eight rows at one k and spreads it down the LDS column.  Edge tiles and
+    // unaligned operands go element by element.
+    const bool full_a = m0 + BM <= g.M && k0 + BK <= kend && a_al;
+    if (full_a && g.sac == 1 && (g.sar & 7) == 0) {
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      *reinterpret_cast<bf16x8 *>(&As[r][c]) =
+          *reinterpret_cast<const bf16x8 *>(g.A + (int64_t)(m0 + r) * g.sar + (k0 + c));
+    } else if (full_a && g.sar == 1 && (g.sac & 7) == 0) {
+      const int c = tid >> 3, r = (tid & 7) * 8;
+      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(g.A + (int64_t)(k0 + c) * g.sac + (m0 + r));
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[r + j][c] = v[j];
+    } else {
+      for (int e = tid; e < BM * BK; e += 256) {
+        int r, c;
+        if (g.sac == 1) { r = e / BK; c = e % BK; } else { c = e / BM; r = e % BM; }
+        const int m = m0 + r, k = k0 + c;
+        As[r][c] = (m < g.M && k < kend) ? g.A[m * g.sar + k * g.sac] : zero;
+      }
     }
-    for (int e = tid; e < BN * BK; e += 256) {
-      int r, c;
-      if (g.sbr == 1) { r = e / BK; c = e % BK; } else { c = e / BN; r = e % BN; }
-      const int n = n0 + r, k = k0 + c;
-      Bs[r][c] = (n < g.N && k < kend) ? g.B[k * g.sbr + n * g.sbc] : zero;
+    const bool full_b = n0 + BN <= g.N && k0 + BK <= kend && b_al;
+    if (full_b && g.sbr == 1 && (g.sbc & 7) == 0) {
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      *reinterpret_cast<bf16x8 *>(&Bs[r][c]) =
+          *reinterpret_cast<const bf16x8 *>(g.B + (int64_t)(n0 + r) * g.sbc + (k0 + c));
+    } else if (full_b && g.sbc == 1 && (g.sbr & 7) == 0) {
+      const int c = tid >> 3, r = (tid & 7) * 8;
+      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(g.B + (int64_t)(k0 + c) * g.sbr + (n0 + r));
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Bs[r + j][c] = v[j];
+    } else {
+      for (int e = tid; e < BN * BK; e += 256) {
+        int r, c;
+        if (g.sbr == 1) { r = e / BK; c = e % BK; } else { c = e / BN; r = e % BN; }
+        const int n = n0 + r, k = k0 + c;
+        Bs[r][c] = (n < g.N && k < kend) ? g.B[k * g.sbr + n * g.sbc] : zero;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -122,9 +156,22 @@ __global__ void k_split_sum(const float *__restrict__ part, int splits, int64_t 
 
 // Column sums of a row-major [M, N] FP32 matrix (bias gradients) in two
 // deterministic passes: block (x, y) sums rows y*chunk .. of 64 columns
-// (consecutive threads, consecutive columns) into part[y][n]; k_split_sum
-// then adds the kColChunks partials of each column in order.
-constexpr int kColChunks = 128;
+// (consecutive threads, consecutive columns) into part[y][n]; k_col_merge
+// then adds the kColChunks partials of each column.
+constexpr int kColChunks = 1024;
+
+// Second pass of the column sums: one wave per column, lane j adds partials
+// j, j + 64, ... in order, then the lanes combine in a fixed shuffle tree
+// (deterministic).
+__global__ void __launch_bounds__(64) k_col_merge(const float *__restrict__ part, int chunks, int N,
+                                                  float *__restrict__ out) {
+  const int n = blockIdx.x, lane = threadIdx.x;
+  float s = 0.f;
+  for (int z = lane; z < chunks; z += 64) s += part[(int64_t)z * N + n];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
+  if (lane == 0) out[n] = s;
+}
 
 __global__ void k_col_sum_part(const float *__restrict__ X, int64_t M, int N, int64_t chunk,
                                float *__restrict__ part) {
@@ -137,13 +184,22 @@ __global__ void k_col_sum_part(const float *__restrict__ X, int64_t M, int N, in
 }
 
 // dH = G * (H > 0) for ReLU layers, FP32 in, BF16 out (also FP32 copy).
+// Four elements per thread (n is a multiple of 4: rows x 256 columns).
 __global__ void k_relu_back(const float *__restrict__ G, const __bf16 *__restrict__ H, int64_t n,
                             float *__restrict__ outf, __bf16 *__restrict__ outb) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   if (i >= n) return;
-  const float v = (float)H[i] > 0.f ? G[i] : 0.f;
-  outf[i] = v;
-  outb[i] = (__bf16)v;
+  const float4 g = *reinterpret_cast<const float4 *>(G + i);
+  const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H + i);
+  const float4 v = make_float4((float)h[0] > 0.f ? g.x : 0.f, (float)h[1] > 0.f ? g.y : 0.f,
+                               (float)h[2] > 0.f ? g.z : 0.f, (float)h[3] > 0.f ? g.w : 0.f);
+  *reinterpret_cast<float4 *>(outf + i) = v;
+  bf16x4 b;
+  b[0] = (__bf16)v.x;
+  b[1] = (__bf16)v.y;
+  b[2] = (__bf16)v.z;
+  b[3] = (__bf16)v.w;
+  *reinterpret_cast<bf16x4 *>(outb + i) = b;
 }
 
 __global__ void k_f32_to_bf16(const float *__restrict__ x, int64_t n, __bf16 *__restrict__ y) {
@@ -335,7 +391,7 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStream_t s) {
   const int64_t chunk = (M + kColChunks - 1) / kColChunks;
   k_col_sum_part<<<dim3((unsigned)((N + 63) / 64), kColChunks), 64, 0, s>>>(X, M, N, chunk, part);
-  k_split_sum<<<blocks(N), 256, 0, s>>>(part, kColChunks, N, out);
+  k_col_merge<<<(unsigned)N, 64, 0, s>>>(part, kColChunks, N, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,6 +600,10 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     set_error("bad MLP backward arguments");
     return PASUR_E_INVAL;
   }
+  if ((reinterpret_cast<uintptr_t>(H1) & 7) || (reinterpret_cast<uintptr_t>(H2) & 7)) {
+    set_error("H1 and H2 must be 8-byte aligned");
+    return PASUR_E_INVAL;
+  }
   hipStream_t s = (hipStream_t)stream;
   const int m = (int)M;
   // workspace: dY in BF16, dH (FP32 and BF16) for both hidden layers, split-K partials
@@ -551,7 +611,8 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
   const int kchunk = ((m + splits - 1) / splits + BK - 1) / BK * BK;
   __bf16 *dYb = nullptr, *G2b = nullptr, *G1b = nullptr;
   float *G2f = nullptr, *G1f = nullptr, *part = nullptr;
-  const size_t part_n = (size_t)splits * kHid * kHid;
+  // split-K partials of the weight gradients, or the column-sum partials of the bias gradients
+  const size_t part_n = std::max((size_t)splits * kHid * kHid, (size_t)kColChunks * kHid);
   hipError_t e = hipMallocAsync((void **)&dYb, sizeof(__bf16) * m * kOut, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&G2b, sizeof(__bf16) * (size_t)m * kHid, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&G1b, sizeof(__bf16) * (size_t)m * kHid, s);
@@ -593,7 +654,7 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     st = gemm(g, 1, s);
   }
   if (!st) {
-    k_relu_back<<<blocks((int64_t)m * kHid), 256, 0, s>>>(G2f, (const __bf16 *)H2, (int64_t)m * kHid,
+    k_relu_back<<<blocks((int64_t)m * kHid / 4), 256, 0, s>>>(G2f, (const __bf16 *)H2, (int64_t)m * kHid,
                                                           G2f, G2b);
     st = dW((const __bf16 *)H1, kHid, G2b, kHid, gr->dW2);
   }
@@ -608,7 +669,7 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     st = gemm(g, 1, s);
   }
   if (!st) {
-    k_relu_back<<<blocks((int64_t)m * kHid), 256, 0, s>>>(G1f, (const __bf16 *)H1, (int64_t)m * kHid,
+    k_relu_back<<<blocks((int64_t)m * kHid / 4), 256, 0, s>>>(G1f, (const __bf16 *)H1, (int64_t)m * kHid,
                                                           G1f, G1b);
     st = dW((const __bf16 *)X, kIn, G1b, kHid, gr->dW1);
   }
