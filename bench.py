@@ -18,9 +18,9 @@ network's MFMA kernels alone), copy (counter calibration).
 
 Prints one JSON line: the metric and its value, the step time, the
 dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
-against the MI355X peak, with counter-measured HBM traffic when recorded
-for this kernel source) and, for the default workload, the FP64 CPU
-oracle's rate on the host (cpu_baseline).
+against the MI355X peak, with counter-measured HBM traffic per launch and
+its rate, `traffic_GBs`, when recorded for this kernel source) and, for the
+default workload, the FP64 CPU oracle's rate on the host (cpu_baseline).
 """
 import argparse
 import json
@@ -192,6 +192,8 @@ def bench_batched(args):
                                              f"largest launch",
                      "achieved": db / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": db / dt / 1e9 / HBM_PEAK_GBS, "traffic": counted_traffic(args, "batched"),
+                     "traffic_GBs": (counted_traffic(args, "batched") / dt / 1e9
+                                     if counted_traffic(args, "batched") is not None else None),
                      "avg_launch_us": dt * 1e6, "algorithmic_bytes_per_launch": db,
                      "all_sweeps_GBs": tot_b / tot_t / 1e9},
     }
@@ -936,6 +938,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": counted_traffic(args),
+            "traffic_GBs": (counted_traffic(args) / (dt / dc) / 1e9
+                            if counted_traffic(args) is not None else None),
             "avg_launch_us": dt / dc * 1e6,
             "launches": dc,
             "algorithmic_bytes_per_launch": db / dc,
