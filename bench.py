@@ -14,7 +14,8 @@ six rounds of one deal), paper-scale (32 full games as one batch),
 warm-start (learned warm start vs plain DCFR), selfplay (games/s and fair
 values on a solved full game), es (external-sampling CFR on a full game),
 infoset (infoset rows of a full game; strategy models on them), mlp (the
-network's MFMA kernels alone), copy (counter calibration).
+network's MFMA kernels alone), variants (DCFR, CFR+ and vanilla CFR
+convergence), copy (counter calibration).
 
 Prints one JSON line: the metric and its value, the step time, the
 dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
@@ -784,6 +785,71 @@ def bench_mlp(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_variants(args):
+    """Convergence of the three CFR update rules built into the sweep kernel
+    (DCFR with the paper's constants and regret floor; CFR+ with R+ and
+    linearly weighted averages; vanilla CFR), on the two-round subgame of
+    seeded deal --seed: for each rule and each iteration count of a grid, a
+    whole solve (trees, iterations, values) timed end to end, then the
+    composed exploitability of its average strategies.  The roofline object
+    is the segment kernel's, measured live on the 2000-iteration CFR+ solve
+    (the generic, non-DCFR instance of the kernel)."""
+    import torch
+    import paper_2508_06559_amd as pa
+    import synth
+
+    dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
+    T = 4 if args.state == "f32" else 8
+    deck, roots = synth.two_round_root(args.seed)
+    rules = {"dcfr": pa.paper_params(),
+             "cfr_plus": pa.CfrParams(pa.CFR_PLUS, pa.RM_POSITIVE, 0.0, 0.0, 0.0, 0.0, pa.SCHED_ROOT, 0, 0),
+             "vanilla": pa.CfrParams(pa.CFR_VANILLA, pa.RM_POSITIVE, 0.0, 0.0, 0.0, 0.0, pa.SCHED_ROOT, 0, 0)}
+    grid = (5, 10, 20, 30, 50, 100, 200, 500, 1000, 2000)
+    res = {}
+    for name, p in rules.items():
+        rows = []
+        for it in grid:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = pa.SubgameSolver(deck, 4, roots, dtype=dtype)
+            s.solve(it, p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            bra, brb, _ = s.exploitability()
+            ex = float(((bra - brb) / 2).max().item())
+            s.free()
+            rows.append({"iterations": it, "seconds": dt, "exploitability": ex})
+        hit = next((r for r in rows if r["exploitability"] <= 1e-3), None)
+        res[name] = {"grid": rows, "iterations_to_1e-3": hit["iterations"] if hit else None,
+                     "seconds_to_1e-3": hit["seconds"] if hit else None}
+        log(f"[bench] {name}: to 1e-3 in {res[name]['iterations_to_1e-3']} iterations")
+    # live roofline of the generic kernel instance (CFR+, 2000 iterations)
+    s = pa.SubgameSolver(deck, 4, roots, dtype=dtype)
+    pa.profile_enable(True)
+    s.solve(2000, rules["cfr_plus"])
+    torch.cuda.synchronize()
+    kern, lev, ms, work = pa.profile_read()
+    pa.profile_enable(False)
+    s.free()
+    db = sum(launch_bytes(int(kern[i]), int(lev[i]), work[i], T) for i in range(len(kern)))
+    dt = sum(float(x) for x in ms) * 1e-3
+    dcfr = res["dcfr"]
+    out = {"metric": "seconds to exploitability 1e-3 by CFR update rule at 1 GPU",
+           "value": dcfr["seconds_to_1e-3"], "unit": "s (DCFR; other rules in config)",
+           "n_gpus": 1, "steps": len(grid) * len(rules), "warmup": 0,
+           "ms_per_step": (dcfr["seconds_to_1e-3"] or 0.0) * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"last two rounds of seeded deal {args.seed}, each CFR update rule over "
+                                  f"the iteration grid {list(grid)}; seconds include building the trees",
+                      "state": args.state, "rules": res},
+           "roofline": {"bound": "hbm", "kernel": "k_cfr_seg, generic variant instance (CFR+), "
+                                                  f"{'float' if T == 4 else 'double'} state",
+                        "achieved": db / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": db / dt / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "avg_launch_us": dt / len(kern) * 1e6, "launches": len(kern)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -796,7 +862,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game",
-                                           "paper-scale", "selfplay", "es", "infoset", "mlp", "copy"],
+                                           "paper-scale", "selfplay", "es", "infoset", "mlp", "variants", "copy"],
                     default="two-round",
                     help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
@@ -839,6 +905,8 @@ def main():
         return bench_infoset(args)
     if args.workload == "mlp":
         return bench_mlp(args)
+    if args.workload == "variants":
+        return bench_variants(args)
     if args.workload == "copy":
         # calibration for hardware byte counters: a plain device copy of a
         # known size (256 MiB read + 256 MiB written per launch, 4 launches)
