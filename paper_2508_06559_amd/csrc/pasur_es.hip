@@ -219,33 +219,10 @@ __device__ __forceinline__ int32_t rec_down(const EsSegArgs &a, int l, int p, ui
     return b;
   }
   EsRec<T> *rc = reinterpret_cast<EsRec<T> *>(a.rec[l + 1]);
-  const int kk = e - b;
   int j = 0;
-  if (kk > 1) {
-    // inverse CDF of the children's strategy, as choose() does it
-    const double u = splitmix_uniform(a.seed, base + (uint64_t)h);
-    const int uni = min((int)(u * (double)kk), kk - 1);
-    double total = 0.0;
-    for (int c = b; c < e; ++c) total += (double)rc[c].sg;
-    if (!(total > 0.0)) {
-      j = uni;
-    } else {
-      const double x = u * total;
-      double acc = 0.0;
-      int last = 0;
-      j = -1;
-      for (int c = 0; c < kk; ++c) {
-        const double pc = (double)rc[b + c].sg;
-        acc += pc;
-        if (pc > 0.0) last = c;
-        if (acc > x) {
-          j = c;
-          break;
-        }
-      }
-      if (j < 0) j = last;
-    }
-  }
+  if (e - b > 1)
+    j = choose_by(splitmix_uniform(a.seed, base + (uint64_t)h), e - b, PASUR_PLAY_SIGMA_BAR,
+                  [rc, b](int c) { return (double)rc[b + c].sg; });
   for (int c = b; c < e; ++c) rc[c].Sb = (T)((double)rc[c].Sb + (double)rc[c].sg);
   *ch = b + j;
   *k = 1;

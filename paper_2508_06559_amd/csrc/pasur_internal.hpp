@@ -85,26 +85,33 @@ __device__ inline double splitmix_uniform(uint64_t seed, uint64_t i) {
   return (double)(z >> 11) * (1.0 / 9007199254740992.0);
 }
 
-// Index of the sampled child among k (k >= 2) whose average strategy is
-// p[0..k-1]: the first whose running sum (FP64, in child order) exceeds
-// u * total; uniform choice when the policy is uniform or the total is 0.
-template <class T>
-__device__ inline int choose(double u, const T *__restrict__ p, int k, int policy) {
+// Index of the sampled child among k (k >= 2) whose strategy is prob(0..k-1)
+// (any accessor returning a child's probability): the first whose running
+// sum (FP64, in child order) exceeds u * total; uniform choice when the
+// policy is uniform or the total is 0.
+template <class Prob>
+__device__ __forceinline__ int choose_by(double u, int k, int policy, const Prob &prob) {
   const int uni = min((int)(u * (double)k), k - 1);
   if (policy == PASUR_PLAY_UNIFORM) return uni;
   double total = 0.0;
-  for (int c = 0; c < k; ++c) total += (double)p[c];
+  for (int c = 0; c < k; ++c) total += prob(c);
   if (!(total > 0.0)) return uni;
   const double x = u * total;
   double acc = 0.0;
   int last = 0;
   for (int c = 0; c < k; ++c) {
-    const double pc = (double)p[c];
+    const double pc = prob(c);
     acc += pc;
     if (pc > 0.0) last = c;
     if (acc > x) return c;
   }
   return last;
+}
+
+// choose_by over a contiguous array p[0..k-1].
+template <class T>
+__device__ inline int choose(double u, const T *__restrict__ p, int k, int policy) {
+  return choose_by(u, k, policy, [p](int c) { return (double)p[c]; });
 }
 
 
