@@ -403,14 +403,17 @@ void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStrea
 // workgroups) 16 bytes per lane and prefetched one K step ahead; the
 // activations (row-major in LDS, contiguous in K) are the B operand.  A
 // 16x16 result tile then holds four consecutive output features of one row
-// per lane, which store as one 8-byte LDS write.  Wave w owns output
-// features 64w..64w+63 for all 128 rows (4 x 8 tiles of 16x16x32).
+// per lane, which store as one 8-byte LDS write.  With W waves, wave w owns
+// output features 256/W consecutive from w*256/W for all 128 rows
+// (256/(16W) x 8 tiles of 16x16x32).
 // The last layer (256 -> 2) is a plain FP32 dot product per (row, output),
 // in feature order.
 constexpr int IM = 128;                 // rows per workgroup
+constexpr int kInferWaves = 16;         // four waves per SIMD in the one workgroup that fits a CU
 constexpr int XS = kIn + 8, HS = kHid + 8;  // LDS row strides (bf16), 16-byte aligned
 
-__global__ void __launch_bounds__(256) k_mlp_infer(int M, const __bf16 *__restrict__ X,
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *__restrict__ X,
                                                    const __bf16 *__restrict__ W1t,
                                                    const float *__restrict__ b1,
                                                    const __bf16 *__restrict__ W2t,
@@ -421,10 +424,12 @@ __global__ void __launch_bounds__(256) k_mlp_infer(int M, const __bf16 *__restri
   extern __shared__ __align__(16) unsigned char smem[];
   __bf16 *Xs = reinterpret_cast<__bf16 *>(smem);          // [IM][XS]
   __bf16 *Hs = Xs + IM * XS;                               // [IM][HS]
+  constexpr int NT = 64 * WAVES;         // threads
+  constexpr int TA = kHid / 16 / WAVES;  // 16-wide output tiles per wave
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * IM;
   // X tile -> LDS (16-byte pieces; rows past M are zero)
-  for (int e = tid; e < IM * (kIn / 8); e += 256) {
+  for (int e = tid; e < IM * (kIn / 8); e += NT) {
     const int r = e / (kIn / 8), c = (e % (kIn / 8)) * 8;
     bf16x8 v;
     if (m0 + r < M) v = *reinterpret_cast<const bf16x8 *>(X + (int64_t)(m0 + r) * kIn + c);
@@ -433,23 +438,23 @@ __global__ void __launch_bounds__(256) k_mlp_infer(int M, const __bf16 *__restri
     *reinterpret_cast<bf16x8 *>(Xs + r * XS + c) = v;
   }
   __syncthreads();
-  const int n_base = wave * 64;        // this wave's output features
+  const int n_base = wave * 16 * TA;   // this wave's output features
   const int lr = lane & 15, lk = 8 * (lane >> 4);
   auto layer = [&](const __bf16 *__restrict__ Wt, int K, const __bf16 *As, int as,
                    const float *__restrict__ bias) {
-    f32x4 acc[4][8];
+    f32x4 acc[TA][8];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < TA; ++a)
 #pragma unroll
       for (int b = 0; b < 8; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 wcur[4], wnext[4];
+    bf16x8 wcur[TA], wnext[TA];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < TA; ++a)
       wcur[a] = *reinterpret_cast<const bf16x8 *>(Wt + (int64_t)(n_base + 16 * a + lr) * K + lk);
     for (int k0 = 0; k0 < K; k0 += 32) {
       if (k0 + 32 < K) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < TA; ++a)
           wnext[a] = *reinterpret_cast<const bf16x8 *>(Wt + (int64_t)(n_base + 16 * a + lr) * K +
                                                        k0 + 32 + lk);
       }
@@ -457,15 +462,15 @@ __global__ void __launch_bounds__(256) k_mlp_infer(int M, const __bf16 *__restri
       for (int b = 0; b < 8; ++b) {
         const bf16x8 x = *reinterpret_cast<const bf16x8 *>(As + (16 * b + lr) * as + k0 + lk);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < TA; ++a)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[a], x, acc[a][b], 0, 0, 0);
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a) wcur[a] = wnext[a];
+      for (int a = 0; a < TA; ++a) wcur[a] = wnext[a];
     }
     __syncthreads();  // every wave has read As before Hs is (over)written
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < TA; ++a) {
       const int n = n_base + 16 * a + 4 * (lane >> 4);
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
@@ -483,7 +488,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(int M, const __bf16 *__restri
   layer(W2t, kHid, Hs, HS, b2);  // H2 in Hs
   // last layer: thread t -> row t / 2, output t % 2
   const int r = tid >> 1, o = tid & 1;
-  if (m0 + r < M) {
+  if (tid < 2 * IM && m0 + r < M) {
     float y = 0.f;
     for (int n = 0; n < kHid; n += 8) {
       const bf16x8 h = *reinterpret_cast<const bf16x8 *>(Hs + r * HS + n);
@@ -988,7 +993,7 @@ extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, in
     return PASUR_E_RANGE;
   }
   std::call_once(lds_once[dev], [&] {
-    lds_err[dev] = hipFuncSetAttribute((const void *)k_mlp_infer,
+    lds_err[dev] = hipFuncSetAttribute((const void *)k_mlp_infer<kInferWaves>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInferLds);
   });
   if (lds_err[dev] != hipSuccess) {
@@ -1010,7 +1015,7 @@ extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, in
     k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid,
                                                          Wt + (size_t)kIn * kHid);
   }
-  k_mlp_infer<<<(unsigned)((M + IM - 1) / IM), 256, kInferLds, s>>>(
+  k_mlp_infer<kInferWaves><<<(unsigned)((M + IM - 1) / IM), 64 * kInferWaves, kInferLds, s>>>(
       (int)M, (const __bf16 *)X, W1t, w->b1, W2t, w->b2, (const __bf16 *)w->W3, w->b3, Y);
   e = hipGetLastError();
   if (Wt) (void)hipFreeAsync(Wt, s);
