@@ -426,6 +426,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *_
   __bf16 *Hs = Xs + IM * XS;                               // [IM][HS]
   constexpr int NT = 64 * WAVES;         // threads
   constexpr int TA = kHid / 16 / WAVES;  // 16-wide output tiles per wave
+  constexpr int TB = IM / 16;            // 16-row tiles per workgroup
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * IM;
   // X tile -> LDS (16-byte pieces; rows past M are zero)
@@ -442,11 +443,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *_
   const int lr = lane & 15, lk = 8 * (lane >> 4);
   auto layer = [&](const __bf16 *__restrict__ Wt, int K, const __bf16 *As, int as,
                    const float *__restrict__ bias) {
-    f32x4 acc[TA][8];
+    f32x4 acc[TA][TB];
 #pragma unroll
     for (int a = 0; a < TA; ++a)
 #pragma unroll
-      for (int b = 0; b < 8; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int b = 0; b < TB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     bf16x8 wcur[TA], wnext[TA];
 #pragma unroll
     for (int a = 0; a < TA; ++a)
@@ -459,7 +460,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *_
                                                        k0 + 32 + lk);
       }
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int b = 0; b < TB; ++b) {
         const bf16x8 x = *reinterpret_cast<const bf16x8 *>(As + (16 * b + lr) * as + k0 + lk);
 #pragma unroll
         for (int a = 0; a < TA; ++a)
@@ -473,7 +474,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *_
     for (int a = 0; a < TA; ++a) {
       const int n = n_base + 16 * a + 4 * (lane >> 4);
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int b = 0; b < TB; ++b) {
         const int m = 16 * b + lr;
         typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
         bf16x4 h;
