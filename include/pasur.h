@@ -254,7 +254,8 @@ int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
  * finaliser of seed + (i+1)*0x9E3779B97F4A7C15) gives u = (z >> 11) / 2^53;
  * the sampled child is the first whose running FP64 sum of sigma_bar exceeds
  * u * total (uniform: floor(u * k)); forced moves draw nothing.  fgts are
- * consecutive rounds ending at the subgame's last round. */
+ * consecutive rounds ending at the subgame's last round.  n_games above
+ * 256 * (2^31 - 1), one launch, is PASUR_E_RANGE. */
 enum { PASUR_PLAY_SIGMA_BAR = 0, PASUR_PLAY_UNIFORM = 1 };
 int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds, const void *const *sigma_bar,
                    int dtype, int root, int64_t n_games, uint64_t seed, int policy_a,
@@ -320,7 +321,8 @@ int pasur_es_iterate(const pasur_fgt *fgt, const pasur_cfr_state *st, int64_t t0
  * (0 Alex, 1 Bob) of the action leading to the node.
  * format PASUR_INFOSET_INT8: d_out int8 [n][58]; PASUR_INFOSET_MLP: d_out
  * BF16 [n][192], the warm-start network's input, with row / 128 in columns
- * 0..57 and zeros after.  Asynchronous on `stream`. */
+ * 0..57 and zeros after.  n above 256 * (2^31 - 1), one launch, is
+ * PASUR_E_RANGE.  Asynchronous on `stream`. */
 enum { PASUR_INFOSET_INT8 = 0, PASUR_INFOSET_MLP = 1 };
 int pasur_infoset_rows(const pasur_gt *gt, const pasur_fgt *fgt, int level,
                        const int32_t *d_edges, int64_t n, int format, void *d_out,

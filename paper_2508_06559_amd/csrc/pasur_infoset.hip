@@ -152,6 +152,10 @@ extern "C" int pasur_infoset_rows(const pasur_gt *gt, const pasur_fgt *fgt, int 
     set_error("level %d outside 1..8", level);
     return PASUR_E_RANGE;
   }
+  if (n > (int64_t)INT32_MAX * kBlock) {
+    set_error("n %lld beyond one launch", (long long)n);
+    return PASUR_E_RANGE;
+  }
   if (format != PASUR_INFOSET_INT8 && format != PASUR_INFOSET_MLP) {
     set_error("unknown format %d", format);
     return PASUR_E_RANGE;

@@ -64,6 +64,11 @@ extern "C" int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds,
     set_error("null argument or negative game count");
     return PASUR_E_INVAL;
   }
+  if (n_games > (int64_t)INT32_MAX * 256) {
+    set_error("n_games %lld beyond one launch (%lld)", (long long)n_games,
+              (long long)INT32_MAX * 256);
+    return PASUR_E_RANGE;
+  }
   if (n_rounds < 1 || n_rounds > kMaxRounds) {
     set_error("n_rounds %d outside 1..%d", n_rounds, kMaxRounds);
     return PASUR_E_RANGE;

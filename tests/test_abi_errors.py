@@ -148,6 +148,7 @@ def test_selfplay_checks(lib):
     expect(lib, f(trees, 1, sb, 0, 0, 4, 1, 2, 0, DUMMY, None), E_RANGE, ["policy 2"])
     expect(lib, f(trees, 1, sb, 0, 0, 4, 1, 0, -1, DUMMY, None), E_RANGE, ["policy -1"])
     expect(lib, f(nulls, 2, sb, 0, 0, 4, 1, 0, 0, DUMMY, None), E_INVAL, ["fgts[0] is NULL"])
+    expect(lib, f(trees, 1, sb, 0, 0, 1 << 40, 1, 0, 0, DUMMY, None), E_RANGE, ["beyond one launch"])
 
 
 def test_es_checks(lib):
@@ -187,3 +188,4 @@ def test_infoset_checks(lib):
     expect(lib, f(DUMMY, DUMMY, 0, None, 4, 0, DUMMY, None), E_RANGE, ["level 0"])
     expect(lib, f(DUMMY, DUMMY, 9, None, 4, 0, DUMMY, None), E_RANGE, ["level 9"])
     expect(lib, f(DUMMY, DUMMY, 1, None, 4, 2, DUMMY, None), E_RANGE, ["format 2"])
+    expect(lib, f(DUMMY, DUMMY, 1, DUMMY, 1 << 40, 0, DUMMY, None), E_RANGE, ["beyond one launch"])
