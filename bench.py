@@ -365,18 +365,25 @@ def bench_warm(args):
 
     def summ(rs):
         sec = np.array([r["seconds"] for r in rs if r["seconds"] is not None])
+        sol = np.array([r["solve_seconds"] for r in rs if r["solve_seconds"] is not None])
         it = np.array([r["iters"] for r in rs if r["iters"] is not None])
         return {"median_seconds": float(np.median(sec)), "p25_seconds": float(np.percentile(sec, 25)),
                 "p75_seconds": float(np.percentile(sec, 75)), "median_iters": float(np.median(it)),
                 "mean_iters": float(np.mean(it)), "reached": int(len(sec)),
-                "fallbacks": int(sum(r["fallback"] for r in rs))}
+                "fallbacks": int(sum(r["fallback"] for r in rs)),
+                "median_solve_seconds_without_trees": float(np.median(sol))}
 
     def paired(rs):
-        # per-deal warm / plain seconds (same deal, same grid)
+        # per-deal warm / plain seconds (same deal, same grid), with and
+        # without building the trees (common to both)
         r = np.array([w["seconds"] / p["seconds"] for w, p in zip(rs, res["plain"])
                       if w["seconds"] is not None and p["seconds"] is not None])
+        q = np.array([w["solve_seconds"] / p["solve_seconds"] for w, p in zip(rs, res["plain"])
+                      if w["solve_seconds"] is not None and p["solve_seconds"] is not None])
         return {"median_ratio_warm_over_plain": float(np.median(r)),
-                "fraction_of_deals_warm_faster": float(np.mean(r < 1.0))}
+                "fraction_of_deals_warm_faster": float(np.mean(r < 1.0)),
+                "median_ratio_without_trees": float(np.median(q)),
+                "fraction_faster_without_trees": float(np.mean(q < 1.0))}
 
     sp, sw = summ(res["plain"]), summ(res["warm"])
     sw.update(paired(res["warm"]))

@@ -240,9 +240,13 @@ def solve_subgame(deck, start_round: int, roots, iters: int, dtype: int = PASUR_
                   model: Optional[WarmStartMLP] = None, warm: WarmParams = WarmParams(),
                   params=None):
     """Backward solve of a subgame, plain or warm-started; returns the solver
-    (states and round values filled)."""
+    (states and round values filled; build_seconds: building and unfolding
+    the trees)."""
     torch = _torch()
+    t_build = time.perf_counter()
     sv = SubgameSolver(deck, start_round, roots, dtype=dtype, keep_gt=model is not None)
+    torch.cuda.synchronize()
+    sv.build_seconds = time.perf_counter() - t_build
     params = params if params is not None else paper_params()
     V = None
     for rr in reversed(sv.rounds):
@@ -275,28 +279,35 @@ def seconds_to_target(deck, start_round: int, roots, target: float, grid: Sequen
                       fallback: bool = True):
     """Smallest iteration count of ``grid`` whose solve reaches exploitability
     <= target, and the wall-clock seconds of that solve (exploitability checks
-    excluded).  A warm start that misses the target on the whole grid falls
-    back to plain DCFR; its seconds then include the failed warm attempts."""
+    excluded), also without building the trees (solve_seconds: warm start,
+    iterations, values).  A warm start that misses the target on the whole
+    grid falls back to plain DCFR; its seconds then include the failed warm
+    attempts."""
     torch = _torch()
-    spent = 0.0
+    spent = spent_solve = 0.0
     for T in grid:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sv = solve_subgame(deck, start_round, roots, T, model=model, warm=warm)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        solve = el - sv.build_seconds
         ex = exploitability(sv)
         sv.free()
         if ex <= target:
-            return {"iters": T, "seconds": el, "exploitability": ex, "fallback": False}
+            return {"iters": T, "seconds": el, "solve_seconds": solve, "exploitability": ex,
+                    "fallback": False}
         if model is not None:
             spent += el
+            spent_solve += solve
     if model is not None and fallback:
         r = seconds_to_target(deck, start_round, roots, target, grid, None)
         r["seconds"] += spent
+        r["solve_seconds"] += spent_solve
         r["fallback"] = True
         return r
-    return {"iters": None, "seconds": None, "exploitability": ex, "fallback": False}
+    return {"iters": None, "seconds": None, "solve_seconds": None, "exploitability": ex,
+            "fallback": False}
 
 
 def train(model: WarmStartMLP, units: List[Unit], epochs: int, seed: int = 0, lr: float = 2e-3,
