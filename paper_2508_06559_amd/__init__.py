@@ -139,10 +139,6 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def _dptr(t) -> C.c_void_p:
-    return C.c_void_p(t.data_ptr())
-
-
 def roots_to_device(roots) -> "torch.Tensor":
     """Roots (objects with pool, ca, cb, d, bonus, or a ROOT_DTYPE array) ->
     device byte tensor laid out as pasur_root[]."""
@@ -300,8 +296,8 @@ class CfrState:
 
 
 def leaf_utilities(fgt: UnfoldedTree, d_V_next, dtype: int, d_out, stream=None):
-    vp = None if d_V_next is None else _dptr(d_V_next)
-    _check(lib().pasur_leaf_utilities(fgt.h, vp, dtype, _dptr(d_out), _stream(stream)),
+    vp = None if d_V_next is None else _p(d_V_next)
+    _check(lib().pasur_leaf_utilities(fgt.h, vp, dtype, _p(d_out), _stream(stream)),
            "pasur_leaf_utilities")
 
 
@@ -328,7 +324,7 @@ def average_strategy(st: CfrState, stream=None):
 
 def round_values(st: CfrState, value_mode: int, d_V, stream=None):
     T = st.t - 1
-    _check(lib().pasur_round_values(st.fgt.h, C.byref(st.c), value_mode, T, st.sb_ptrs, _dptr(d_V),
+    _check(lib().pasur_round_values(st.fgt.h, C.byref(st.c), value_mode, T, st.sb_ptrs, _p(d_V),
                                     _stream(stream)), "pasur_round_values")
     return d_V
 
@@ -339,7 +335,7 @@ def tree_values(fgt: UnfoldedTree, d_leaf, dtype: int, sigma: Optional[List], mo
         sp = None
     else:
         sp = (C.c_void_p * 9)(*([None] + [t.data_ptr() for t in sigma[1:]]))
-    _check(lib().pasur_tree_values(fgt.h, _dptr(d_leaf), dtype, sp, mode, _dptr(d_out),
+    _check(lib().pasur_tree_values(fgt.h, _p(d_leaf), dtype, sp, mode, _p(d_out),
                                    _stream(stream)), "pasur_tree_values")
     return d_out
 
@@ -392,6 +388,7 @@ class MlpGrads(C.Structure):
 
 
 def _p(t):
+    """Device pointer of a tensor (None stays NULL)."""
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
