@@ -244,7 +244,9 @@ def solve_subgame(deck, start_round: int, roots, iters: int, dtype: int = PASUR_
     the trees)."""
     torch = _torch()
     t_build = time.perf_counter()
-    sv = SubgameSolver(deck, start_round, roots, dtype=dtype, keep_gt=model is not None)
+    # both arms keep the game trees (the warm start needs them; freeing them
+    # inside the timed solve would charge the plain arm alone)
+    sv = SubgameSolver(deck, start_round, roots, dtype=dtype, keep_gt=True)
     torch.cuda.synchronize()
     sv.build_seconds = time.perf_counter() - t_build
     params = params if params is not None else paper_params()
