@@ -23,7 +23,7 @@ namespace {
 constexpr int kIn = 192, kHid = 256, kOut = 2;
 constexpr int kMaxDevices = 64;
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // 80-byte LDS rows keep 16-byte alignment
+constexpr int BK = 32, LDK = BK + 8;  // 80-byte LDS rows keep 16-byte alignment
 
 struct GemmArgs {
   int M, N, K;
@@ -39,84 +39,87 @@ struct GemmArgs {
   int kchunk;  // K range of one split (blockIdx.z)
 };
 
-// C = op(A) op(B) (+ bias, ReLU).  Workgroup tile 64x64, K step 32; four
-// waves each own a 32x32 quadrant as 2x2 MFMA 16x16x32 tiles.  MFMA operand
-// layout: lane l holds row (l % 16) of the A tile and column (l % 16) of the
-// B tile, K elements 8*(l/16) .. 8*(l/16)+7; the accumulator holds rows
-// 4*(l/16) .. +3 of column (l % 16).
+// One operand tile (ROWS x BK, rows = output rows of A or output columns of
+// B) from global memory into LDS T[ROWS][LDK], for op(X)(row, k) =
+// X[row * s_row + k * s_k].  A full tile whose contiguous global direction is
+// K takes 16-byte loads straight into LDS rows; one whose contiguous
+// direction is the rows takes 16-byte loads of eight rows at one k and
+// spreads them down an LDS column.  Edge tiles and unaligned operands go
+// element by element (zeros outside the matrix and the K range).
+template <int ROWS>
+__device__ __forceinline__ void load_tile(__bf16 (*T)[LDK], const __bf16 *X, int64_t s_row,
+                                          int64_t s_k, int row0, int nrows, int k0, int kend,
+                                          bool aligned, int tid) {
+  const bool full = row0 + ROWS <= nrows && k0 + BK <= kend && aligned;
+  if (full && s_k == 1 && (s_row & 7) == 0) {
+#pragma unroll
+    for (int it = 0; it < ROWS / 64; ++it) {
+      const int idx = tid + it * 256, r = idx >> 2, c = (idx & 3) * 8;
+      *reinterpret_cast<bf16x8 *>(&T[r][c]) =
+          *reinterpret_cast<const bf16x8 *>(X + (int64_t)(row0 + r) * s_row + (k0 + c));
+    }
+  } else if (full && s_row == 1 && (s_k & 7) == 0) {
+#pragma unroll
+    for (int it = 0; it < ROWS / 64; ++it) {
+      const int idx = tid + it * 256, c = idx / (ROWS / 8), r = (idx % (ROWS / 8)) * 8;
+      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(X + (int64_t)(k0 + c) * s_k + (row0 + r));
+#pragma unroll
+      for (int j = 0; j < 8; ++j) T[r + j][c] = v[j];
+    }
+  } else {
+    const __bf16 zero = (__bf16)0.f;
+    for (int e = tid; e < ROWS * BK; e += 256) {
+      int r, c;
+      if (s_k == 1) { r = e / BK; c = e % BK; } else { c = e / ROWS; r = e % ROWS; }
+      const int row = row0 + r, k = k0 + c;
+      T[r][c] = (row < nrows && k < kend) ? X[row * s_row + k * s_k] : zero;
+    }
+  }
+}
+
+// C = op(A) op(B) (+ bias, ReLU).  Workgroup tile (32 TI) x (32 TJ), K step
+// 32; four waves each own a (16 TI) x (16 TJ) quadrant as TI x TJ MFMA
+// 16x16x32 tiles.  MFMA operand layout: lane l holds row (l % 16) of the A
+// tile and column (l % 16) of the B tile, K elements 8*(l/16) .. 8*(l/16)+7;
+// the accumulator holds rows 4*(l/16) .. +3 of column (l % 16).
+template <int TI, int TJ>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  constexpr int BM = 32 * TI, BN = 32 * TJ;
   __shared__ __align__(16) __bf16 As[BM][LDK];
   __shared__ __align__(16) __bf16 Bs[BN][LDK];
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int kbeg = blockIdx.z * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const __bf16 zero = (__bf16)0.f;
+  const int wm = (wave >> 1) * 16 * TI, wn = (wave & 1) * 16 * TJ;
+  f32x4 acc[TI][TJ];
+  for (int i = 0; i < TI; ++i)
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   // 16-byte aligned operands and K-range starts (the fast tile loads need both)
   const bool a_al = ((reinterpret_cast<uintptr_t>(g.A) & 15) == 0) && (kbeg & 7) == 0;
   const bool b_al = ((reinterpret_cast<uintptr_t>(g.B) & 15) == 0) && (kbeg & 7) == 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // global -> LDS.  A full tile whose contiguous global direction is K
-    // takes one 16-byte load per thread straight into its LDS row; one whose
-    // contiguous direction is the rows (columns of B) takes a 16-byte load of
-    // eight rows at one k and spreads it down the LDS column.  Edge tiles and
-    // unaligned operands go element by element.
-    const bool full_a = m0 + BM <= g.M && k0 + BK <= kend && a_al;
-    if (full_a && g.sac == 1 && (g.sar & 7) == 0) {
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      *reinterpret_cast<bf16x8 *>(&As[r][c]) =
-          *reinterpret_cast<const bf16x8 *>(g.A + (int64_t)(m0 + r) * g.sar + (k0 + c));
-    } else if (full_a && g.sar == 1 && (g.sac & 7) == 0) {
-      const int c = tid >> 3, r = (tid & 7) * 8;
-      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(g.A + (int64_t)(k0 + c) * g.sac + (m0 + r));
-#pragma unroll
-      for (int j = 0; j < 8; ++j) As[r + j][c] = v[j];
-    } else {
-      for (int e = tid; e < BM * BK; e += 256) {
-        int r, c;
-        if (g.sac == 1) { r = e / BK; c = e % BK; } else { c = e / BM; r = e % BM; }
-        const int m = m0 + r, k = k0 + c;
-        As[r][c] = (m < g.M && k < kend) ? g.A[m * g.sar + k * g.sac] : zero;
-      }
-    }
-    const bool full_b = n0 + BN <= g.N && k0 + BK <= kend && b_al;
-    if (full_b && g.sbr == 1 && (g.sbc & 7) == 0) {
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      *reinterpret_cast<bf16x8 *>(&Bs[r][c]) =
-          *reinterpret_cast<const bf16x8 *>(g.B + (int64_t)(n0 + r) * g.sbc + (k0 + c));
-    } else if (full_b && g.sbc == 1 && (g.sbr & 7) == 0) {
-      const int c = tid >> 3, r = (tid & 7) * 8;
-      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(g.B + (int64_t)(k0 + c) * g.sbr + (n0 + r));
-#pragma unroll
-      for (int j = 0; j < 8; ++j) Bs[r + j][c] = v[j];
-    } else {
-      for (int e = tid; e < BN * BK; e += 256) {
-        int r, c;
-        if (g.sbr == 1) { r = e / BK; c = e % BK; } else { c = e / BN; r = e % BN; }
-        const int n = n0 + r, k = k0 + c;
-        Bs[r][c] = (n < g.N && k < kend) ? g.B[k * g.sbr + n * g.sbc] : zero;
-      }
-    }
+    load_tile<BM>(As, g.A, g.sar, g.sac, m0, g.M, k0, kend, a_al, tid);
+    load_tile<BN>(Bs, g.B, g.sbc, g.sbr, n0, g.N, k0, kend, b_al, tid);
     __syncthreads();
+    bf16x8 a[TI], b[TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < TI; ++i)
+      a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
-        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[wn + j * 16 + (lane & 15)][8 * (lane >> 4)]);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
-      }
-    }
+    for (int j = 0; j < TJ; ++j)
+      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
@@ -131,14 +134,23 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       }
 }
 
+// 128x128 workgroup tiles where both output dimensions reach 128, else 64x64
+// (the 2-wide layer and small problems).
+inline bool big_tiles(int M, int N) { return M >= 128 && N >= 128; }
+
 int gemm(GemmArgs g, int splits, hipStream_t s);
 
 // out[n] = sum over rows of X[m][n] (part: kColChunks * N floats of scratch)
 void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStream_t s);
 
 int gemm(GemmArgs g, int splits, hipStream_t s) {
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)splits);
-  k_gemm<<<grid, 256, 0, s>>>(g);
+  if (big_tiles(g.M, g.N)) {
+    dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), (unsigned)splits);
+    k_gemm<4, 4><<<grid, 256, 0, s>>>(g);
+  } else {
+    dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)splits);
+    k_gemm<2, 2><<<grid, 256, 0, s>>>(g);
+  }
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
 }
@@ -613,7 +625,9 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
   hipStream_t s = (hipStream_t)stream;
   const int m = (int)M;
   // workspace: dY in BF16, dH (FP32 and BF16) for both hidden layers, split-K partials
-  const int splits = m >= 8192 ? 32 : (m >= 1024 ? 8 : 1);
+  // weight gradients reduce over the M rows in chunks of at least 2048 rows,
+  // up to 128 chunks (a 256x256 gradient is 4 tiles of 128x128)
+  const int splits = std::min(128, std::max(1, m / 2048));
   const int kchunk = ((m + splits - 1) / splits + BK - 1) / BK * BK;
   __bf16 *dYb = nullptr, *G2b = nullptr, *G1b = nullptr;
   float *G2f = nullptr, *G1f = nullptr, *part = nullptr;

@@ -28,7 +28,11 @@ def from_bf16(t):
 
 @pytest.mark.parametrize("M,N,K,transA,transB", [(100, 70, 45, False, False), (64, 64, 32, False, False),
                                                   (33, 257, 160, False, True), (160, 256, 1000, True, False),
-                                                  (1, 2, 256, False, False), (515, 2, 256, False, False)])
+                                                  (1, 2, 256, False, False), (515, 2, 256, False, False),
+                                                  # 128x128 tiles: ragged, both operand orientations, long K
+                                                  (300, 200, 100, False, False), (257, 384, 64, True, True),
+                                                  (1024, 256, 192, False, False), (130, 129, 33, False, True),
+                                                  (256, 256, 2048, True, False)])
 def test_gemm_matches_fp64(M, N, K, transA, transB):
     pa = require_gpu()
     import torch
@@ -67,11 +71,13 @@ def make_problem(seed, n_par=300):
     return X, seg, tsig, tval, W
 
 
-def test_mlp_forward_backward_match_oracle():
+# about 900 rows (one K chunk per weight gradient) and about 6000 (two ragged chunks)
+@pytest.mark.parametrize("n_par", [300, 2000])
+def test_mlp_forward_backward_match_oracle(n_par):
     pa = require_gpu()
     from paper_2508_06559_amd import learn
     import torch
-    X, seg, tsig, tval, W = make_problem(3)
+    X, seg, tsig, tval, W = make_problem(3, n_par)
     M = X.shape[0]
     model = learn.WarmStartMLP(0)
     model.set_weights(W)
@@ -90,9 +96,14 @@ def test_mlp_forward_backward_match_oracle():
     torch.cuda.synchronize()
     H1o, H2o, Yo = omlp.forward(W, X, bf16=True)
     H1g, H2g = from_bf16(b["H1"][:M]), from_bf16(b["H2"][:M])
-    for Hg, Ho in ((H1g, H1o), (H2g, H2o)):
+    # each layer within one BF16 ulp of the oracle's layer on the same input:
+    # layer 2 on the GPU's own H1, since a one-ulp difference of H1 (FP32
+    # against FP64 pre-activations straddling a rounding point) carries
+    # through layer 2; against the oracle's whole forward pass, few differ
+    H2o_own = omlp.bf16_round(np.maximum(H1g @ omlp.bf16_round(W[2]) + W[3], 0.0))
+    for Hg, Ho, Hfull in ((H1g, H1o, H1o), (H2g, H2o_own, H2o)):
         assert np.all(np.abs(Hg - Ho) <= np.abs(Ho) * 2 ** -7 + 1e-6)
-        assert np.mean(Hg != Ho) < 0.01
+        assert np.mean(Hg != Hfull) < 0.01
     Yg = to_np(b["Y"][:M]).astype(np.float64)
     assert np.abs(Yg - Yo).max() <= 1e-2 * (np.abs(Yo).max() + 1)
     # loss gradient and weight gradients, both from the oracle's own activations
