@@ -15,6 +15,7 @@
 using namespace pasur;
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(uint16_t)))) uint16_t u16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
@@ -41,41 +42,84 @@ struct GemmArgs {
 
 // One operand tile (ROWS x BK, rows = output rows of A or output columns of
 // B) from global memory into LDS T[ROWS][LDK], for op(X)(row, k) =
-// X[row * s_row + k * s_k].  A full tile whose contiguous global direction is
-// K takes 16-byte loads straight into LDS rows; one whose contiguous
-// direction is the rows takes 16-byte loads of eight rows at one k and
-// spreads them down an LDS column.  Edge tiles and unaligned operands go
-// element by element (zeros outside the matrix and the K range).
+// X[row * s_row + k * s_k], in two steps so that the global loads of the next
+// K step are in flight during the MFMAs of this one: fetch() reads a full
+// tile into registers, commit() writes it to LDS.  A full tile whose
+// contiguous global direction is K goes with 16-byte loads straight into LDS
+// rows.  One whose contiguous direction is the rows takes, per thread, the
+// 16-byte runs of eight rows at two consecutive k and writes each row's pair
+// (k, k+1) as one 32-bit LDS word: lanes of one k pair and row blocks eight
+// rows apart would otherwise all meet in two LDS banks.  Edge tiles and
+// unaligned operands are read element by element in commit() (zeros outside
+// the matrix and the K range).
 template <int ROWS>
-__device__ __forceinline__ void load_tile(__bf16 (*T)[LDK], const __bf16 *X, int64_t s_row,
-                                          int64_t s_k, int row0, int nrows, int k0, int kend,
-                                          bool aligned, int tid) {
-  const bool full = row0 + ROWS <= nrows && k0 + BK <= kend && aligned;
-  if (full && s_k == 1 && (s_row & 7) == 0) {
+struct TileLoader {
+  static constexpr int N = ROWS / 64;             // 16-byte loads per thread, K contiguous
+  static constexpr int NP = (ROWS / 8) * (BK / 2);  // (row block, k pair) tasks, rows contiguous
+  static constexpr int NPT = (NP + 255) / 256;     // such tasks per thread
+  static constexpr int NV = N > 2 * NPT ? N : 2 * NPT;
+  bf16x8 v[NV];
+  int mode;  // 0: K contiguous, 1: rows contiguous, 2: element by element
+
+  __device__ __forceinline__ void fetch(const __bf16 *X, int64_t s_row, int64_t s_k, int row0,
+                                        int nrows, int k0, int kend, bool aligned, int tid) {
+    const bool full = row0 + ROWS <= nrows && k0 + BK <= kend && aligned;
+    mode = (full && s_k == 1 && (s_row & 7) == 0) ? 0 : (full && s_row == 1 && (s_k & 7) == 0) ? 1 : 2;
+    if (mode == 0) {
 #pragma unroll
-    for (int it = 0; it < ROWS / 64; ++it) {
-      const int idx = tid + it * 256, r = idx >> 2, c = (idx & 3) * 8;
-      *reinterpret_cast<bf16x8 *>(&T[r][c]) =
-          *reinterpret_cast<const bf16x8 *>(X + (int64_t)(row0 + r) * s_row + (k0 + c));
-    }
-  } else if (full && s_row == 1 && (s_k & 7) == 0) {
+      for (int it = 0; it < N; ++it) {
+        const int idx = tid + it * 256, r = idx >> 2, c = (idx & 3) * 8;
+        v[it] = *reinterpret_cast<const bf16x8 *>(X + (int64_t)(row0 + r) * s_row + (k0 + c));
+      }
+    } else if (mode == 1) {
 #pragma unroll
-    for (int it = 0; it < ROWS / 64; ++it) {
-      const int idx = tid + it * 256, c = idx / (ROWS / 8), r = (idx % (ROWS / 8)) * 8;
-      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(X + (int64_t)(k0 + c) * s_k + (row0 + r));
-#pragma unroll
-      for (int j = 0; j < 8; ++j) T[r + j][c] = v[j];
-    }
-  } else {
-    const __bf16 zero = (__bf16)0.f;
-    for (int e = tid; e < ROWS * BK; e += 256) {
-      int r, c;
-      if (s_k == 1) { r = e / BK; c = e % BK; } else { c = e / ROWS; r = e % ROWS; }
-      const int row = row0 + r, k = k0 + c;
-      T[r][c] = (row < nrows && k < kend) ? X[row * s_row + k * s_k] : zero;
+      for (int it = 0; it < NPT; ++it) {
+        const int idx = tid + it * 256;
+        if (idx < NP) {
+          const int c = 2 * (idx % (BK / 2)), r = (idx / (BK / 2)) * 8;
+          const __bf16 *p = X + (int64_t)(k0 + c) * s_k + (row0 + r);
+          v[2 * it] = *reinterpret_cast<const bf16x8 *>(p);
+          v[2 * it + 1] = *reinterpret_cast<const bf16x8 *>(p + s_k);
+        }
+      }
     }
   }
-}
+
+  __device__ __forceinline__ void commit(__bf16 (*T)[LDK], const __bf16 *X, int64_t s_row,
+                                         int64_t s_k, int row0, int nrows, int k0, int kend,
+                                         int tid) const {
+    if (mode == 0) {
+#pragma unroll
+      for (int it = 0; it < N; ++it) {
+        const int idx = tid + it * 256, r = idx >> 2, c = (idx & 3) * 8;
+        *reinterpret_cast<bf16x8 *>(&T[r][c]) = v[it];
+      }
+    } else if (mode == 1) {
+#pragma unroll
+      for (int it = 0; it < NPT; ++it) {
+        const int idx = tid + it * 256;
+        if (idx < NP) {
+          const int c = 2 * (idx % (BK / 2)), r = (idx / (BK / 2)) * 8;
+          // bit patterns of whole vectors (a bit cast of one subscripted
+          // __bf16 element yields element 0 with this compiler)
+          const u16x8 lo = __builtin_bit_cast(u16x8, v[2 * it]);
+          const u16x8 hi = __builtin_bit_cast(u16x8, v[2 * it + 1]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            *reinterpret_cast<uint32_t *>(&T[r + j][c]) = (uint32_t)lo[j] | ((uint32_t)hi[j] << 16);
+        }
+      }
+    } else {
+      const __bf16 zero = (__bf16)0.f;
+      for (int e = tid; e < ROWS * BK; e += 256) {
+        int r, c;
+        if (s_k == 1) { r = e / BK; c = e % BK; } else { c = e / ROWS; r = e % ROWS; }
+        const int row = row0 + r, k = k0 + c;
+        T[r][c] = (row < nrows && k < kend) ? X[row * s_row + k * s_k] : zero;
+      }
+    }
+  }
+};
 
 // C = op(A) op(B) (+ bias, ReLU).  Workgroup tile (32 TI) x (32 TJ), K step
 // 32; four waves each own a (16 TI) x (16 TJ) quadrant as TI x TJ MFMA
@@ -98,10 +142,20 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   // 16-byte aligned operands and K-range starts (the fast tile loads need both)
   const bool a_al = ((reinterpret_cast<uintptr_t>(g.A) & 15) == 0) && (kbeg & 7) == 0;
   const bool b_al = ((reinterpret_cast<uintptr_t>(g.B) & 15) == 0) && (kbeg & 7) == 0;
+  TileLoader<BM> la;
+  TileLoader<BN> lb;
+  if (kbeg < kend) {
+    la.fetch(g.A, g.sar, g.sac, m0, g.M, kbeg, kend, a_al, tid);
+    lb.fetch(g.B, g.sbc, g.sbr, n0, g.N, kbeg, kend, b_al, tid);
+  }
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    load_tile<BM>(As, g.A, g.sar, g.sac, m0, g.M, k0, kend, a_al, tid);
-    load_tile<BN>(Bs, g.B, g.sbc, g.sbr, n0, g.N, k0, kend, b_al, tid);
+    la.commit(As, g.A, g.sar, g.sac, m0, g.M, k0, kend, tid);
+    lb.commit(Bs, g.B, g.sbc, g.sbr, n0, g.N, k0, kend, tid);
     __syncthreads();
+    if (k0 + BK < kend) {
+      la.fetch(g.A, g.sar, g.sac, m0, g.M, k0 + BK, kend, a_al, tid);
+      lb.fetch(g.B, g.sbc, g.sbr, n0, g.N, k0 + BK, kend, b_al, tid);
+    }
     bf16x8 a[TI], b[TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i)
@@ -195,23 +249,51 @@ __global__ void k_col_sum_part(const float *__restrict__ X, int64_t M, int N, in
   part[(int64_t)blockIdx.y * N + n] = s;
 }
 
-// dH = G * (H > 0) for ReLU layers, FP32 in, BF16 out (also FP32 copy).
-// Four elements per thread (n is a multiple of 4: rows x 256 columns).
-__global__ void k_relu_back(const float *__restrict__ G, const __bf16 *__restrict__ H, int64_t n,
-                            float *__restrict__ outf, __bf16 *__restrict__ outb) {
-  const int64_t i = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= n) return;
-  const float4 g = *reinterpret_cast<const float4 *>(G + i);
-  const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H + i);
-  const float4 v = make_float4((float)h[0] > 0.f ? g.x : 0.f, (float)h[1] > 0.f ? g.y : 0.f,
-                               (float)h[2] > 0.f ? g.z : 0.f, (float)h[3] > 0.f ? g.w : 0.f);
-  *reinterpret_cast<float4 *>(outf + i) = v;
-  bf16x4 b;
-  b[0] = (__bf16)v.x;
-  b[1] = (__bf16)v.y;
-  b[2] = (__bf16)v.z;
-  b[3] = (__bf16)v.w;
-  *reinterpret_cast<bf16x4 *>(outb + i) = b;
+// Backward of a ReLU layer of kHid columns: dH = G * (H > 0) in BF16, and
+// the bias gradient's column sums of dH over row chunk blockIdx.x into
+// part[chunk][n] (k_col_merge adds the chunks).  Wave w takes rows
+// r0 + w, r0 + w + 4, ... in order; lane l columns 4l .. 4l+3 (one row per
+// wave step, 16-byte reads); the four waves' sums are added in wave order, so
+// the result is deterministic.
+__global__ void __launch_bounds__(256) k_relu_back_colsum(const float *__restrict__ G,
+                                                          const __bf16 *__restrict__ H, int64_t M,
+                                                          int64_t chunk, __bf16 *__restrict__ outb,
+                                                          float *__restrict__ part) {
+  static_assert(kHid == 256, "one wave spans a row of 4 x 64 columns");
+  __shared__ float4 red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(M, r0 + chunk);
+  float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
+  for (int64_t m = r0 + w; m < r1; m += 4) {
+    const int64_t i = m * kHid + 4 * lane;
+    const float4 g = *reinterpret_cast<const float4 *>(G + i);
+    const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H + i);
+    const float vx = (float)h[0] > 0.f ? g.x : 0.f, vy = (float)h[1] > 0.f ? g.y : 0.f;
+    const float vz = (float)h[2] > 0.f ? g.z : 0.f, vw = (float)h[3] > 0.f ? g.w : 0.f;
+    sx += vx;
+    sy += vy;
+    sz += vz;
+    sw += vw;
+    bf16x4 b;
+    b[0] = (__bf16)vx;
+    b[1] = (__bf16)vy;
+    b[2] = (__bf16)vz;
+    b[3] = (__bf16)vw;
+    *reinterpret_cast<bf16x4 *>(outb + i) = b;
+  }
+  red[w][lane] = make_float4(sx, sy, sz, sw);
+  __syncthreads();
+  if (w == 0) {
+    float4 t = red[0][lane];
+    for (int k = 1; k < 4; ++k) {
+      const float4 u = red[k][lane];
+      t.x += u.x;
+      t.y += u.y;
+      t.z += u.z;
+      t.w += u.w;
+    }
+    *reinterpret_cast<float4 *>(part + (int64_t)blockIdx.x * kHid + 4 * lane) = t;
+  }
 }
 
 __global__ void k_f32_to_bf16(const float *__restrict__ x, int64_t n, __bf16 *__restrict__ y) {
@@ -404,6 +486,15 @@ void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStrea
   const int64_t chunk = (M + kColChunks - 1) / kColChunks;
   k_col_sum_part<<<dim3((unsigned)((N + 63) / 64), kColChunks), 64, 0, s>>>(X, M, N, chunk, part);
   k_col_merge<<<(unsigned)N, 64, 0, s>>>(part, kColChunks, N, out);
+}
+
+// dH of a ReLU layer in BF16 and its bias gradient (part: kColChunks * kHid
+// floats of scratch).
+void relu_back_colsum(const float *G, const __bf16 *H, int64_t M, __bf16 *outb, float *part,
+                      float *out, hipStream_t s) {
+  const int64_t chunk = (M + kColChunks - 1) / kColChunks;
+  k_relu_back_colsum<<<kColChunks, 256, 0, s>>>(G, H, M, chunk, outb, part);
+  k_col_merge<<<kHid, 64, 0, s>>>(part, kColChunks, kHid, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -674,12 +765,10 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     st = gemm(g, 1, s);
   }
   if (!st) {
-    k_relu_back<<<blocks((int64_t)m * kHid / 4), 256, 0, s>>>(G2f, (const __bf16 *)H2, (int64_t)m * kHid,
-                                                          G2f, G2b);
+    relu_back_colsum(G2f, (const __bf16 *)H2, m, G2b, part, gr->db2, s);
     st = dW((const __bf16 *)H1, kHid, G2b, kHid, gr->dW2);
   }
   if (!st) {
-    col_sum(G2f, m, kHid, part, gr->db2, s);
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.M = m; g.N = kHid; g.K = kHid;
@@ -689,12 +778,10 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     st = gemm(g, 1, s);
   }
   if (!st) {
-    k_relu_back<<<blocks((int64_t)m * kHid / 4), 256, 0, s>>>(G1f, (const __bf16 *)H1, (int64_t)m * kHid,
-                                                          G1f, G1b);
+    relu_back_colsum(G1f, (const __bf16 *)H1, m, G1b, part, gr->db1, s);
     st = dW((const __bf16 *)X, kIn, G1b, kHid, gr->dW1);
   }
   if (!st) {
-    col_sum(G1f, m, kHid, part, gr->db1, s);
     e = hipGetLastError();
     if (e != hipSuccess) {
       set_error("MLP backward: %s", hipGetErrorString(e));
