@@ -189,7 +189,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 }
 
 // 128x128 workgroup tiles where both output dimensions reach 128, else 64x64
-// (the 2-wide layer and small problems).
+// (the 2-wide layer and small problems).  Split-K products (weight
+// gradients: a few output tiles, long K) keep 64x64 tiles, four times as
+// many workgroups in flight (measured faster: 1.48 vs 1.80 ms per training
+// step of 2^18 rows).
 inline bool big_tiles(int M, int N) { return M >= 128 && N >= 128; }
 
 int gemm(GemmArgs g, int splits, hipStream_t s);
@@ -198,7 +201,7 @@ int gemm(GemmArgs g, int splits, hipStream_t s);
 void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStream_t s);
 
 int gemm(GemmArgs g, int splits, hipStream_t s) {
-  if (big_tiles(g.M, g.N)) {
+  if (big_tiles(g.M, g.N) && splits == 1) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), (unsigned)splits);
     k_gemm<4, 4><<<grid, 256, 0, s>>>(g);
   } else {
