@@ -358,7 +358,9 @@ int pasur_gemm_bf16(int M, int N, int K, const uint16_t *A, int64_t sar, int64_t
                     const uint16_t *B, int64_t sbr, int64_t sbc, float *Cf, uint16_t *Cb,
                     int64_t ldc, const float *bias, int relu, void *stream);
 /* Forward for M rows of X [M][192] (BF16): H1, H2 [M][256] (BF16, after
- * ReLU), Y [M][2] (FP32: logit, value). */
+ * ReLU), Y [M][2] (FP32: logit, value).  With H2 16-byte aligned the output
+ * layer runs as two dot products per row, else as a GEMM (same arithmetic,
+ * FP32 accumulation in another order). */
 int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
                       uint16_t *H1, uint16_t *H2, float *Y, void *stream);
 /* Inference only: Y [M][2] (FP32) for M rows of X [M][192] (BF16), the same
@@ -370,7 +372,7 @@ int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M, fl
 /* W1t = W1^T [256][192], W2t = W2^T [256][256] (BF16, caller-owned). */
 int pasur_mlp_transpose(const pasur_mlp_weights *w, uint16_t *W1t, uint16_t *W2t, void *stream);
 /* Gradients of the loss with respect to the weights given dY [M][2] (FP32);
- * dY is rounded to BF16 for the GEMMs.  H1 and H2 must be 8-byte aligned
+ * dY is rounded to BF16 for its products (db3 sums it in FP32).  H1 and H2 must be 8-byte aligned
  * (PASUR_E_INVAL otherwise).  Uses stream-ordered scratch. */
 int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X, const uint16_t *H1,
                        const uint16_t *H2, const float *dY, int64_t M, pasur_mlp_grads *g,

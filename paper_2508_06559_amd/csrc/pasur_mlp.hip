@@ -197,9 +197,6 @@ inline bool big_tiles(int M, int N) { return M >= 128 && N >= 128; }
 
 int gemm(GemmArgs g, int splits, hipStream_t s);
 
-// out[n] = sum over rows of X[m][n] (part: kColChunks * N floats of scratch)
-void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStream_t s);
-
 int gemm(GemmArgs g, int splits, hipStream_t s) {
   if (big_tiles(g.M, g.N) && splits == 1) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), (unsigned)splits);
@@ -223,10 +220,10 @@ __global__ void k_split_sum(const float *__restrict__ part, int splits, int64_t 
   out[i] = s;
 }
 
-// Column sums of a row-major [M, N] FP32 matrix (bias gradients) in two
-// deterministic passes: block (x, y) sums rows y*chunk .. of 64 columns
-// (consecutive threads, consecutive columns) into part[y][n]; k_col_merge
-// then adds the kColChunks partials of each column.
+// Column sums over the M rows (bias gradients, the output layer's weight
+// gradient) in two deterministic passes: one workgroup per chunk of rows
+// writes its partial sums part[chunk][n]; k_col_merge then adds the
+// kColChunks partials of each column.
 constexpr int kColChunks = 1024;
 
 // Second pass of the column sums: one wave per column, lane j adds partials
@@ -242,34 +239,45 @@ __global__ void __launch_bounds__(64) k_col_merge(const float *__restrict__ part
   if (lane == 0) out[n] = s;
 }
 
-__global__ void k_col_sum_part(const float *__restrict__ X, int64_t M, int N, int64_t chunk,
-                               float *__restrict__ part) {
-  const int n = blockIdx.x * 64 + threadIdx.x;
-  if (n >= N) return;
-  const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min(M, r0 + chunk);
-  float s = 0.f;
-  for (int64_t m = r0; m < r1; ++m) s += X[m * N + n];
-  part[(int64_t)blockIdx.y * N + n] = s;
-}
-
 // Backward of a ReLU layer of kHid columns: dH = G * (H > 0) in BF16, and
 // the bias gradient's column sums of dH over row chunk blockIdx.x into
-// part[chunk][n] (k_col_merge adds the chunks).  Wave w takes rows
-// r0 + w, r0 + w + 4, ... in order; lane l columns 4l .. 4l+3 (one row per
-// wave step, 16-byte reads); the four waves' sums are added in wave order, so
-// the result is deterministic.
+// part[chunk][n] (k_col_merge adds the chunks).  G is read (FP32), or with
+// OUTER formed here as the output layer's gradient dY W3^T (dY rounded to
+// BF16, the two products added in FP32).  Wave w takes rows r0 + w,
+// r0 + w + 4, ... in order; lane l columns 4l .. 4l+3 (one row per wave
+// step); the four waves' sums are added in wave order, so the result is
+// deterministic.
+template <bool OUTER>
 __global__ void __launch_bounds__(256) k_relu_back_colsum(const float *__restrict__ G,
+                                                          const float *__restrict__ dY,
+                                                          const __bf16 *__restrict__ W3,
                                                           const __bf16 *__restrict__ H, int64_t M,
                                                           int64_t chunk, __bf16 *__restrict__ outb,
                                                           float *__restrict__ part) {
-  static_assert(kHid == 256, "one wave spans a row of 4 x 64 columns");
+  static_assert(kHid == 256 && kOut == 2, "one wave spans a row of 4 x 64 columns");
   __shared__ float4 red[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(M, r0 + chunk);
+  float w3[4][2];
+  if constexpr (OUTER) {
+    for (int j = 0; j < 4; ++j) {
+      w3[j][0] = (float)W3[(4 * lane + j) * kOut];
+      w3[j][1] = (float)W3[(4 * lane + j) * kOut + 1];
+    }
+  }
   float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
   for (int64_t m = r0 + w; m < r1; m += 4) {
     const int64_t i = m * kHid + 4 * lane;
-    const float4 g = *reinterpret_cast<const float4 *>(G + i);
+    float4 g;
+    if constexpr (OUTER) {
+      const float y0 = (float)(__bf16)dY[2 * m], y1 = (float)(__bf16)dY[2 * m + 1];
+      g.x = y0 * w3[0][0] + y1 * w3[0][1];
+      g.y = y0 * w3[1][0] + y1 * w3[1][1];
+      g.z = y0 * w3[2][0] + y1 * w3[2][1];
+      g.w = y0 * w3[3][0] + y1 * w3[3][1];
+    } else {
+      g = *reinterpret_cast<const float4 *>(G + i);
+    }
     const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H + i);
     const float vx = (float)h[0] > 0.f ? g.x : 0.f, vy = (float)h[1] > 0.f ? g.y : 0.f;
     const float vz = (float)h[2] > 0.f ? g.z : 0.f, vw = (float)h[3] > 0.f ? g.w : 0.f;
@@ -299,9 +307,95 @@ __global__ void __launch_bounds__(256) k_relu_back_colsum(const float *__restric
   }
 }
 
-__global__ void k_f32_to_bf16(const float *__restrict__ x, int64_t n, __bf16 *__restrict__ y) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (__bf16)x[i];
+// Output layer (kHid -> kOut = 2) of the forward pass: Y[m] = H2[m] W3 + b3
+// with FP32 accumulation.  Half a wave per row: lane l of the half reads
+// H2[m][8l .. 8l+7] (16 bytes) and holds W3's rows 8l .. 8l+7; the 32
+// partial sums of each output combine in a fixed shuffle tree.
+__global__ void __launch_bounds__(256) k_out_forward(const __bf16 *__restrict__ H2,
+                                                     const __bf16 *__restrict__ W3,
+                                                     const float *__restrict__ b3, int64_t M,
+                                                     float *__restrict__ Y) {
+  static_assert(kHid == 256 && kOut == 2, "32 lanes of 8 features per row");
+  const int lane = threadIdx.x & 63, half = lane >> 5, l = lane & 31;
+  float w0[8], w1[8];
+  for (int j = 0; j < 8; ++j) {
+    w0[j] = (float)W3[(8 * l + j) * kOut];
+    w1[j] = (float)W3[(8 * l + j) * kOut + 1];
+  }
+  const float c0 = b3 ? b3[0] : 0.f, c1 = b3 ? b3[1] : 0.f;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t m0 = 2 * wave; m0 < M; m0 += 2 * nwaves) {
+    const int64_t m = m0 + half;
+    float s0 = 0.f, s1 = 0.f;
+    if (m < M) {
+      const bf16x8 h = *reinterpret_cast<const bf16x8 *>(H2 + m * kHid + 8 * l);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        s0 += (float)h[j] * w0[j];
+        s1 += (float)h[j] * w1[j];
+      }
+    }
+#pragma unroll
+    for (int d = 16; d >= 1; d >>= 1) {
+      s0 += __shfl_xor(s0, d, 32);
+      s1 += __shfl_xor(s1, d, 32);
+    }
+    if (l == 0 && m < M) {
+      Y[2 * m] = s0 + c0;
+      Y[2 * m + 1] = s1 + c1;
+    }
+  }
+}
+
+// Output-layer gradients, partial sums over row chunk blockIdx.x:
+// dW3[k][o] = sum_m H2[m][k] dY[m][o] (dY rounded to BF16, as the layer's
+// other products) into part[chunk][2k + o], and db3[o] = sum_m dY[m][o]
+// (FP32) into partb[chunk][o]; k_col_merge adds the chunks.  Wave w takes rows
+// r0 + w, r0 + w + 4, ... in order, lane l the features 4l .. 4l+3; the four
+// waves' sums are added in wave order.
+__global__ void __launch_bounds__(256) k_out_backward_part(const __bf16 *__restrict__ H2,
+                                                           const float *__restrict__ dY, int64_t M,
+                                                           int64_t chunk, float *__restrict__ part,
+                                                           float *__restrict__ partb) {
+  static_assert(kHid == 256 && kOut == 2, "one wave spans a row of 4 x 64 features");
+  __shared__ float red[4][64][8];
+  __shared__ float redb[4][2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(M, r0 + chunk);
+  float acc[8];
+  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  float sb0 = 0.f, sb1 = 0.f;
+  for (int64_t m = r0 + w; m < r1; m += 4) {
+    const float y0 = dY[2 * m], y1 = dY[2 * m + 1];
+    const float q0 = (float)(__bf16)y0, q1 = (float)(__bf16)y1;
+    const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H2 + m * kHid + 4 * lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[2 * j] += (float)h[j] * q0;
+      acc[2 * j + 1] += (float)h[j] * q1;
+    }
+    sb0 += y0;
+    sb1 += y1;
+  }
+  for (int i = 0; i < 8; ++i) red[w][lane][i] = acc[i];
+  if (lane == 0) {
+    redb[w][0] = sb0;
+    redb[w][1] = sb1;
+  }
+  __syncthreads();
+  if (w == 0) {
+    for (int i = 0; i < 8; ++i) {
+      float t = red[0][lane][i];
+      for (int k = 1; k < 4; ++k) t += red[k][lane][i];
+      part[(int64_t)blockIdx.x * (kHid * kOut) + 8 * lane + i] = t;
+    }
+    if (lane < kOut) {
+      float t = redb[0][lane];
+      for (int k = 1; k < 4; ++k) t += redb[k][lane];
+      partb[(int64_t)blockIdx.x * kOut + lane] = t;
+    }
+  }
 }
 
 // Features of FGT edges (the child node's card state and score), one row of
@@ -485,18 +579,12 @@ __global__ void k_warm_init_levels(WarmLevels<T> W, const float *__restrict__ Y,
 
 inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-void col_sum(const float *X, int64_t M, int N, float *part, float *out, hipStream_t s) {
-  const int64_t chunk = (M + kColChunks - 1) / kColChunks;
-  k_col_sum_part<<<dim3((unsigned)((N + 63) / 64), kColChunks), 64, 0, s>>>(X, M, N, chunk, part);
-  k_col_merge<<<(unsigned)N, 64, 0, s>>>(part, kColChunks, N, out);
-}
-
 // dH of a ReLU layer in BF16 and its bias gradient (part: kColChunks * kHid
-// floats of scratch).
+// floats of scratch), from the FP32 gradient G.
 void relu_back_colsum(const float *G, const __bf16 *H, int64_t M, __bf16 *outb, float *part,
                       float *out, hipStream_t s) {
   const int64_t chunk = (M + kColChunks - 1) / kColChunks;
-  k_relu_back_colsum<<<kColChunks, 256, 0, s>>>(G, H, M, chunk, outb, part);
+  k_relu_back_colsum<false><<<kColChunks, 256, 0, s>>>(G, nullptr, nullptr, H, M, chunk, outb, part);
   k_col_merge<<<kHid, 64, 0, s>>>(part, kColChunks, kHid, out);
 }
 
@@ -701,7 +789,16 @@ extern "C" int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, 
   const int m = (int)M;
   PASUR_TRY(pasur_gemm_bf16(m, kHid, kIn, X, kIn, 1, w->W1, kHid, 1, nullptr, H1, kHid, w->b1, 1, s));
   PASUR_TRY(pasur_gemm_bf16(m, kHid, kHid, H1, kHid, 1, w->W2, kHid, 1, nullptr, H2, kHid, w->b2, 1, s));
-  PASUR_TRY(pasur_gemm_bf16(m, kOut, kHid, H2, kHid, 1, w->W3, kOut, 1, Y, nullptr, kOut, w->b3, 0, s));
+  if ((reinterpret_cast<uintptr_t>(H2) & 15) == 0) {
+    // the 2-wide output layer as one dot product pair per row (a 64-wide
+    // GEMM tile would be 97% padding)
+    // 8 rows per workgroup and pass, at most 2048 workgroups (grid-stride)
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, (M + 7) / 8);
+    k_out_forward<<<grid, 256, 0, s>>>((const __bf16 *)H2, (const __bf16 *)w->W3, w->b3, M, Y);
+    PASUR_TRY_HIP(hipGetLastError());
+  } else {
+    PASUR_TRY(pasur_gemm_bf16(m, kOut, kHid, H2, kHid, 1, w->W3, kOut, 1, Y, nullptr, kOut, w->b3, 0, s));
+  }
   return PASUR_OK;
 }
 
@@ -718,19 +815,19 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
   }
   hipStream_t s = (hipStream_t)stream;
   const int m = (int)M;
-  // workspace: dY in BF16, dH (FP32 and BF16) for both hidden layers, split-K partials
-  // weight gradients reduce over the M rows in chunks of at least 2048 rows,
-  // up to 128 chunks (a 256x256 gradient is 4 tiles of 128x128)
+  // workspace: dH in BF16 for both hidden layers, dH1 before the mask in
+  // FP32, split-K partials.  Weight gradients reduce over the M rows in chunks
+  // of at least 2048 rows, up to 128 chunks.
   const int splits = std::min(128, std::max(1, m / 2048));
   const int kchunk = ((m + splits - 1) / splits + BK - 1) / BK * BK;
-  __bf16 *dYb = nullptr, *G2b = nullptr, *G1b = nullptr;
-  float *G2f = nullptr, *G1f = nullptr, *part = nullptr;
-  // split-K partials of the weight gradients, or the column-sum partials of the bias gradients
-  const size_t part_n = std::max((size_t)splits * kHid * kHid, (size_t)kColChunks * kHid);
-  hipError_t e = hipMallocAsync((void **)&dYb, sizeof(__bf16) * m * kOut, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&G2b, sizeof(__bf16) * (size_t)m * kHid, s);
+  __bf16 *G2b = nullptr, *G1b = nullptr;
+  float *G1f = nullptr, *part = nullptr;
+  // split-K partials of the weight gradients, or the row-chunk partials of
+  // the bias gradients and of the output layer's weight gradient
+  const size_t part_n = std::max((size_t)splits * kHid * kHid,
+                                 (size_t)kColChunks * (kHid * kOut + kOut + kHid));
+  hipError_t e = hipMallocAsync((void **)&G2b, sizeof(__bf16) * (size_t)m * kHid, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&G1b, sizeof(__bf16) * (size_t)m * kHid, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&G2f, sizeof(float) * (size_t)m * kHid, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&G1f, sizeof(float) * (size_t)m * kHid, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&part, sizeof(float) * part_n, s);
   int st = PASUR_OK;
@@ -752,23 +849,17 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     k_split_sum<<<blocks((int64_t)kin * nout), 256, 0, s>>>(part, splits, (int64_t)kin * nout, out);
     return PASUR_OK;
   };
+  const int64_t rchunk = (M + kColChunks - 1) / kColChunks;
   if (!st) {
-    k_f32_to_bf16<<<blocks((int64_t)m * kOut), 256, 0, s>>>(dY, (int64_t)m * kOut, dYb);
-    // layer 3: dW3 = H2^T dY, db3 = colsum dY, dH2 = dY W3^T masked
-    st = dW((const __bf16 *)H2, kHid, dYb, kOut, gr->dW3);
-  }
-  if (!st) {
-    col_sum(dY, m, kOut, part, gr->db3, s);
-    GemmArgs g;
-    std::memset(&g, 0, sizeof(g));
-    g.M = m; g.N = kHid; g.K = kOut;
-    g.A = dYb; g.sar = kOut; g.sac = 1;
-    g.B = (const __bf16 *)w->W3; g.sbr = 1; g.sbc = kOut;  // W3^T(k, n) = W3[n, k]
-    g.Cf = G2f; g.ldc = kHid; g.kchunk = kOut;
-    st = gemm(g, 1, s);
-  }
-  if (!st) {
-    relu_back_colsum(G2f, (const __bf16 *)H2, m, G2b, part, gr->db2, s);
+    // layer 3: dW3 = H2^T dY, db3 = colsum dY (one pass over the rows)
+    float *part3 = part, *partb = part + (size_t)kColChunks * kHid * kOut;
+    k_out_backward_part<<<kColChunks, 256, 0, s>>>((const __bf16 *)H2, dY, M, rchunk, part3, partb);
+    k_col_merge<<<kHid * kOut, 64, 0, s>>>(part3, kColChunks, kHid * kOut, gr->dW3);
+    k_col_merge<<<kOut, 64, 0, s>>>(partb, kColChunks, kOut, gr->db3);
+    // dH2 = (dY W3^T) masked by H2 > 0, in BF16, and db2 = its column sums
+    k_relu_back_colsum<true><<<kColChunks, 256, 0, s>>>(nullptr, dY, (const __bf16 *)w->W3,
+                                                         (const __bf16 *)H2, M, rchunk, G2b, part);
+    k_col_merge<<<kHid, 64, 0, s>>>(part, kColChunks, kHid, gr->db2);
     st = dW((const __bf16 *)H1, kHid, G2b, kHid, gr->dW2);
   }
   if (!st) {
@@ -791,10 +882,8 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
       st = PASUR_E_HIP;
     }
   }
-  (void)hipFreeAsync(dYb, s);
   (void)hipFreeAsync(G2b, s);
   (void)hipFreeAsync(G1b, s);
-  (void)hipFreeAsync(G2f, s);
   (void)hipFreeAsync(G1f, s);
   (void)hipFreeAsync(part, s);
   return st;
