@@ -406,7 +406,7 @@ def bench_warm(args):
                                                 "16x16x32, FP32 accumulate), 2^20 rows",
                      "achieved": inf_tflops, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": inf_tflops / 2500.0, "traffic": None,
-                     "forward_three_gemms_TFLOPs": fwd_tflops, "training_TFLOPs": train_tflops},
+                     "forward_pass_TFLOPs": fwd_tflops, "training_TFLOPs": train_tflops},
     }
     print(json.dumps(out), flush=True)
 
@@ -727,7 +727,7 @@ def bench_mlp(args):
     feature rows (card bits set with probability 1/4, score and level
     columns as the feature layout fills them): --steps timed calls of the
     fused inference (k_mlp_infer) over 2^20 rows, and --steps training steps
-    (three-GEMM forward, loss, backward, Adam) over 2^18 rows in groups of
+    (forward: two GEMMs and the output layer; loss, backward, Adam) over 2^18 rows in groups of
     four siblings, each timed with HIP events on the launch stream."""
     import torch
     from paper_2508_06559_amd import learn

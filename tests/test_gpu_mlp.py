@@ -158,7 +158,7 @@ def test_features_encode_state_and_score():
 def test_mlp_infer_matches_oracle_and_forward(M):
     """The fused inference kernel against the oracle's BF16-rounded forward
     pass (ragged row counts around the 128-row tile) and against the
-    three-GEMM forward pass of the same weights."""
+    forward pass (two GEMMs and the output layer) of the same weights."""
     pa = require_gpu()
     from paper_2508_06559_amd import learn
     import torch
