@@ -191,3 +191,36 @@ def test_mlp_infer_matches_oracle_and_forward(M):
     # same BF16 activations as the forward pass up to FP32 accumulation order
     assert np.abs(Yi - Yf).max() <= 1e-2 * scale
     assert np.median(np.abs(Yi - Yf)) <= 1e-4 * scale
+
+
+def test_forward_output_layer_both_paths():
+    """The forward pass's output layer as per-row dot products (H2 16-byte
+    aligned) and as a GEMM (H2 8 bytes off): the same hidden activations, Y
+    equal up to FP32 accumulation order, both near the oracle."""
+    pa = require_gpu()
+    from paper_2508_06559_amd import learn
+    import torch
+    X, seg, tsig, tval, W = make_problem(5, 400)
+    M = X.shape[0]
+    model = learn.WarmStartMLP(0)
+    model.set_weights(W)
+    dX = bf16_tensor(X)
+    w = model.weights()
+    H1 = torch.empty((M, 256), dtype=torch.int16, device="cuda")
+    H2 = torch.empty((M, 256), dtype=torch.int16, device="cuda")
+    H2off = torch.empty(M * 256 + 4, dtype=torch.int16, device="cuda")[4:]
+    assert H2.data_ptr() % 16 == 0 and H2off.data_ptr() % 16 == 8
+    Ya = torch.empty((M, 2), dtype=torch.float32, device="cuda")
+    Yb = torch.empty((M, 2), dtype=torch.float32, device="cuda")
+    pa.mlp_forward(w, dX, M, H1, H2, Ya)
+    pa.mlp_forward(w, dX, M, H1, H2off, Yb)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(H2), to_np(H2off).reshape(M, 256))
+    _, _, Yo = omlp.forward(W, X, bf16=True)
+    scale = np.abs(Yo).max() + 1
+    Ya, Yb = to_np(Ya).astype(np.float64), to_np(Yb).astype(np.float64)
+    # each side within 2e-6 of the sum of |terms| of the exact result (FP32
+    # accumulation), so within twice that of each other
+    terms = np.abs(from_bf16(H2)) @ np.abs(omlp.bf16_round(W[4])) + np.abs(W[5])
+    assert np.all(np.abs(Ya - Yb) <= 4e-6 * terms + 1e-30)
+    assert np.abs(Ya - Yo).max() <= 1e-2 * scale
