@@ -216,6 +216,8 @@ __global__ void k_split_sum(const float *__restrict__ part, int splits, int64_t 
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float s = 0.f;
+  // eight loads in flight per thread; the sum still runs in split order
+#pragma unroll 8
   for (int z = 0; z < splits; ++z) s += part[(int64_t)z * n + i];
   out[i] = s;
 }
@@ -846,7 +848,8 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     g.kchunk = kchunk;
     int r = gemm(g, splits, s);
     if (r) return r;
-    k_split_sum<<<blocks((int64_t)kin * nout), 256, 0, s>>>(part, splits, (int64_t)kin * nout, out);
+    // 64-thread workgroups: a 256x256 gradient spreads over 1024 CUs' worth of workgroups
+    k_split_sum<<<blocks((int64_t)kin * nout, 64), 64, 0, s>>>(part, splits, (int64_t)kin * nout, out);
     return PASUR_OK;
   };
   const int64_t rchunk = (M + kColChunks - 1) / kColChunks;
