@@ -38,6 +38,11 @@ struct GemmArgs {
   const float *bias;  // per output column, may be null
   int relu;
   int kchunk;  // K range of one split (blockIdx.z)
+  // ReLU-backward epilogue (split-free products only): C(m, n) is kept where
+  // mask[m * ldc + n] > 0 and zeroed elsewhere, and each row tile's column
+  // sums of the kept FP32 values go to colpart[blockIdx.y * N + n]
+  const __bf16 *mask;
+  float *colpart;
 };
 
 // One operand tile (ROWS x BK, rows = output rows of A or output columns of
@@ -170,6 +175,43 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
+  if (g.mask) {
+    // ReLU backward: mask, BF16 store, and the row tile's column sums (per
+    // column: this lane's rows in (i, r) order, then the four lane groups
+    // and the two row halves of the tile in a fixed order)
+    __shared__ float csum[2][BN];
+    float cs[TJ];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) cs[j] = 0.f;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+          const int n = n0 + wn + j * 16 + (lane & 15);
+          if (m < g.M && n < g.N) {
+            const int64_t o = (int64_t)m * g.ldc + n;
+            const float v = (float)g.mask[o] > 0.f ? acc[i][j][r] : 0.f;
+            g.Cb[o] = (__bf16)v;
+            cs[j] += v;
+          }
+        }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      cs[j] += __shfl_xor(cs[j], 16);
+      cs[j] += __shfl_xor(cs[j], 32);
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) csum[wave >> 1][wn + j * 16 + lane] = cs[j];
+    }
+    __syncthreads();
+    for (int c = tid; c < BN; c += 256)
+      if (n0 + c < g.N) g.colpart[(int64_t)blockIdx.y * g.N + n0 + c] = csum[0][c] + csum[1][c];
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -194,6 +236,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 // many workgroups in flight (measured faster: 1.48 vs 1.80 ms per training
 // step of 2^18 rows).
 inline bool big_tiles(int M, int N) { return M >= 128 && N >= 128; }
+// Row tiles of a split-free product's grid (its blockIdx.y range).
+inline int row_tiles(int M, int N) { return (M + (big_tiles(M, N) ? 127 : 63)) / (big_tiles(M, N) ? 128 : 64); }
 
 int gemm(GemmArgs g, int splits, hipStream_t s);
 
@@ -241,17 +285,14 @@ __global__ void __launch_bounds__(64) k_col_merge(const float *__restrict__ part
   if (lane == 0) out[n] = s;
 }
 
-// Backward of a ReLU layer of kHid columns: dH = G * (H > 0) in BF16, and
-// the bias gradient's column sums of dH over row chunk blockIdx.x into
-// part[chunk][n] (k_col_merge adds the chunks).  G is read (FP32), or with
-// OUTER formed here as the output layer's gradient dY W3^T (dY rounded to
-// BF16, the two products added in FP32).  Wave w takes rows r0 + w,
+// Backward of the second ReLU layer: dH2 = (dY W3^T) * (H2 > 0) in BF16, the
+// output layer's gradient formed here (dY rounded to BF16, the two products
+// added in FP32), and db2's column sums of dH2 over row chunk blockIdx.x into
+// part[chunk][n] (k_col_merge adds the chunks).  Wave w takes rows r0 + w,
 // r0 + w + 4, ... in order; lane l columns 4l .. 4l+3 (one row per wave
 // step); the four waves' sums are added in wave order, so the result is
 // deterministic.
-template <bool OUTER>
-__global__ void __launch_bounds__(256) k_relu_back_colsum(const float *__restrict__ G,
-                                                          const float *__restrict__ dY,
+__global__ void __launch_bounds__(256) k_relu_back_colsum(const float *__restrict__ dY,
                                                           const __bf16 *__restrict__ W3,
                                                           const __bf16 *__restrict__ H, int64_t M,
                                                           int64_t chunk, __bf16 *__restrict__ outb,
@@ -261,25 +302,19 @@ __global__ void __launch_bounds__(256) k_relu_back_colsum(const float *__restric
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(M, r0 + chunk);
   float w3[4][2];
-  if constexpr (OUTER) {
-    for (int j = 0; j < 4; ++j) {
-      w3[j][0] = (float)W3[(4 * lane + j) * kOut];
-      w3[j][1] = (float)W3[(4 * lane + j) * kOut + 1];
-    }
+  for (int j = 0; j < 4; ++j) {
+    w3[j][0] = (float)W3[(4 * lane + j) * kOut];
+    w3[j][1] = (float)W3[(4 * lane + j) * kOut + 1];
   }
   float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
   for (int64_t m = r0 + w; m < r1; m += 4) {
     const int64_t i = m * kHid + 4 * lane;
     float4 g;
-    if constexpr (OUTER) {
-      const float y0 = (float)(__bf16)dY[2 * m], y1 = (float)(__bf16)dY[2 * m + 1];
-      g.x = y0 * w3[0][0] + y1 * w3[0][1];
-      g.y = y0 * w3[1][0] + y1 * w3[1][1];
-      g.z = y0 * w3[2][0] + y1 * w3[2][1];
-      g.w = y0 * w3[3][0] + y1 * w3[3][1];
-    } else {
-      g = *reinterpret_cast<const float4 *>(G + i);
-    }
+    const float y0 = (float)(__bf16)dY[2 * m], y1 = (float)(__bf16)dY[2 * m + 1];
+    g.x = y0 * w3[0][0] + y1 * w3[0][1];
+    g.y = y0 * w3[1][0] + y1 * w3[1][1];
+    g.z = y0 * w3[2][0] + y1 * w3[2][1];
+    g.w = y0 * w3[3][0] + y1 * w3[3][1];
     const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H + i);
     const float vx = (float)h[0] > 0.f ? g.x : 0.f, vy = (float)h[1] > 0.f ? g.y : 0.f;
     const float vz = (float)h[2] > 0.f ? g.z : 0.f, vw = (float)h[3] > 0.f ? g.w : 0.f;
@@ -581,15 +616,6 @@ __global__ void k_warm_init_levels(WarmLevels<T> W, const float *__restrict__ Y,
 
 inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-// dH of a ReLU layer in BF16 and its bias gradient (part: kColChunks * kHid
-// floats of scratch), from the FP32 gradient G.
-void relu_back_colsum(const float *G, const __bf16 *H, int64_t M, __bf16 *outb, float *part,
-                      float *out, hipStream_t s) {
-  const int64_t chunk = (M + kColChunks - 1) / kColChunks;
-  k_relu_back_colsum<false><<<kColChunks, 256, 0, s>>>(G, nullptr, nullptr, H, M, chunk, outb, part);
-  k_col_merge<<<kHid, 64, 0, s>>>(part, kColChunks, kHid, out);
-}
-
 // ---------------------------------------------------------------------------
 // Fused inference: Y = (relu(relu(X W1 + b1) W2 + b2)) W3 + b3 for a tile of
 // 128 rows per workgroup, H1 and H2 kept in LDS (rounded to BF16 as in
@@ -817,20 +843,21 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
   }
   hipStream_t s = (hipStream_t)stream;
   const int m = (int)M;
-  // workspace: dH in BF16 for both hidden layers, dH1 before the mask in
-  // FP32, split-K partials.  Weight gradients reduce over the M rows in chunks
-  // of at least 2048 rows, up to 128 chunks.
+  // workspace: dH in BF16 for both hidden layers, split-K and row-chunk
+  // partials.  Weight gradients reduce over the M rows in chunks of at least
+  // 2048 rows, up to 128 chunks.
   const int splits = std::min(128, std::max(1, m / 2048));
   const int kchunk = ((m + splits - 1) / splits + BK - 1) / BK * BK;
   __bf16 *G2b = nullptr, *G1b = nullptr;
-  float *G1f = nullptr, *part = nullptr;
+  float *part = nullptr;
   // split-K partials of the weight gradients, or the row-chunk partials of
-  // the bias gradients and of the output layer's weight gradient
-  const size_t part_n = std::max((size_t)splits * kHid * kHid,
-                                 (size_t)kColChunks * (kHid * kOut + kOut + kHid));
+  // the bias gradients and of the output layer's weight gradient, or the
+  // dH1 product's row-tile partials of db1
+  const size_t part_n = std::max({(size_t)splits * kHid * kHid,
+                                  (size_t)kColChunks * (kHid * kOut + kOut + kHid),
+                                  (size_t)row_tiles(m, kHid) * kHid});
   hipError_t e = hipMallocAsync((void **)&G2b, sizeof(__bf16) * (size_t)m * kHid, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&G1b, sizeof(__bf16) * (size_t)m * kHid, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&G1f, sizeof(float) * (size_t)m * kHid, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&part, sizeof(float) * part_n, s);
   int st = PASUR_OK;
   if (e != hipSuccess) {
@@ -860,23 +887,26 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     k_col_merge<<<kHid * kOut, 64, 0, s>>>(part3, kColChunks, kHid * kOut, gr->dW3);
     k_col_merge<<<kOut, 64, 0, s>>>(partb, kColChunks, kOut, gr->db3);
     // dH2 = (dY W3^T) masked by H2 > 0, in BF16, and db2 = its column sums
-    k_relu_back_colsum<true><<<kColChunks, 256, 0, s>>>(nullptr, dY, (const __bf16 *)w->W3,
-                                                         (const __bf16 *)H2, M, rchunk, G2b, part);
+    k_relu_back_colsum<<<kColChunks, 256, 0, s>>>(dY, (const __bf16 *)w->W3, (const __bf16 *)H2, M,
+                                                  rchunk, G2b, part);
     k_col_merge<<<kHid, 64, 0, s>>>(part, kColChunks, kHid, gr->db2);
     st = dW((const __bf16 *)H1, kHid, G2b, kHid, gr->dW2);
   }
   if (!st) {
+    // dH1 = (dH2 W2^T) masked by H1 > 0, in BF16, with db1's row-tile
+    // partial sums from the GEMM's epilogue
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.M = m; g.N = kHid; g.K = kHid;
     g.A = G2b; g.sar = kHid; g.sac = 1;
     g.B = (const __bf16 *)w->W2; g.sbr = 1; g.sbc = kHid;  // W2^T
-    g.Cf = G1f; g.ldc = kHid; g.kchunk = kHid;
+    g.Cb = G1b; g.ldc = kHid; g.kchunk = kHid;
+    g.mask = (const __bf16 *)H1; g.colpart = part;
     st = gemm(g, 1, s);
-  }
-  if (!st) {
-    relu_back_colsum(G1f, (const __bf16 *)H1, m, G1b, part, gr->db1, s);
-    st = dW((const __bf16 *)X, kIn, G1b, kHid, gr->dW1);
+    if (!st) {
+      k_col_merge<<<kHid, 64, 0, s>>>(part, row_tiles(m, kHid), kHid, gr->db1);
+      st = dW((const __bf16 *)X, kIn, G1b, kHid, gr->dW1);
+    }
   }
   if (!st) {
     e = hipGetLastError();
@@ -887,7 +917,6 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
   }
   (void)hipFreeAsync(G2b, s);
   (void)hipFreeAsync(G1b, s);
-  (void)hipFreeAsync(G1f, s);
   (void)hipFreeAsync(part, s);
   return st;
 }
