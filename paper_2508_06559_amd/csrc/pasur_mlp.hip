@@ -253,8 +253,7 @@ int gemm(GemmArgs g, int splits, hipStream_t s) {
   return PASUR_OK;
 }
 
-// out[i] = sum over splits of part[z * n + i], in split order; optional BF16
-// copy and ReLU-mask multiply (mask[i] > 0).
+// out[i] = sum over splits of part[z * n + i], in split order.
 __global__ void k_split_sum(const float *__restrict__ part, int splits, int64_t n,
                             float *__restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -875,7 +874,7 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     g.kchunk = kchunk;
     int r = gemm(g, splits, s);
     if (r) return r;
-    // 64-thread workgroups: a 256x256 gradient spreads over 1024 CUs' worth of workgroups
+    // 64-thread workgroups: 1024 of them for a 256x256 gradient, every CU busy
     k_split_sum<<<blocks((int64_t)kin * nout, 64), 64, 0, s>>>(part, splits, (int64_t)kin * nout, out);
     return PASUR_OK;
   };
