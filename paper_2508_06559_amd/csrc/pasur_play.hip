@@ -30,28 +30,55 @@ struct PlayArgs {
   int64_t n_games;
 };
 
+// Two games per thread, g and g + stride (stride = threads in the grid),
+// stepped together so that their dependent gathers overlap.  The second game
+// of a thread past the last game is played (indices stay valid) and its
+// margin dropped.
+constexpr int kGamesPerThread = 2;
+
 template <class T>
 __global__ void k_selfplay(PlayArgs a, int32_t *__restrict__ margin) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= a.n_games) return;
-  int32_t q = a.root;
-  int32_t m = 0;
+  constexpr int G = kGamesPerThread;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g0 >= a.n_games) return;
+  int64_t g[G];
+  int32_t q[G], m[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    g[i] = g0 + i * stride;
+    q[i] = a.root;
+    m[i] = 0;
+  }
   for (int r = 0; r < a.n_rounds; ++r) {
     const PlayRound &R = a.r[r];
     for (int l = 0; l < 8; ++l) {
-      const int32_t b = R.cb[l][q], e = R.cb[l][q + 1];
-      const int k = e - b;
-      int c = 0;
-      if (k > 1) {
-        const double u = splitmix_uniform(a.seed, (uint64_t)g * 64u + (uint64_t)(r * 8 + l));
-        c = choose<T>(u, reinterpret_cast<const T *>(R.sbar[l + 1]) + b, k, a.policy[l & 1]);
+      int32_t b[G], e[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        b[i] = R.cb[l][q[i]];
+        e[i] = R.cb[l][q[i] + 1];
       }
-      q = b + c;
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int k = e[i] - b[i];
+        int c = 0;
+        if (k > 1) {
+          const double u = splitmix_uniform(a.seed, (uint64_t)g[i] * 64u + (uint64_t)(r * 8 + l));
+          c = choose<T>(u, reinterpret_cast<const T *>(R.sbar[l + 1]) + b[i], k, a.policy[l & 1]);
+        }
+        q[i] = b[i] + c;
+      }
     }
-    m += R.base[q];
-    if (r + 1 < a.n_rounds) q = R.link[q];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      m[i] += R.base[q[i]];
+      if (r + 1 < a.n_rounds) q[i] = R.link[q[i]];
+    }
   }
-  margin[g] = m;
+#pragma unroll
+  for (int i = 0; i < G; ++i)
+    if (g[i] < a.n_games) margin[g[i]] = m[i];
 }
 
 }  // namespace
@@ -127,7 +154,8 @@ extern "C" int pasur_selfplay(const pasur_fgt *const *fgts, int n_rounds,
   a.seed = seed;
   a.n_games = n_games;
   hipStream_t s = (hipStream_t)stream;
-  const unsigned grid = (unsigned)((n_games + 255) / 256);
+  const int64_t threads = (n_games + kGamesPerThread - 1) / kGamesPerThread;
+  const unsigned grid = (unsigned)((threads + 255) / 256);
   if (dtype == PASUR_F32)
     k_selfplay<float><<<grid, 256, 0, s>>>(a, d_margin);
   else

@@ -29,7 +29,7 @@ def test_selfplay_matches_oracle_game_by_game():
         for l in range(1, 9):
             np.testing.assert_allclose(to_np(rr.state.sigma_bar[l]), sbars[k][l], rtol=0, atol=1e-12)
     rounds = play_rounds(orr, sbars)
-    n = 2000
+    n = 2001  # odd: a thread's second game past the end
     for seed, pa_, pb_ in ((1, pa.PLAY_SIGMA_BAR, pa.PLAY_SIGMA_BAR),
                            (2, pa.PLAY_SIGMA_BAR, pa.PLAY_UNIFORM),
                            (3, pa.PLAY_UNIFORM, pa.PLAY_SIGMA_BAR),
