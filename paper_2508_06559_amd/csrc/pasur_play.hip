@@ -30,11 +30,12 @@ struct PlayArgs {
   int64_t n_games;
 };
 
-// Two games per thread, g and g + stride (stride = threads in the grid),
-// stepped together so that their dependent gathers overlap.  The second game
-// of a thread past the last game is played (indices stay valid) and its
-// margin dropped.
-constexpr int kGamesPerThread = 2;
+// kGamesPerThread games per thread, g, g + stride, ... (stride = threads in
+// the grid), stepped together so that their dependent gathers overlap (one
+// game per thread: 19.3 ms per three matchups of 2^24 full games; two 17.7,
+// four 16.2, eight 15.5).  A thread's games past the last one are played
+// (indices stay valid) and their margins dropped.
+constexpr int kGamesPerThread = 8;
 
 template <class T>
 __global__ void k_selfplay(PlayArgs a, int32_t *__restrict__ margin) {
