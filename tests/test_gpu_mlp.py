@@ -224,3 +224,38 @@ def test_forward_output_layer_both_paths():
     terms = np.abs(from_bf16(H2)) @ np.abs(omlp.bf16_round(W[4])) + np.abs(W[5])
     assert np.all(np.abs(Ya - Yb) <= 4e-6 * terms + 1e-30)
     assert np.abs(Ya - Yo).max() <= 1e-2 * scale
+
+
+def test_mlp_backward_full_size():
+    """At the size the benchmark trains on (2^18 rows): the weight gradients
+    take 128 K chunks, db1 the 2048 row tiles of the dH1 product, db2, dW3
+    and db3 1024 full row chunks.  All six gradients against the oracle's
+    backward on the GPU's own activations."""
+    pa = require_gpu()
+    from paper_2508_06559_amd import learn
+    import torch
+    M = 1 << 18
+    rng = np.random.default_rng(18)
+    X = (rng.random((M, omlp.N_IN)) < 0.25).astype(np.float64)
+    X[:, 156:167] = rng.normal(0, 0.5, (M, 11))
+    X = omlp.bf16_round(X)
+    W = omlp.init_weights(rng)
+    W[1] = rng.normal(0, 0.1, 256)
+    W[3] = rng.normal(0, 0.1, 256)
+    W[5] = rng.normal(0, 0.1, 2)
+    W = [np.asarray(w, np.float32).astype(np.float64) for w in W]
+    model = learn.WarmStartMLP(0)
+    model.set_weights(W)
+    dX = bf16_tensor(X)
+    b = model._buffers(M)
+    w = model.weights()
+    pa.mlp_forward(w, dX, M, b["H1"], b["H2"], b["Y"])
+    dY = rng.normal(0, 1e-3, (M, 2)).astype(np.float32)
+    pa.mlp_backward(w, dX, b["H1"], b["H2"], torch.from_numpy(dY).cuda(), M, model.grads())
+    torch.cuda.synchronize()
+    print(f"[mlp] backward at {M} rows done, oracle next", flush=True)
+    H1g, H2g = from_bf16(b["H1"][:M]), from_bf16(b["H2"][:M])
+    go = omlp.backward(W, X, H1g, H2g, dY.astype(np.float64), bf16=True)
+    for k, (gg, gref) in enumerate(zip(model.g, go)):
+        gg = to_np(gg).astype(np.float64).reshape(gref.shape)
+        assert np.linalg.norm(gg - gref) <= 1e-2 * np.linalg.norm(gref) + 1e-12, k
