@@ -259,3 +259,31 @@ def test_mlp_backward_full_size():
     for k, (gg, gref) in enumerate(zip(model.g, go)):
         gg = to_np(gg).astype(np.float64).reshape(gref.shape)
         assert np.linalg.norm(gg - gref) <= 1e-2 * np.linalg.norm(gref) + 1e-12, k
+
+
+def test_mlp_infer_full_size_sampled():
+    """The fused inference at the benchmark's call size (2^20 rows, 8192
+    workgroups): 4096 sampled rows against the oracle's forward pass."""
+    pa = require_gpu()
+    from paper_2508_06559_amd import learn
+    import torch
+    M = 1 << 20
+    rng = np.random.default_rng(20)
+    X = (rng.random((M, omlp.N_IN)) < 0.25).astype(np.float32)
+    X[:, 156:167] = rng.normal(0, 0.5, (M, 11))
+    X = omlp.bf16_round(X)
+    W = omlp.init_weights(rng)
+    W[1] = rng.normal(0, 0.1, 256)
+    W[3] = rng.normal(0, 0.1, 256)
+    W[5] = rng.normal(0, 0.1, 2)
+    W = [np.asarray(w, np.float32).astype(np.float64) for w in W]
+    model = learn.WarmStartMLP(0)
+    model.set_weights(W)
+    Y = torch.empty((M, 2), dtype=torch.float32, device="cuda")
+    pa.mlp_infer(model.infer_weights(), bf16_tensor(X), M, Y)
+    torch.cuda.synchronize()
+    idx = np.sort(rng.choice(M, 4096, replace=False))
+    idx[-1] = M - 1  # the last row of the last tile
+    _, _, Yo = omlp.forward(W, X[idx].astype(np.float64), bf16=True)
+    Yi = to_np(Y)[idx].astype(np.float64)
+    assert np.abs(Yi - Yo).max() <= 1e-2 * (np.abs(Yo).max() + 1)
