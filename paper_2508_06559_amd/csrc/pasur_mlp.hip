@@ -175,6 +175,38 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
+  if (g.Cb && !g.Cf && gridDim.z == 1 && m0 + BM <= g.M && n0 + BN <= g.N && (g.ldc & 7) == 0 &&
+      (reinterpret_cast<uintptr_t>(g.Cb) & 15) == 0 && !g.mask) {
+    // Full BF16 tile: each wave stages half of its quadrant at a time in LDS
+    // (the operand tiles are no longer read) and writes it as 16-byte row
+    // pieces, eight lanes per 128-byte run, instead of 2-byte stores.
+    constexpr int RH = 8 * TI, CW = 16 * TJ, SS = CW + 8;  // rows per half, columns, stride
+    static_assert(2 * RH * SS <= BM * LDK, "two waves' halves fit one operand tile");
+    __bf16 *S = (wave < 2 ? &As[0][0] : &Bs[0][0]) + (wave & 1) * RH * SS;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int ii = 0; ii < TI / 2; ++ii)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = ii * 16 + 4 * (lane >> 4) + r, col = j * 16 + (lane & 15);
+            float v = acc[h * (TI / 2) + ii][j][r];
+            if (g.bias) v += g.bias[n0 + wn + col];
+            if (g.relu) v = fmaxf(v, 0.f);
+            S[row * SS + col] = (__bf16)v;
+          }
+      __syncthreads();
+      for (int c = lane; c < RH * CW / 8; c += 64) {
+        const int row = c / (CW / 8), col = (c % (CW / 8)) * 8;
+        *reinterpret_cast<bf16x8 *>(g.Cb + (int64_t)(m0 + wm + h * RH + row) * g.ldc + n0 + wn + col) =
+            *reinterpret_cast<const bf16x8 *>(S + row * SS + col);
+      }
+      __syncthreads();
+    }
+    return;
+  }
   if (g.mask) {
     // ReLU backward: mask, BF16 store, and the row tile's column sums (per
     // column: this lane's rows in (i, r) order, then the four lane groups
