@@ -131,7 +131,9 @@ struct TileLoader {
 // 16x16x32 tiles.  MFMA operand layout: lane l holds row (l % 16) of the A
 // tile and column (l % 16) of the B tile, K elements 8*(l/16) .. 8*(l/16)+7;
 // the accumulator holds rows 4*(l/16) .. +3 of column (l % 16).
-template <int TI, int TJ>
+// MASK selects the ReLU-backward epilogue at compile time (g.mask set), so
+// the plain products do not carry its registers.
+template <int TI, int TJ, bool MASK>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   constexpr int BM = 32 * TI, BN = 32 * TJ;
   __shared__ __align__(16) __bf16 As[BM][LDK];
@@ -175,8 +177,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
-  if (g.Cb && !g.Cf && gridDim.z == 1 && m0 + BM <= g.M && n0 + BN <= g.N && (g.ldc & 7) == 0 &&
-      (reinterpret_cast<uintptr_t>(g.Cb) & 15) == 0 && !g.mask) {
+  if (!MASK && g.Cb && !g.Cf && gridDim.z == 1 && m0 + BM <= g.M && n0 + BN <= g.N &&
+      (g.ldc & 7) == 0 && (reinterpret_cast<uintptr_t>(g.Cb) & 15) == 0) {
     // Full BF16 tile: each wave stages half of its quadrant at a time in LDS
     // (the operand tiles are no longer read) and writes it as 16-byte row
     // pieces, eight lanes per 128-byte run, instead of 2-byte stores.
@@ -207,7 +209,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
     return;
   }
-  if (g.mask) {
+  if constexpr (MASK) {
     // ReLU backward: mask, BF16 store, and the row tile's column sums (per
     // column: this lane's rows in (i, r) order, then the four lane groups
     // and the two row halves of the tile in a fixed order)
@@ -215,21 +217,58 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     float cs[TJ];
 #pragma unroll
     for (int j = 0; j < TJ; ++j) cs[j] = 0.f;
+    if (m0 + BM <= g.M && n0 + BN <= g.N && (g.ldc & 7) == 0 &&
+        ((reinterpret_cast<uintptr_t>(g.Cb) | reinterpret_cast<uintptr_t>(g.mask)) & 15) == 0) {
+      // full tile: each wave brings half of its quadrant's mask into LDS with
+      // 16-byte loads, masks its accumulators there in place (each lane its
+      // own elements) and writes the half out as 16-byte row pieces
+      constexpr int RH = 8 * TI, CW = 16 * TJ, SS = CW + 8;
+      __bf16 *S = (wave < 2 ? &As[0][0] : &Bs[0][0]) + (wave & 1) * RH * SS;
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
-#pragma unroll
-      for (int j = 0; j < TJ; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-          const int n = n0 + wn + j * 16 + (lane & 15);
-          if (m < g.M && n < g.N) {
-            const int64_t o = (int64_t)m * g.ldc + n;
-            const float v = (float)g.mask[o] > 0.f ? acc[i][j][r] : 0.f;
-            g.Cb[o] = (__bf16)v;
-            cs[j] += v;
-          }
+      for (int h = 0; h < 2; ++h) {
+        const int64_t base = (int64_t)(m0 + wm + h * RH) * g.ldc + n0 + wn;
+        for (int c = lane; c < RH * CW / 8; c += 64) {
+          const int row = c / (CW / 8), col = (c % (CW / 8)) * 8;
+          *reinterpret_cast<bf16x8 *>(S + row * SS + col) =
+              *reinterpret_cast<const bf16x8 *>(g.mask + base + (int64_t)row * g.ldc + col);
         }
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < TI / 2; ++ii)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = ii * 16 + 4 * (lane >> 4) + r, col = j * 16 + (lane & 15);
+              const float v = (float)S[row * SS + col] > 0.f ? acc[h * (TI / 2) + ii][j][r] : 0.f;
+              S[row * SS + col] = (__bf16)v;
+              cs[j] += v;
+            }
+        __syncthreads();
+        for (int c = lane; c < RH * CW / 8; c += 64) {
+          const int row = c / (CW / 8), col = (c % (CW / 8)) * 8;
+          *reinterpret_cast<bf16x8 *>(g.Cb + base + (int64_t)row * g.ldc + col) =
+              *reinterpret_cast<const bf16x8 *>(S + row * SS + col);
+        }
+        __syncthreads();
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+            const int n = n0 + wn + j * 16 + (lane & 15);
+            if (m < g.M && n < g.N) {
+              const int64_t o = (int64_t)m * g.ldc + n;
+              const float v = (float)g.mask[o] > 0.f ? acc[i][j][r] : 0.f;
+              g.Cb[o] = (__bf16)v;
+              cs[j] += v;
+            }
+          }
+    }
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
       cs[j] += __shfl_xor(cs[j], 16);
@@ -276,10 +315,16 @@ int gemm(GemmArgs g, int splits, hipStream_t s);
 int gemm(GemmArgs g, int splits, hipStream_t s) {
   if (big_tiles(g.M, g.N) && splits == 1) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), (unsigned)splits);
-    k_gemm<4, 4><<<grid, 256, 0, s>>>(g);
+    if (g.mask)
+      k_gemm<4, 4, true><<<grid, 256, 0, s>>>(g);
+    else
+      k_gemm<4, 4, false><<<grid, 256, 0, s>>>(g);
   } else {
     dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)splits);
-    k_gemm<2, 2><<<grid, 256, 0, s>>>(g);
+    if (g.mask)
+      k_gemm<2, 2, true><<<grid, 256, 0, s>>>(g);
+    else
+      k_gemm<2, 2, false><<<grid, 256, 0, s>>>(g);
   }
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
