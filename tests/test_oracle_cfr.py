@@ -59,6 +59,86 @@ def test_dcfr_three_iterations_by_hand():
     np.testing.assert_allclose(c.get(oracle.CF_U, 1), [-1.0, 0.0], atol=1e-14)
 
 
+def test_vanilla_cfr_three_iterations_by_hand():
+    # Same game; vanilla CFR (section "CFR": R <- R + r, no discount, uniform
+    # average weights), textbook regret matching.  Reaches: level-1 nodes
+    # have pi_A = sigma(root), pi_B = 1; Bob's regret is -pi_A (u(q) - u(h)).
+    #   t=1: sigma uniform; u(a1)=u(a2)=u=1; r(a1:b)=(-1,1), r(a2:b)=(1/2,-1/2),
+    #        r(root)=(0,0); Sbar(root)=(1/2,1/2), Sbar(a1:b)=Sbar(a2:b)=(1/2,1/2)
+    #   t=2: sigma(a1:b)=(0,1), sigma(a2:b)=(1,0), sigma(root)=(1/2,1/2);
+    #        u(a1)=-1, u(a2)=0, u=-1/2; r(a1:b)=(-2,0), r(a2:b)=(0,-1),
+    #        r(root)=(-1/2,1/2); R(a1:b)=(-3,1), R(a2:b)=(1/2,-3/2),
+    #        R(root)=(-1/2,1/2); Sbar(root)=(1,1), Sbar(a1:b)=(1/2,3/2),
+    #        Sbar(a2:b)=(3/2,1/2)
+    #   t=3: sigma(root)=(0,1) (pi_A(a1)=0, so Bob's regrets at a1 stay);
+    #        u(a1)=-1, u(a2)=0, u=0; r(a2:b)=(0,-2), r(root)=(-1,0);
+    #        R(a1:b)=(-3,1), R(a2:b)=(1/2,-7/2), R(root)=(-3/2,1/2);
+    #        Sbar(root)=(1,2), Sbar(a1:b)=(1/2,5/2), Sbar(a2:b)=(5/2,1/2);
+    #        average (1/3,2/3), (1/6,5/6), (5/6,1/6); vacc = 1 - 1/2 + 0.
+    n, cb, leaves = padded_tree([2, 2], [3, -1, 0, 2])
+    c = oracle.CFR(n, cb, leaves)
+    c.run(3, oracle.Params(variant=oracle.CFR_VANILLA, rm_mode=oracle.RM_POSITIVE))
+    np.testing.assert_allclose(c.get(oracle.CF_R, 1), [-1.5, 0.5], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_R, 2), [-3, 1, 0.5, -3.5], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SBAR, 1), [1, 2], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SBAR, 2), [0.5, 2.5, 2.5, 0.5], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA_BAR, 1), [1 / 3, 2 / 3], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA_BAR, 2), [1 / 6, 5 / 6, 5 / 6, 1 / 6],
+                               atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA, 1), [0, 1], atol=0)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA, 2), [0, 1, 1, 0], atol=0)
+    np.testing.assert_allclose(c.get(oracle.CF_VACC), [0.5], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_U, 1), [-1.0, 0.0], atol=1e-14)
+    # forced edges keep zero regret and probability one
+    for l in range(3, 9):
+        np.testing.assert_allclose(c.get(oracle.CF_R, l), np.zeros(4), atol=0)
+        np.testing.assert_allclose(c.get(oracle.CF_SIGMA, l), np.ones(4), atol=0)
+
+
+def test_cfr_plus_three_iterations_by_hand():
+    # Same game; CFR+ (section "CFR", the CFR+ rule: R <- max(R + r, 0)) with
+    # the linearly weighted average of Tammelin's CFR+ (iteration t adds
+    # t * pi_p * sigma^t), textbook regret matching.  Instantaneous regrets
+    # are those of the vanilla run until the profiles differ (they do not here):
+    #   t=1: R(a1:b)=(0,1), R(a2:b)=(1/2,0), R(root)=(0,0); Sbar as vanilla
+    #   t=2: same sigma^2; R(a1:b)=(0,1), R(a2:b)=(1/2,0), R(root)=(0,1/2);
+    #        Sbar(root)=(1/2+1, 1/2+1), Sbar(a1:b)=(1/2, 1/2+2), Sbar(a2:b)=(1/2+2, 1/2)
+    #   t=3: sigma(root)=(0,1); R(a2:b)=(1/2, max(0-2,0)), R(root)=(max(0-1,0), 1/2);
+    #        Sbar(root)=(3/2, 3/2+3), Sbar(a1:b)=(1/2, 5/2+3), Sbar(a2:b)=(5/2+3, 1/2);
+    #        average (1/4,3/4), (1/12,11/12), (11/12,1/12)
+    n, cb, leaves = padded_tree([2, 2], [3, -1, 0, 2])
+    c = oracle.CFR(n, cb, leaves)
+    c.run(3, oracle.Params(variant=oracle.CFR_PLUS, rm_mode=oracle.RM_POSITIVE))
+    np.testing.assert_allclose(c.get(oracle.CF_R, 1), [0, 0.5], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_R, 2), [0, 1, 0.5, 0], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SBAR, 1), [1.5, 4.5], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SBAR, 2), [0.5, 5.5, 5.5, 0.5], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA_BAR, 1), [0.25, 0.75], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA_BAR, 2), [1 / 12, 11 / 12, 11 / 12, 1 / 12],
+                               atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA, 1), [0, 1], atol=0)
+    np.testing.assert_allclose(c.get(oracle.CF_VACC), [0.5], atol=1e-14)
+    # clipped regrets are never negative
+    for l in range(1, 9):
+        assert (c.get(oracle.CF_R, l) >= 0).all()
+
+
+def test_cfr_plus_and_vanilla_split_runs_continue_the_count():
+    # t0 carries the iteration number: 3 iterations as 1 + 2 equal 3 at once
+    # (the linear weight of CFR+ and the counters of both rules depend on t).
+    n, cb, leaves = padded_tree([2, 2], [3, -1, 0, 2])
+    for variant in (oracle.CFR_PLUS, oracle.CFR_VANILLA):
+        p = oracle.Params(variant=variant, rm_mode=oracle.RM_POSITIVE)
+        a = oracle.CFR(n, cb, leaves)
+        a.run(3, p)
+        b = oracle.CFR(n, cb, leaves)
+        b.run(1, p)
+        b.run(2, p)  # continues at t = 2
+        for l in (1, 2):
+            np.testing.assert_array_equal(a.get(oracle.CF_SBAR, l), b.get(oracle.CF_SBAR, l))
+            np.testing.assert_array_equal(a.get(oracle.CF_R, l), b.get(oracle.CF_R, l))
+
+
 def test_floor_rule_matches_textbook_when_regrets_are_large():
     # The executed rule max(R, 1e-8)/sum differs from the positive-part rule
     # only by terms of order 1e-8.
