@@ -161,14 +161,27 @@ typedef struct {
 
 typedef enum { PASUR_DCFR = 0, PASUR_CFR_PLUS = 1, PASUR_CFR_VANILLA = 2 } pasur_variant;
 typedef enum { PASUR_RM_FLOOR = 0, PASUR_RM_POSITIVE = 1 } pasur_rm_mode;
-/* Kernel schedule of pasur_cfr_iterate (same results bit for bit):
- * ROOT (default): one persistent workgroup per segment (a run of
- *   consecutive roots, see seg_nodes) runs all iterations on that segment's
- *   subtrees, its state held in LDS when it fits (else in global memory);
+/* Kernel schedule of pasur_cfr_iterate (same results bit for bit, except
+ * as noted for STREAM):
+ * ROOT: one persistent workgroup per segment (a run of consecutive roots,
+ *   see seg_nodes) runs all iterations on that segment's subtrees, its state
+ *   held in LDS when it fits (else in global memory);
  * LEVEL_SYNC: one launch per level and sweep direction;
- * ROOT_GLOBAL: the persistent schedule with state always in global memory. */
+ * ROOT_GLOBAL: the persistent schedule with state always in global memory;
+ * STREAM: one coalesced launch per level and sweep direction that streams
+ *   the level through HBM, without a strategy array inside the call (sigma is
+ *   recomputed from R and the parent's regret-matching sum) and without
+ *   iterating chains of single-child nodes (their edges are forced).  Every
+ *   state array ends as with the other schedules except Sbar of the edges
+ *   below a node whose whole subtree is such a chain: those sums are not
+ *   accumulated (their average strategy is 1 regardless).  The sigma array
+ *   is read on a call's first iteration and written after its last; single-
+ *   child edges must hold sigma = 1 (as pasur_cfr_init and the warm start
+ *   leave them);
+ * AUTO: STREAM for rounds of at least 4e7 nodes, else ROOT. */
 typedef enum { PASUR_SCHED_ROOT = 0, PASUR_SCHED_LEVEL_SYNC = 1,
-               PASUR_SCHED_ROOT_GLOBAL = 2 } pasur_schedule;
+               PASUR_SCHED_ROOT_GLOBAL = 2, PASUR_SCHED_STREAM = 3,
+               PASUR_SCHED_AUTO = 4 } pasur_schedule;
 typedef struct {
   int variant;  /* pasur_variant */
   int rm_mode;  /* PASUR_RM_FLOOR: max(R, eps)/sum (the paper's executed rule);

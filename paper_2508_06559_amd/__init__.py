@@ -33,7 +33,7 @@ class PasurError(RuntimeError):
     pass
 
 
-SCHED_ROOT, SCHED_LEVEL_SYNC, SCHED_ROOT_GLOBAL = 0, 1, 2
+SCHED_ROOT, SCHED_LEVEL_SYNC, SCHED_ROOT_GLOBAL, SCHED_STREAM, SCHED_AUTO = 0, 1, 2, 3, 4
 
 
 class CfrParams(C.Structure):
@@ -42,9 +42,10 @@ class CfrParams(C.Structure):
                 ("schedule", C.c_int), ("block", C.c_int), ("seg_nodes", C.c_int)]
 
 
-def paper_params(schedule: int = SCHED_ROOT, block: int = 0, seg_nodes: int = 0) -> CfrParams:
+def paper_params(schedule: int = SCHED_AUTO, block: int = 0, seg_nodes: int = 0) -> CfrParams:
     """DCFR with the paper's constants (alpha 1.5, beta 0, gamma 2) and its
-    regret-matching floor (1e-8)."""
+    regret-matching floor (1e-8); by default the library picks the schedule
+    per round (persistent segments, or streaming sweeps for large rounds)."""
     return CfrParams(DCFR, RM_FLOOR, 1.5, 0.0, 2.0, 1e-8, schedule, block, seg_nodes)
 
 

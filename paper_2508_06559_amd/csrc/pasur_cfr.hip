@@ -23,11 +23,6 @@ namespace {
 
 // Optional per-launch timing of the sweep kernels (HIP events on the launch
 // stream), off unless pasur_profile_enable(1) was called.
-struct ProfRec {
-  int kernel, level;
-  int64_t work[5];  // edges, internal nodes, roots, level-7 nodes, iterations
-  hipEvent_t a, b;
-};
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof;
 bool g_prof_on = false;
@@ -39,33 +34,6 @@ void prof_clear() {
   }
   g_prof.clear();
 }
-
-struct ProfScope {
-  ProfRec rec;
-  hipStream_t s;
-  bool on;
-  ProfScope(int kernel, int level, hipStream_t stream, int64_t edges = 0, int64_t internal = 0,
-            int64_t roots = 0, int64_t n7 = 0, int64_t iters = 1)
-      : s(stream), on(g_prof_on) {
-    if (!on) return;
-    rec.kernel = kernel;
-    rec.level = level;
-    rec.work[0] = edges;
-    rec.work[1] = internal;
-    rec.work[2] = roots;
-    rec.work[3] = n7;
-    rec.work[4] = iters;
-    (void)hipEventCreate(&rec.a);
-    (void)hipEventCreate(&rec.b);
-    (void)hipEventRecord(rec.a, s);
-  }
-  ~ProfScope() {
-    if (!on) return;
-    (void)hipEventRecord(rec.b, s);
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    g_prof.push_back(rec);
-  }
-};
 
 constexpr int kThreads = 256;
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -109,14 +77,6 @@ __global__ void k_down(int64_t n, int mover, const int32_t *__restrict__ parent,
   ra[q] = (T)a;
   rb[q] = (T)b;
 }
-
-struct IterConsts {
-  double dpos, dneg;  // DCFR discounts for R > 0 and R <= 0
-  double avg_w;       // weight of the previous average-strategy sum
-  double avg_t;       // multiplier of the new term (t for CFR+, else 1)
-  double eps;
-  int variant, rm_mode;
-};
 
 // FindUtility, one level, one thread per parent h (children cb[h]..cb[h+1]):
 //   u(h) = sum sigma^t u;  r = s_p pi_{-p}(h) (u(q) - u(h));
@@ -182,10 +142,6 @@ __global__ void k_up(int64_t np, int mover, const int32_t *__restrict__ cb,
 // results are bit-identical to the level-synchronous kernels.  A launch can
 // cover the trees of many deals (batched solve).
 // ---------------------------------------------------------------------------
-
-struct IterK {
-  double dpos, dneg, avg_w, avg_t;
-};
 
 // One (tree, state) pair of a launch.
 template <class T>
@@ -406,52 +362,6 @@ __device__ __forceinline__ void up_one(const SubT &S, const IterK &k, int varian
 // Largest sibling group the chunked up sweep handles (chunks of at most 64
 // children then start at least every 32 children).
 constexpr int kMaxChunkGroup = 33;
-
-// The value of lane i-1 (lane_from_below) or lane i+1 (lane_from_above) of
-// the wave, by a DPP whole-wave shift; lane 0 (resp. 63) receives 0.
-__device__ __forceinline__ double lane_from_below(double v) {
-  const long long x = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x138, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double lane_from_above(double v) {
-  const long long x = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x130, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum of v over each sibling group of the wave (the group's lanes are
-// consecutive; pos = index within the group, k = group size), added in
-// sibling order from 0.0 exactly as the sequential loop does, and returned
-// on every lane of the group.  Each step moves values one lane; the steps
-// stop once no lane of the wave needs another (kw = largest group of the
-// wave).  Must run with all lanes of the wave active.
-__device__ __forceinline__ double group_sum(double v, int pos, int k, int kw) {
-  double acc = 0.0 + v;
-  for (int s = 1; s < kw; ++s) {
-    const double prev = lane_from_below(acc);
-    acc = pos == s ? prev + v : acc;
-  }
-  for (int s = 1; s < kw; ++s) {
-    const double next = lane_from_above(acc);
-    acc = k - 1 - pos == s ? next : acc;
-  }
-  return acc;
-}
-
-// Largest value of x over the wave (x >= 0), as a wave-uniform scalar.
-__device__ __forceinline__ int wave_max(int x) {
-  int m = x;
-  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x111, 0xF, 0xF, false));  // row_shr:1
-  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x112, 0xF, 0xF, false));  // row_shr:2
-  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x114, 0xF, 0xF, false));  // row_shr:4
-  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x118, 0xF, 0xF, false));  // row_shr:8
-  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x142, 0xF, 0xF, false));  // row_bcast:15
-  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x143, 0xF, 0xF, false));  // row_bcast:31
-  return __builtin_amdgcn_readlane(m, 63);
-}
 
 // FindUtility on level L, one lane per child: wave w takes chunks w, w+nw,
 // ... of the level's children (a chunk never splits a sibling group); the
@@ -882,21 +792,6 @@ int init_t(const pasur_fgt *f, const pasur_cfr_state *st, hipStream_t s) {
   return PASUR_OK;
 }
 
-IterConsts consts_for(const pasur_cfr_params *p, int64_t t) {
-  IterConsts ic;
-  const double tm1 = (double)(t - 1);
-  double pa = std::pow(tm1, p->alpha);
-  double pb = std::pow(tm1, p->beta);
-  ic.dpos = pa / (pa + 1.0);
-  ic.dneg = pb / (pb + 1.0);
-  ic.avg_w = p->variant == PASUR_DCFR ? std::pow(tm1 / (double)t, p->gamma) : 1.0;
-  ic.avg_t = (double)t;
-  ic.eps = p->eps;
-  ic.variant = p->variant;
-  ic.rm_mode = p->rm_mode;
-  return ic;
-}
-
 template <class T>
 int iterate_t(const pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p,
               int64_t t0, int n_iters, hipStream_t s) {
@@ -938,6 +833,14 @@ void *seg_kernel(bool paper) {
 }
 
 }  // namespace
+
+namespace pasur {
+bool prof_on() { return g_prof_on; }
+void prof_push(const ProfRec &r) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof.push_back(r);
+}
+}  // namespace pasur
 
 struct pasur_plan {
   int dtype, block, variant, rm_mode;
@@ -1101,12 +1004,12 @@ extern "C" int pasur_plan_create(const pasur_fgt *const *fgts,
     return PASUR_E_RANGE;
   }
   if (p->variant < 0 || p->variant > 2 || p->rm_mode < 0 || p->rm_mode > 1 ||
-      p->schedule < 0 || p->schedule > 2 || p->seg_nodes < 0 ||
+      p->schedule < 0 || p->schedule > PASUR_SCHED_AUTO || p->seg_nodes < 0 ||
       (p->block != 0 && p->block != 256 && p->block != 512 && p->block != 1024)) {
     set_error("unknown variant, regret-matching mode, schedule, block or segment size");
     return PASUR_E_RANGE;
   }
-  if (p->schedule == PASUR_SCHED_LEVEL_SYNC) {
+  if (p->schedule == PASUR_SCHED_LEVEL_SYNC || p->schedule == PASUR_SCHED_STREAM) {
     set_error("plans use the persistent segment schedule");
     return PASUR_E_RANGE;
   }
@@ -1247,12 +1150,15 @@ extern "C" int pasur_cfr_iterate(const pasur_fgt *f, const pasur_cfr_state *st,
     set_error("unknown variant or regret-matching mode");
     return PASUR_E_RANGE;
   }
-  if (p->schedule < 0 || p->schedule > 2 || (p->block != 0 && p->block != 256 &&
-                                               p->block != 512 && p->block != 1024)) {
+  if (p->schedule < 0 || p->schedule > PASUR_SCHED_AUTO ||
+      (p->block != 0 && p->block != 256 && p->block != 512 && p->block != 1024)) {
     set_error("unknown schedule or block size");
     return PASUR_E_RANGE;
   }
   hipStream_t s = (hipStream_t)stream;
+  if (p->schedule == PASUR_SCHED_STREAM ||
+      (p->schedule == PASUR_SCHED_AUTO && sweep_pays(f)))
+    return sweep_iterate(const_cast<pasur_fgt *>(f), st, p, t0, n_iters, s);
   if (p->schedule == PASUR_SCHED_LEVEL_SYNC)
     return st->dtype == PASUR_F32 ? iterate_t<float>(f, st, p, t0, n_iters, s)
                                   : iterate_t<double>(f, st, p, t0, n_iters, s);

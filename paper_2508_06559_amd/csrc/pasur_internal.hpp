@@ -6,6 +6,7 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <cmath>
 #include <cstdio>
 
 #include "../../include/pasur.h"
@@ -115,6 +116,135 @@ __device__ inline int choose(double u, const T *__restrict__ p, int k, int polic
 }
 
 
+// ---- DCFR iteration constants (computed on the host so that FP64 results
+// stay bit-exact) --------------------------------------------------------------
+struct IterConsts {
+  double dpos, dneg;  // DCFR discounts for R > 0 and R <= 0
+  double avg_w;       // weight of the previous average-strategy sum
+  double avg_t;       // multiplier of the new term (t for CFR+, else 1)
+  double eps;
+  int variant, rm_mode;
+};
+
+struct IterK {
+  double dpos, dneg, avg_w, avg_t;
+};
+
+inline IterConsts consts_for(const pasur_cfr_params *p, int64_t t) {
+  IterConsts ic;
+  const double tm1 = (double)(t - 1);
+  double pa = std::pow(tm1, p->alpha);
+  double pb = std::pow(tm1, p->beta);
+  ic.dpos = pa / (pa + 1.0);
+  ic.dneg = pb / (pb + 1.0);
+  ic.avg_w = p->variant == PASUR_DCFR ? std::pow(tm1 / (double)t, p->gamma) : 1.0;
+  ic.avg_t = (double)t;
+  ic.eps = p->eps;
+  ic.variant = p->variant;
+  ic.rm_mode = p->rm_mode;
+  return ic;
+}
+
+inline IterK iter_k(const pasur_cfr_params *p, int64_t t) {
+  const IterConsts ic = consts_for(p, t);
+  return IterK{ic.dpos, ic.dneg, ic.avg_w, ic.avg_t};
+}
+
+// ---- wave-level helpers of the chunked up sweeps ----------------------------
+// The value of lane i-1 (lane_from_below) or lane i+1 (lane_from_above) of
+// the wave, by a DPP whole-wave shift; lane 0 (resp. 63) receives 0.
+__device__ __forceinline__ double lane_from_below(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x138, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_from_above(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x130, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of v over each sibling group of the wave (the group's lanes are
+// consecutive; pos = index within the group, k = group size), added in
+// sibling order from 0.0 exactly as the sequential loop does, and returned
+// on every lane of the group.  Each step moves values one lane; the steps
+// stop once no lane of the wave needs another (kw = largest group of the
+// wave).  Must run with all lanes of the wave active.
+__device__ __forceinline__ double group_sum(double v, int pos, int k, int kw) {
+  double acc = 0.0 + v;
+  for (int s = 1; s < kw; ++s) {
+    const double prev = lane_from_below(acc);
+    acc = pos == s ? prev + v : acc;
+  }
+  for (int s = 1; s < kw; ++s) {
+    const double next = lane_from_above(acc);
+    acc = k - 1 - pos == s ? next : acc;
+  }
+  return acc;
+}
+
+// Largest value of x over the wave (x >= 0), as a wave-uniform scalar.
+__device__ __forceinline__ int wave_max(int x) {
+  int m = x;
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x111, 0xF, 0xF, false));  // row_shr:1
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x112, 0xF, 0xF, false));  // row_shr:2
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x114, 0xF, 0xF, false));  // row_shr:4
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x118, 0xF, 0xF, false));  // row_shr:8
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x142, 0xF, 0xF, false));  // row_bcast:15
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x143, 0xF, 0xF, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(m, 63);
+}
+
+// ---- optional per-launch timing (pasur_profile_enable) ------------------------
+struct ProfRec {
+  int kernel, level;
+  int64_t work[5];  // kernel-specific work counts (edges, parents, roots, ..., iterations)
+  hipEvent_t a, b;
+};
+bool prof_on();
+void prof_push(const ProfRec &r);
+
+// Records HIP events around the launches made in its scope when profiling is on.
+struct ProfScope {
+  ProfRec rec;
+  hipStream_t s;
+  bool on;
+  ProfScope(int kernel, int level, hipStream_t stream, int64_t w0 = 0, int64_t w1 = 0,
+            int64_t w2 = 0, int64_t w3 = 0, int64_t w4 = 1)
+      : s(stream), on(prof_on()) {
+    if (!on) return;
+    rec.kernel = kernel;
+    rec.level = level;
+    rec.work[0] = w0;
+    rec.work[1] = w1;
+    rec.work[2] = w2;
+    rec.work[3] = w3;
+    rec.work[4] = w4;
+    (void)hipEventCreate(&rec.a);
+    (void)hipEventCreate(&rec.b);
+    (void)hipEventRecord(rec.a, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(rec.b, s);
+    prof_push(rec);
+  }
+};
+
+// ---- HBM-streaming schedule (pasur_sweep.hip) --------------------------------
+struct SweepIndex;
+void sweep_index_free(SweepIndex *x);
+// Iterations t0 .. t0+n_iters-1 of one round with level-wide streaming
+// launches (PASUR_SCHED_STREAM); same arguments as pasur_cfr_iterate.
+int sweep_iterate(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p,
+                  int64_t t0, int n_iters, hipStream_t s);
+// Whether the streaming schedule is expected to beat the persistent segment
+// schedule on this round (PASUR_SCHED_AUTO).
+bool sweep_pays(const pasur_fgt *f);
+
+
 }  // namespace pasur
 
 // Round game tree, device arrays per level.
@@ -150,4 +280,6 @@ struct pasur_fgt {
   int64_t n_roots;
   int32_t *root_off[9];
   int32_t *h_root_off;  // 9 * (n_roots + 1), level-major
+  // structure index of the streaming schedule, built on first use
+  pasur::SweepIndex *sweep;
 };

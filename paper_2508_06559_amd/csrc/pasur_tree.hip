@@ -676,6 +676,7 @@ extern "C" void pasur_fgt_free(pasur_fgt *f) {
   dev_free(f->leaf_base);
   for (int l = 0; l < 9; ++l) dev_free(f->root_off[l]);
   std::free(f->h_root_off);
+  sweep_index_free(f->sweep);
   delete f;
 }
 
