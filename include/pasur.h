@@ -178,7 +178,7 @@ typedef enum { PASUR_RM_FLOOR = 0, PASUR_RM_POSITIVE = 1 } pasur_rm_mode;
  *   is read on a call's first iteration and written after its last; single-
  *   child edges must hold sigma = 1 (as pasur_cfr_init and the warm start
  *   leave them);
- * AUTO: STREAM for rounds of at least 4e7 nodes, else ROOT. */
+ * AUTO: STREAM for rounds of at least 1e7 nodes, else ROOT. */
 typedef enum { PASUR_SCHED_ROOT = 0, PASUR_SCHED_LEVEL_SYNC = 1,
                PASUR_SCHED_ROOT_GLOBAL = 2, PASUR_SCHED_STREAM = 3,
                PASUR_SCHED_AUTO = 4 } pasur_schedule;

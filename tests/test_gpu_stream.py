@@ -57,7 +57,11 @@ def solve(pa, deck, start, roots, dtype, iters, sched, params=None):
     return s
 
 
+# deals whose trees have non-chain nodes on levels 6 and 7 (so the compact
+# tail has two levels), and one whose level 6 is all chains
 CASES = [("two-round 1", lambda: (4, synth.two_round_root(1))),
+         ("two-round 13", lambda: (4, synth.two_round_root(13))),
+         ("two-round 38", lambda: (4, synth.two_round_root(38))),
          ("last-round 2", lambda: (5, synth.last_round_roots(2)))]
 
 
@@ -86,6 +90,31 @@ def test_stream_equals_segment_schedule(dtype_name, case):
         assert np.array_equal(to_np(ra.V), to_np(rb.V))
     # the last round of these subgames has passive chains to skip
     assert skipped_edges([b.rounds[-1].fgt.read(pa.FGT_CHILD_BEGIN, l) for l in range(8)])[8].any()
+
+
+def test_stream_fp64_two_round_matches_oracle():
+    # a two-round subgame whose compact tail has non-chain nodes on levels 6
+    # and 7 in both rounds, 300 iterations per round, against the oracle
+    pa = require_gpu()
+    deck, roots = synth.two_round_root(13)
+    print("[stream] fp64 two-round 13 vs oracle", flush=True)
+    s = solve(pa, deck, 4, roots, pa.PASUR_F64, 300, pa.SCHED_STREAM)
+    rounds = oracle_rounds(deck, 4, roots)
+    res = oracle_solve(rounds, 300)
+    for k in (0, 1):
+        c, leaf, V = res[k]
+        st = s.rounds[k].state
+        skip = skipped_edges(rounds[k][1].child_begin())
+        for l in range(1, 9):
+            m = ~skip[l]
+            np.testing.assert_allclose(to_np(st.R[l]), c.get(oracle.CF_R, l), rtol=0, atol=1e-9)
+            np.testing.assert_allclose(to_np(st.Sbar[l])[m], c.get(oracle.CF_SBAR, l)[m], rtol=0,
+                                       atol=1e-9)
+            np.testing.assert_allclose(to_np(st.sigma_bar[l]), c.get(oracle.CF_SIGMA_BAR, l),
+                                       rtol=0, atol=1e-9)
+        for l in range(8):
+            np.testing.assert_allclose(to_np(st.u[l]), c.get(oracle.CF_U, l), rtol=0, atol=1e-9)
+        np.testing.assert_allclose(to_np(s.rounds[k].V), V, rtol=0, atol=1e-9)
 
 
 @pytest.mark.parametrize("variant,rm", [(oracle.CFR_DCFR, oracle.RM_FLOOR),
