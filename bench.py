@@ -36,30 +36,44 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CFR node-updates/s at 1 GPU; secs to exploitability 1e-3, warm-start vs plain"
 
-# HBM bytes per k_cfr_seg launch of the two-round workload (FP32 state, default
-# schedule) from rocprofv3 FETCH_SIZE / WRITE_SIZE counters, scaled by a
-# plain-copy calibration (the counter summaries under profiles/).  Valid only
-# while the kernel source is unchanged.
-TRAFFIC = {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
-           "sha256": "8a5ddb5c77265daad665dce4f88b4a8561c5daf99c8fbfcfc7c9ae652406889c",
-           # average per k_cfr_seg launch, two-round subgame of deal 1 (two launches)
-           "two-round": 4.60e6,
-           # the batched solve's largest launch (round 6 of all 64 deals)
-           "batched": 1.226e12}
+# HBM bytes per launch of each workload's dominant kernel, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE counters scaled by a plain-copy calibration (the
+# counter summaries under profiles/).  Valid only while the kernel's source
+# file is unchanged (sha256 recorded with the counters).
+TRAFFIC = {
+    # k_cfr_seg, two-round subgame of deal 1 (average of its two launches)
+    "two-round": {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
+                  "sha256": "8a5ddb5c77265daad665dce4f88b4a8561c5daf99c8fbfcfc7c9ae652406889c",
+                  "bytes": 4.60e6},
+    # k_cfr_seg, the batched solve's largest launch (round 6 of all 64 deals)
+    "batched": {"source": "paper_2508_06559_amd/csrc/pasur_cfr.hip",
+                "sha256": "8a5ddb5c77265daad665dce4f88b4a8561c5daf99c8fbfcfc7c9ae652406889c",
+                "bytes": 1.226e12},
+    # the full game's dominant streaming kernel (average over its launches)
+    "full-game": {"source": "paper_2508_06559_amd/csrc/pasur_sweep.hip",
+                  "sha256": "254fdc290d0d10bf97cde322f2949b2f51efb72502f91bd862f5dc3f31c37ea4",
+                  "bytes": 2.134e9},
+}
 
 
 def counted_traffic(args, workload="two-round"):
     """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (copy
     calibrated), valid only for the kernel source they were taken on."""
     import hashlib
-    path = os.path.join(ROOT, TRAFFIC["source"])
-    with open(path, "rb") as fh:
-        same = hashlib.sha256(fh.read()).hexdigest() == TRAFFIC["sha256"]
-    if not same or args.state != "f32":
+    rec = TRAFFIC[workload]
+    if rec["sha256"] is None or args.state != "f32":
         return None
-    if workload == "two-round" and (args.sched != "root" or args.block not in (0, 1024)):
+    with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != rec["sha256"]:
+            return None
+    if workload == "two-round" and (args.sched not in ("root", "auto") or
+                                    args.block not in (0, 1024)):
         return None
-    return TRAFFIC[workload]
+    if workload == "full-game" and args.sched != "auto":
+        return None
+    return rec["bytes"]
+
+
 HBM_PEAK_GBS = 8000.0
 
 
@@ -88,7 +102,52 @@ def launch_bytes(kernel, level, work, T):
     return iters * (up + down)
 
 
-KERNEL_NAMES = {0: "k_down", 1: "k_up", 2: "k_cfr_seg (all LDS)", 3: "k_cfr_seg (LDS + global)"}
+def sweep_bytes(kernel, level, work, T):
+    """Algorithmic bytes of one launch of the streaming schedule (kernel ids
+    of pasur_profile_read; work = nodes or children, parents, boundary-list
+    entries).  Per child of a tile up sweep: R and Sbar read and written, u
+    read (5 T); per parent: two CSR ends, both reaches read, u written
+    (4 + 3 T); per head of the compact tail at its boundary: its index, its
+    utility and its next strategy (4 + 2 T).  Per node of a tile down sweep:
+    R read, both reaches written (3 T); per parent: CSR, both reaches read
+    (4 + 2 T); per boundary parent: two reach copies (2 T).  List and tail
+    sweeps add their index reads (4 or 8 per node) and the stored sums of
+    the tail's parents (8 read and written)."""
+    n0, n1, n2 = int(work[0]), int(work[1]), int(work[2])
+    if kernel in (5, 6):      # up, tiles / one thread per parent
+        return n0 * 5 * T + n1 * (4 + 3 * T) + (16 * n1 if level == 1 else 0)
+    if kernel == 11:          # up, tiles, the tail's first level
+        return n0 * 5 * T + n1 * (4 + 3 * T) + n2 * (4 + 2 * T)
+    if kernel in (4, 14):     # down, tiles / one thread per parent
+        return n0 * 3 * T + n1 * (4 + 2 * T)
+    if kernel == 12:          # down, tiles, the level above the tail
+        return n0 * 3 * T + n1 * (4 + 2 * T) + n2 * (4 + 2 * T)
+    if kernel == 13:          # down over a node list (first iteration)
+        return n0 * (8 + 3 * T + 8 + 2 * T)
+    if kernel == 7:           # up over a parent list
+        return n0 * 5 * T + n1 * (4 + 8 + 3 * T)
+    if kernel == 9:           # tail down
+        return n0 * (8 + 3 * T + 8 + 2 * T)
+    if kernel == 10:          # tail up
+        return n0 * 5 * T + n1 * (4 + 4 + 16 + 3 * T)
+    return 0
+
+
+KERNEL_NAMES = {0: "k_down", 1: "k_up", 2: "k_cfr_seg (all LDS)", 3: "k_cfr_seg (LDS + global)",
+                4: "k_sw_down_tile", 5: "k_sw_up_tile", 6: "k_sw_up_parent (dense)",
+                7: "k_sw_up_parent (list)", 8: "streaming set-up", 9: "k_sw_down_list (tail)",
+                10: "k_sw_up_parent (tail)", 11: "k_sw_up_tile (tail boundary)",
+                12: "k_sw_down_tile (tail boundary)", 13: "k_sw_down_list", 14: "k_sw_down_parent"}
+# rocprofv3 names of the kernel ids (FP32 state, the paper's variant)
+KERNEL_SYMBOLS = {2: "k_cfr_seg<float, 1024, true>", 3: "k_cfr_seg<float, 1024, true>",
+                  4: "k_sw_down_tile<float, true, false>", 5: "k_sw_up_tile<float, true, false>",
+                  11: "k_sw_up_tile<float, true, true>", 12: "k_sw_down_tile<float, true, true>"}
+
+
+def all_launch_bytes(kernel, level, work, T):
+    if kernel in (0, 1, 2, 3):
+        return launch_bytes(kernel, level, work, T)
+    return sweep_bytes(kernel, level, work, T)
 
 
 def cpu_baseline(deck, roots, iters):
@@ -202,12 +261,78 @@ def bench_batched(args):
     b.free()
 
 
+def oracle_sample_roots(deck, per_round, seed):
+    """Roots of every round that the full game from the initial deal
+    reaches, found by following seeded picks through the oracle's own
+    unfolding (up to per_round roots per round)."""
+    import oracle
+    import synth
+    rng = np.random.default_rng(seed)
+    cur = [synth.Root(synth.mask_of(deck[:4]), 0, 0, 0, 0)]
+    out = []
+    for r in range(6):
+        out.append(cur)
+        if r == 5:
+            break
+        f = oracle.FGT(oracle.GT(deck, r, sorted({x.pool for x in cur})), cur)
+        nxt = [synth.Root(int(x["pool"]), int(x["ca"]), int(x["cb"]), int(x["d"]), int(x["bonus"]))
+               for x in f.get(oracle.FGT_NEXT_ROOTS)]
+        idx = sorted(rng.choice(len(nxt), size=min(per_round, len(nxt)), replace=False))
+        cur = [nxt[i] for i in idx]
+    return out
+
+
+def cpu_baseline_full(deck, round_edges, iters, threads, per_round=32, seed=7, min_s=1.0):
+    """The FP64 oracle's DCFR rate on seeded samples of every round of the
+    full game (roots reached through the oracle's own unfolding), each round
+    iterated until at least min_s seconds have passed, extrapolated per
+    node-update to the whole workload (round_edges[r] edges per round,
+    iters iterations each).  threads > 1 shares each level's parent loops."""
+    import oracle
+    sample = oracle_sample_roots(deck, per_round, seed)
+    oracle.set_threads(threads)
+    try:
+        rates, desc = [], []
+        for r, roots in enumerate(sample):
+            f = oracle.FGT(oracle.GT(deck, r, sorted({x.pool for x in roots})), roots)
+            leaf = f.leaf_utilities(None if r == 5 else np.zeros(max(f.n_next, 1)))
+            c = oracle.CFR(f.n, f.child_begin(), leaf)
+            edges = sum(f.n[1:])
+            done, t0 = 0, time.perf_counter()
+            while True:
+                c.run(5)
+                done += 5
+                el = time.perf_counter() - t0
+                if el >= min_s:
+                    break
+            rates.append(edges * done / el)
+            desc.append(f"round {r + 1}: {len(roots)} roots, {sum(f.n)} nodes, {done} iterations")
+    finally:
+        oracle.set_threads(1)
+    total_t = sum(e * iters / rt for e, rt in zip(round_edges, rates))
+    value = sum(round_edges) * iters / total_t
+    return value, rates, desc, total_t
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def bench_full(args):
-    """All six rounds of seeded deal --full-seed from the initial deal: build
-    and unfold every round, then DCFR round by round from round 6 backward
-    (--iters per round, default 1000), with exploitability.  The default
-    deal, seed 40, is the largest full game among seeds 1-64 (8.5e8 FGT
-    nodes; the paper reports about 1e9 per deck on average)."""
+    """All six rounds of seeded deal --full-seed from the initial deal, one
+    step = the whole hot path: build and unfold every round, leaf
+    utilities, DCFR round by round from round 6 backward (--iters per round,
+    default 1000), average strategies, round values passed back, and the
+    composed exploitability.  The default deal, seed 40, is the largest full
+    game among seeds 1-64 (8.5e8 FGT nodes; the paper reports about 1e9 per
+    deck on average)."""
     import torch
     import paper_2508_06559_amd as pa
     import synth
@@ -216,35 +341,124 @@ def bench_full(args):
     T = 4 if args.state == "f32" else 8
     iters = 1000 if args.iters == 2000 else args.iters
     deck, roots = synth.full_game_root(args.full_seed)
-    params = pa.paper_params(block=args.block)
-    times = []
-    for k in range(args.warmup + args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+    d_roots = pa.roots_to_device(roots)  # resident before timing
+    params = pa.paper_params({"root": pa.SCHED_ROOT, "level": pa.SCHED_LEVEL_SYNC,
+                              "root-global": pa.SCHED_ROOT_GLOBAL, "stream": pa.SCHED_STREAM,
+                              "auto": pa.SCHED_AUTO}[args.sched], args.block)
+    round_ms = []
+
+    def step(record_rounds=False):
         s = pa.SubgameSolver(deck, 0, roots, dtype=dtype)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        s.solve(iters, params)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        ev = [] if record_rounds else None
+        s.solve(iters, params, round_events=ev)
         bra, brb, _ = s.exploitability()
+        torch.cuda.synchronize()
+        if ev is not None:
+            round_ms[:] = [a.elapsed_time(b) for a, b in ev]
         ex = float(((bra - brb) / 2).max().item())
         sizes = s.sizes()
         V0 = float(s.rounds[0].V[0].item())
         s.free()
-        times.append((t1 - t0, tb - t0))
-        log(f"[bench] full game step {k + 1}: build {tb - t0:.2f} s, total {t1 - t0:.2f} s, "
-            f"exploitability {ex:.2e}, value {V0:.3f}")
-    el = sum(t for t, _ in times[args.warmup:])
+        return sizes, ex, V0
+
+    def per_kernel():
+        """Algorithmic bytes, seconds and launches per kernel id over the
+        recorded launches (HIP events on the launch stream)."""
+        kern, lev, ms, work = pa.profile_read()
+        per = {}
+        for i in range(len(kern)):
+            k = int(kern[i])
+            if k == 8:  # the streaming schedule's per-call set-up, not a sweep
+                continue
+            b, t, c = per.get(k, (0.0, 0.0, 0))
+            per[k] = (b + all_launch_bytes(k, int(lev[i]), work[i], T), t + float(ms[i]) * 1e-3,
+                      c + 1)
+        return per
+
+    # Warm-up steps time every sweep launch, which picks the dominant kernel
+    # (the largest share of time) and gives the whole-sweep figures; the
+    # timed steps then record only the dominant kernel's launches.  Without
+    # warm-up, the timed steps record every launch.
+    pa.profile_enable(True)
+    per_all = None
+    for w in range(args.warmup):
+        sizes, ex, V0 = step()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done, exploitability {ex:.3e}")
+    if args.warmup:
+        per_all = per_kernel()
+        dom = max(per_all, key=lambda k: per_all[k][1])
+        pa.profile_enable(True)
+        pa.profile_select([dom])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sizes, ex, V0 = step(record_rounds=k == args.steps - 1)
+        log(f"[bench] step {k + 1}/{args.steps} done ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    per_t = per_kernel()
+    pa.profile_enable(False)
+    if per_all is None:
+        per_all = per_t
+        dom = max(per_all, key=lambda k: per_all[k][1])
+    for k, (b, t, c) in sorted(per_all.items(), key=lambda kv: -kv[1][1]):
+        log(f"[bench] {KERNEL_NAMES.get(k, k)}: {c} launches, {t:.3f} s, avg {t / c * 1e6:.1f} us, "
+            f"{b / c / 1e6:.3f} MB/launch, {b / t / 1e9:.1f} GB/s")
+    all_b = sum(v[0] for v in per_all.values())
+    all_t = sum(v[1] for v in per_all.values())
+    db, dt, dc = per_t[dom]
+    achieved = db / dt / 1e9
     edges = sum(sum(n[1:]) for n in sizes)
-    out = {"metric": METRIC, "value": edges * iters * args.steps / el, "unit": "node-updates/s",
+    nodes = sum(sum(n) for n in sizes)
+    value = edges * iters * args.steps / el
+    tr = counted_traffic(args, "full-game")
+    rounds = []
+    for r, n in enumerate(sizes):
+        e_r = sum(n[1:])
+        ms_r = round_ms[5 - r] if len(round_ms) == 6 else None
+        rounds.append({"round": r + 1, "nodes": int(sum(n)), "edges": int(e_r),
+                       "schedule": "stream" if sum(n) >= 10_000_000 else "persistent segments",
+                       "dcfr_ms": ms_r,
+                       "node_updates_per_s": e_r * iters / (ms_r * 1e-3) if ms_r else None})
+    out = {"metric": METRIC, "value": value, "unit": "node-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"full game of seeded deal {args.full_seed}: 6 rounds, "
-                                  f"{sum(sum(n) for n in sizes)} nodes, {iters} DCFR iterations per round",
-                      "state": args.state, "round_sizes": [sum(n) for n in sizes],
-                      "build_seconds": times[-1][1], "exploitability_points": ex, "game_value": V0}}
+           "config": {"workload": f"full game of seeded deal {args.full_seed}: all 6 rounds "
+                                  f"({nodes} FGT nodes, {edges} edges), {iters} DCFR iterations per "
+                                  f"round, trees built and unfolded, round values passed back, "
+                                  f"composed exploitability",
+                      "state": args.state, "arithmetic": "f64 registers",
+                      "schedule": args.sched, "iters_per_round": iters,
+                      "rounds": rounds, "exploitability_points": ex, "game_value": V0},
+           "roofline": {"bound": "hbm",
+                        "kernel": f"{KERNEL_SYMBOLS.get(dom, KERNEL_NAMES.get(dom, dom))}",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": tr,
+                        "traffic_GBs": tr / (dt / dc) / 1e9 if tr is not None else None,
+                        "avg_launch_us": dt / dc * 1e6, "launches": dc,
+                        "algorithmic_bytes_per_launch": db / dc,
+                        "all_sweeps_GBs": all_b / all_t / 1e9,
+                        "all_sweeps_frac": all_b / all_t / 1e9 / HBM_PEAK_GBS}}
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        round_edges = [sum(n[1:]) for n in sizes]
+        log("[bench] cpu baseline (oracle, 1 thread) ...")
+        v1, r1, desc, t1 = cpu_baseline_full(deck, round_edges, iters, 1)
+        log(f"[bench] cpu baseline (oracle, {threads} threads) ...")
+        vn, rn, _, tn = cpu_baseline_full(deck, round_edges, iters, threads)
+        out["cpu_baseline"] = {
+            "value": vn, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+            "extrapolated": True,
+            "sample": (f"the FP64 oracle's DCFR on seeded samples of every round (up to 32 roots "
+                       f"per round, reached through the oracle's own unfolding; "
+                       f"{'; '.join(desc)}), each round iterated >= 1 s, per-round rates "
+                       f"extrapolated to the whole workload ({t1:.0f} s single-threaded, "
+                       f"{tn:.0f} s on {threads} threads per step)"),
+            "per_round_rates": rn,
+            "single_thread": {"value": v1, "cores": 1, "per_round_rates": r1},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
     print(json.dumps(out), flush=True)
 
 
@@ -860,18 +1074,20 @@ def bench_variants(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--state", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--sched", choices=["root", "level", "root-global"], default="root")
+    ap.add_argument("--sched", choices=["auto", "root", "level", "root-global", "stream"],
+                    default="auto")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game",
                                            "paper-scale", "selfplay", "es", "infoset", "mlp", "variants", "copy"],
-                    default="two-round",
-                    help="two-round: the headline configuration; batched: 64 deals, rounds 4-6; "
+                    default="full-game",
+                    help="full-game: the headline configuration (all six rounds of one deal); "
+                         "two-round: rounds 5-6 of one deal; batched: 64 deals, rounds 4-6; "
                          "warm-start: learned warm start vs plain DCFR")
     ap.add_argument("--train-deals", type=int, default=512)
     ap.add_argument("--test-deals", type=int, default=256)
@@ -927,7 +1143,8 @@ def main():
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
     params = pa.paper_params({"root": pa.SCHED_ROOT, "level": pa.SCHED_LEVEL_SYNC,
-                              "root-global": pa.SCHED_ROOT_GLOBAL}[args.sched], args.block)
+                              "root-global": pa.SCHED_ROOT_GLOBAL, "stream": pa.SCHED_STREAM,
+                              "auto": pa.SCHED_AUTO}[args.sched], args.block)
     deck, roots = synth.two_round_root(args.seed)
     d_roots = pa.roots_to_device(roots)  # resident before timing
     torch.cuda.synchronize()

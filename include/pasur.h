@@ -446,16 +446,26 @@ int pasur_shift_i32(const int32_t *src, int64_t n, int32_t add, int32_t *dst, vo
 /* ---- tracing ----------------------------------------------------------------
  * Per-launch timing of the sweep kernels with HIP events recorded on the
  * launch stream around every launch made by pasur_cfr_iterate.  Enabling
- * (or disabling) clears earlier records.  pasur_profile_read waits for the
- * events and copies up to `cap` records (kernel 0 = reach down-sweep,
- * 1 = fused up-sweep, level = child level; 2 = per-root kernel with every
- * subtree in LDS, 3 = per-root kernel with some subtrees in global memory,
- * level = -1) into host arrays, with
- * the work of each launch in `work` (5 int64 per record: edges, internal
- * nodes, roots, level-7 nodes covered, iterations); any output array may be
- * NULL.  *n_out gets the number recorded.  Not thread-safe against
- * concurrent iterate calls. */
+ * (or disabling) clears earlier records and selects every kernel;
+ * pasur_profile_select restricts recording to the kernel ids whose bit is
+ * set in kernel_mask.  pasur_profile_read waits for the events and copies up
+ * to `cap` records into host arrays, with the work of each launch in `work`
+ * (5 int64 per record); any output array may be NULL.  *n_out gets the
+ * number recorded.  Kernel ids, level and work:
+ *   0 reach down-sweep, 1 fused up-sweep (level-synchronous; level = child
+ *     level; work = edges, internal nodes);
+ *   2 / 3 persistent segment kernel, every subtree in LDS / some in global
+ *     memory (level -1; work = edges, internal nodes, roots, level-7 nodes,
+ *     iterations);
+ *   streaming schedule (level = child level; work = nodes or children,
+ *   parents, boundary-list entries): 4 tile down-sweep, 5 tile up-sweep,
+ *   6 up-sweep one thread per parent, 7 up-sweep over a parent list, 8 set-up
+ *   and tear-down of a call, 9 / 10 down / up sweeps of the compact tail,
+ *   11 / 12 tile up / down sweeps at the tail's boundary, 13 down-sweep over
+ *   a node list, 14 down-sweep one thread per parent.
+ * Not thread-safe against concurrent iterate calls. */
 int pasur_profile_enable(int on);
+int pasur_profile_select(uint64_t kernel_mask);
 int pasur_profile_read(int64_t cap, int32_t *kernel, int32_t *level, float *ms,
                        int64_t *work, int64_t *n_out);
 

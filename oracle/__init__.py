@@ -31,9 +31,10 @@ ROOT_DTYPE = np.dtype([("pool", "<u8"), ("ca", "i1"), ("cb", "i1"), ("d", "i1"),
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C99, -O2, single-threaded)."""
+    """Compile the oracle with gcc (plain C99, -O2; OpenMP only for the
+    optional multi-threaded CFR loops, single-threaded by default)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-Wall", "-Wextra",
+        cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
                "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd, cwd=_HERE)
         os.replace(_LIB + ".tmp", _LIB)
@@ -76,6 +77,7 @@ def lib():
         L.or_cfr_create.restype = vp
         L.or_cfr_create.argtypes = [vp, vp, vp, C.POINTER(C.c_int)]
         L.or_cfr_run.argtypes = [vp, vp, i64, i32]
+        L.or_set_threads.argtypes = [i32]
         L.or_cfr_copy.argtypes = [vp, i32, i32, vp]
         L.or_cfr_free.argtypes = [vp]
         L.or_tree_values.argtypes = [vp, vp, vp, vp, i32, i32, vp]
@@ -269,6 +271,12 @@ class CFR:
 
     def sigma_bar(self) -> List[np.ndarray]:
         return [np.ones(self.n[0])] + [self.get(CF_SIGMA_BAR, l) for l in range(1, 9)]
+
+
+def set_threads(n: int) -> None:
+    """Threads for the per-level parent loops of CFR.run (1 = the plain
+    single-threaded oracle; results are bit-identical for any count)."""
+    _check(lib().or_set_threads(int(n)), "set_threads")
 
 
 def tree_values(n, child_begin, leaf, sigma, mode: int, level: int = 0) -> np.ndarray:

@@ -1,10 +1,14 @@
 /*
  * pasur_oracle.c -- FP64 CPU oracle for the Pasur round solver.
  *
- * TEST INFRASTRUCTURE ONLY (see pasur_oracle.h).  Plain, slow and
- * single-threaded on purpose: every function follows the passage of the
- * paper it cites, in the order the paper gives, with no blocking, fusion or
- * reordering.
+ * TEST INFRASTRUCTURE ONLY (see pasur_oracle.h).  Plain and slow on
+ * purpose: every function follows the passage of the paper it cites, in the
+ * order the paper gives, with no blocking, fusion or reordering.  It runs
+ * single-threaded unless or_set_threads asks for more; then only the
+ * per-parent loops of one tree level inside or_cfr_run are shared out
+ * (each parent's sums stay sequential in child order, so every result is
+ * bit-identical to the single-threaded run) -- used to time the oracle on
+ * all host cores beside the GPU.
  */
 #include "pasur_oracle.h"
 
@@ -806,6 +810,13 @@ or_cfr *or_cfr_create(const int64_t n[9], const int32_t *const child_begin[8],
   return c;
 }
 
+static int g_threads = 1;
+
+int or_set_threads(int n) {
+  g_threads = n < 1 ? 1 : n;
+  return OR_OK;
+}
+
 static double o_dcfr_factor(double t_minus_1, double expo) {
   double p = pow(t_minus_1, expo); /* pow(0, 0) = 1 */
   return p / (p + 1.0);
@@ -818,6 +829,7 @@ int or_cfr_run(or_cfr *c, const or_params *p, int64_t t0, int n_iters) {
     for (int64_t j = 0; j < c->n[0]; j++) { c->reachA[0][j] = 1.0; c->reachB[0][j] = 1.0; }
     for (int l = 1; l <= 7; l++) {
       int mover = (l - 1) % 2;
+#pragma omp parallel for num_threads(g_threads) schedule(static) if (g_threads > 1)
       for (int64_t h = 0; h < c->n[l - 1]; h++) {
         for (int32_t q = c->cb[l - 1][h]; q < c->cb[l - 1][h + 1]; q++) {
           double a = c->reachA[l - 1][h], b = c->reachB[l - 1][h];
@@ -834,6 +846,7 @@ int or_cfr_run(or_cfr *c, const or_params *p, int64_t t0, int n_iters) {
     for (int l = 8; l >= 1; l--) {
       int mover = (l - 1) % 2;
       double sgn = mover == 0 ? 1.0 : -1.0;
+#pragma omp parallel for num_threads(g_threads) schedule(static) if (g_threads > 1)
       for (int64_t h = 0; h < c->n[l - 1]; h++) {
         int32_t b = c->cb[l - 1][h], e = c->cb[l - 1][h + 1];
         double uh = 0.0;

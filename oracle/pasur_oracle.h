@@ -101,6 +101,9 @@ enum { CF_SIGMA, CF_R, CF_SBAR, CF_U, CF_REACHA, CF_REACHB, CF_VACC,
 or_cfr *or_cfr_create(const int64_t n[9], const int32_t *const child_begin[8],
                       const double *leaf_u, int *status);
 int or_cfr_run(or_cfr *c, const or_params *p, int64_t t0, int n_iters);
+/* Threads for the per-level parent loops of or_cfr_run (default 1; results
+ * are bit-identical for any count). */
+int or_set_threads(int n);
 int or_cfr_copy(const or_cfr *c, int field, int level, double *dst);
 void or_cfr_free(or_cfr *c);
 

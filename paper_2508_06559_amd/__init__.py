@@ -116,6 +116,7 @@ def lib():
         L.pasur_gather_f32.argtypes = [vp, i32, vp, i64, vp, vp]
         L.pasur_shift_i32.argtypes = [vp, i64, i32, vp, vp]
         L.pasur_profile_enable.argtypes = [i32]
+        L.pasur_profile_select.argtypes = [C.c_uint64]
         L.pasur_profile_read.argtypes = [i64, vp, vp, vp, vp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
@@ -531,6 +532,14 @@ def shift_i32(src, n: int, add: int, dst, stream=None):
 
 def profile_enable(on: bool):
     _check(lib().pasur_profile_enable(1 if on else 0), "pasur_profile_enable")
+
+
+def profile_select(kernels):
+    """Record only the given kernel ids (see pasur_profile_read)."""
+    mask = 0
+    for k in kernels:
+        mask |= 1 << int(k)
+    _check(lib().pasur_profile_select(mask), "pasur_profile_select")
 
 
 def profile_read():

@@ -25,12 +25,14 @@ namespace {
 // stream), off unless pasur_profile_enable(1) was called.
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;  // events of cleared records, reused
 bool g_prof_on = false;
+uint64_t g_prof_mask = ~0ull;  // kernel ids recorded (bit k)
 
 void prof_clear() {
   for (auto &r : g_prof) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    g_event_pool.push_back(r.a);
+    g_event_pool.push_back(r.b);
   }
   g_prof.clear();
 }
@@ -835,10 +837,21 @@ void *seg_kernel(bool paper) {
 }  // namespace
 
 namespace pasur {
-bool prof_on() { return g_prof_on; }
+bool prof_on(int kernel) { return g_prof_on && ((g_prof_mask >> (kernel & 63)) & 1ull); }
 void prof_push(const ProfRec &r) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   g_prof.push_back(r);
+}
+void prof_events(hipEvent_t *a, hipEvent_t *b) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (hipEvent_t *e : {a, b}) {
+    if (!g_event_pool.empty()) {
+      *e = g_event_pool.back();
+      g_event_pool.pop_back();
+    } else {
+      (void)hipEventCreate(e);
+    }
+  }
 }
 }  // namespace pasur
 
@@ -1288,6 +1301,13 @@ extern "C" int pasur_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   prof_clear();
   g_prof_on = on != 0;
+  g_prof_mask = ~0ull;
+  return PASUR_OK;
+}
+
+extern "C" int pasur_profile_select(uint64_t kernel_mask) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_mask = kernel_mask;
   return PASUR_OK;
 }
 

@@ -203,8 +203,9 @@ struct ProfRec {
   int64_t work[5];  // kernel-specific work counts (edges, parents, roots, ..., iterations)
   hipEvent_t a, b;
 };
-bool prof_on();
+bool prof_on(int kernel);
 void prof_push(const ProfRec &r);
+void prof_events(hipEvent_t *a, hipEvent_t *b);  // two events from the pool
 
 // Records HIP events around the launches made in its scope when profiling is on.
 struct ProfScope {
@@ -213,7 +214,7 @@ struct ProfScope {
   bool on;
   ProfScope(int kernel, int level, hipStream_t stream, int64_t w0 = 0, int64_t w1 = 0,
             int64_t w2 = 0, int64_t w3 = 0, int64_t w4 = 1)
-      : s(stream), on(prof_on()) {
+      : s(stream), on(prof_on(kernel)) {
     if (!on) return;
     rec.kernel = kernel;
     rec.level = level;
@@ -222,8 +223,7 @@ struct ProfScope {
     rec.work[2] = w2;
     rec.work[3] = w3;
     rec.work[4] = w4;
-    (void)hipEventCreate(&rec.a);
-    (void)hipEventCreate(&rec.b);
+    prof_events(&rec.a, &rec.b);
     (void)hipEventRecord(rec.a, s);
   }
   ~ProfScope() {

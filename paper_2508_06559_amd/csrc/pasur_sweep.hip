@@ -934,9 +934,11 @@ __global__ void k_sw_sig_gather(int64_t m, const int32_t *__restrict__ act,
 }
 
 // kernel ids of the profile records (pasur_profile_read); work[0] = nodes
-// (or children) of the launch, work[1] = parents
+// (or children) of the launch, work[1] = parents, work[2] = entries of the
+// tail's boundary lists
 enum { PK_DOWN = 4, PK_UP = 5, PK_UP_PARENT = 6, PK_UP_LIST = 7, PK_SETUP = 8,
-       PK_TAIL_DOWN = 9, PK_TAIL_UP = 10 };
+       PK_TAIL_DOWN = 9, PK_TAIL_UP = 10, PK_UP_BND = 11, PK_DOWN_BND = 12, PK_DOWN_LIST = 13,
+       PK_DOWN_PARENT = 14 };
 
 // Per-call buffers of the compact tail.
 template <class T>
@@ -1050,14 +1052,16 @@ int sweep_t(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p, 
   };
   // every node of level L (tiles, or one thread per parent)
   auto down_dense = [&](int L, const Reach<T> &rc, const T *sg_first) {
-    ProfScope ps(PK_DOWN, L, s, f->n[L], f->n[L - 1], 0, 0, 1);
     if (x.tile[L]) {
       const int64_t nt = x.n_tile[L];
+      ProfScope ps(rc.bp ? PK_DOWN_BND : PK_DOWN, L, s, f->n[L], f->n[L - 1], rc.bp ? x.n_bp : 0, 0,
+                   1);
       auto kern = rc.bp ? (pos ? k_sw_down_tile<T, true, true> : k_sw_down_tile<T, false, true>)
                         : (pos ? k_sw_down_tile<T, true, false> : k_sw_down_tile<T, false, false>);
       kern<<<grid_of(nt * kBlk), kBlk, 0, s>>>(nt, x.tile[L], x.tile_c[L], f->child_begin[L - 1],
                                                R[L], sg_first, rc, rm, eps);
     } else if (f->n[L - 1] > 0) {
+      ProfScope ps(PK_DOWN_PARENT, L, s, f->n[L], f->n[L - 1], 0, 0, 1);
       k_sw_down_parent<T><<<grid_of(f->n[L - 1]), kBlk, 0, s>>>(f->n[L - 1], f->child_begin[L - 1],
                                                                  R[L], sg_first, rc, rm, eps);
     }
@@ -1066,7 +1070,8 @@ int sweep_t(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p, 
   auto up_dense = [&](int L, const UpArgs<T> &a, const IterK &ik) {
     if (x.tile[L]) {
       const int64_t nt = x.n_tile[L];
-      ProfScope ps(PK_UP, L, s, f->n[L], f->n[L - 1], 0, 0, 1);
+      ProfScope ps(a.act ? PK_UP_BND : PK_UP, L, s, f->n[L], f->n[L - 1],
+                   a.act ? x.n_act[x.S] : 0, 0, 1);
       auto kern = a.act ? (pos ? k_sw_up_tile<T, true, true> : k_sw_up_tile<T, false, true>)
                         : (pos ? k_sw_up_tile<T, true, false> : k_sw_up_tile<T, false, false>);
       kern<<<grid_of(nt * kBlk), kBlk, 0, s>>>(nt, x.tile[L], x.tile_c[L], a, ik, var, rm, eps);
@@ -1086,7 +1091,7 @@ int sweep_t(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p, 
         down_dense(L, rc, first ? sg[L] : nullptr);
       } else if (x.n_act[L] > 0) {
         const int64_t n = x.n_act[L];
-        ProfScope ps(PK_DOWN, L, s, n, 0, 0, 0, 1);
+        ProfScope ps(PK_DOWN_LIST, L, s, n, 0, 0, 0, 1);
         k_sw_down_list<T><<<grid_of(n), kBlk, 0, s>>>(n, x.act[L], f->parent[L], nullptr, R[L],
                                                        first ? sg[L] : nullptr, nullptr,
                                                        f->child_begin[L - 1], rc, rm, eps);
@@ -1098,7 +1103,7 @@ int sweep_t(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p, 
       if (x.n_act[L - 1] < f->n[L - 1]) {
         const int64_t n = x.n_act[L - 1];
         if (n == 0) continue;
-        ProfScope ps(PK_UP_LIST, L, s, 0, n, 0, 0, 1);
+        ProfScope ps(PK_UP_LIST, L, s, x.m[L], n, 0, 0, 1);
         k_sw_up_parent<T, PAPER><<<grid_of(n), kBlk, 0, s>>>(n, x.act[L - 1], a, ik, var, rm, eps);
       } else {
         up_dense(L, a, ik);

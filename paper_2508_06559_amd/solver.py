@@ -59,8 +59,11 @@ class SubgameSolver:
     def edges(self) -> int:
         return sum(rr.fgt.edges() for rr in self.rounds)
 
-    def solve(self, iters: int, params=None, value_mode: int = V_ITERATE_MEAN):
-        """Backward DCFR: ``iters`` iterations per round."""
+    def solve(self, iters: int, params=None, value_mode: int = V_ITERATE_MEAN,
+              round_events=None):
+        """Backward DCFR: ``iters`` iterations per round.  If ``round_events``
+        is a list, a (start, end) pair of CUDA events around each round's
+        iterations is appended to it (last round first)."""
         torch = self.torch
         params = params if params is not None else paper_params()
         V = None
@@ -69,7 +72,13 @@ class SubgameSolver:
             rr.state = st
             leaf_utilities(rr.fgt, V, self.dtype, st.u[8], self.stream)
             cfr_init(st, self.stream)
+            if round_events is not None:
+                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                ev[0].record()
             cfr_iterate(st, iters, params, stream=self.stream)
+            if round_events is not None:
+                ev[1].record()
+                round_events.append(ev)
             average_strategy(st, self.stream)
             rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
             round_values(st, value_mode, rr.V, self.stream)

@@ -139,6 +139,25 @@ def test_cfr_plus_and_vanilla_split_runs_continue_the_count():
             np.testing.assert_array_equal(a.get(oracle.CF_R, l), b.get(oracle.CF_R, l))
 
 
+def test_threaded_cfr_is_bit_identical():
+    # the per-level parent loops shared out over threads give the same
+    # arrays bit for bit (each parent's sums stay sequential)
+    deck, roots = synth.last_round_roots(2)
+    f = oracle.FGT(oracle.GT(deck, 5, sorted({x.pool for x in roots})), roots)
+    out = []
+    for threads in (1, 4):
+        oracle.set_threads(threads)
+        try:
+            c = oracle.CFR(f.n, f.child_begin(), f.leaf_utilities())
+            c.run(50)
+            out.append([c.get(fld, l) for fld in (oracle.CF_R, oracle.CF_SBAR, oracle.CF_SIGMA)
+                        for l in range(1, 9)] + [c.get(oracle.CF_VACC)])
+        finally:
+            oracle.set_threads(1)
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_floor_rule_matches_textbook_when_regrets_are_large():
     # The executed rule max(R, 1e-8)/sum differs from the positive-part rule
     # only by terms of order 1e-8.
