@@ -49,7 +49,9 @@ typedef enum {
   PASUR_E_RANGE = -2,    /* round outside 0..5, t0 < 1, unknown enum value */
   PASUR_E_OVERFLOW = -3, /* a tree level would exceed INT32_MAX nodes */
   PASUR_E_HIP = -4,      /* HIP runtime error (text in pasur_last_error) */
-  PASUR_E_NOMEM = -5     /* device allocation failed */
+  PASUR_E_NOMEM = -5,    /* device allocation failed */
+  PASUR_E_CAPACITY = -6  /* a fixed or caller-sized buffer is too small (the size
+                            needed is reported where the call says so) */
 } pasur_status;
 
 typedef enum { PASUR_F32 = 0, PASUR_F64 = 1 } pasur_dtype;
@@ -253,6 +255,18 @@ typedef enum { PASUR_TV_EXPECT = 0, PASUR_TV_BR_A = 1, PASUR_TV_BR_B = 2,
 int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
                       void *const sigma[9], int mode, double *d_out,
                       void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and arguments as pasur_tree_values, with its two level
+ * buffers in a fixed device array instead of stream-ordered allocations.
+ * Allocates nothing.  Limit: every level 0..7 of the tree at most 2^21
+ * (2,097,152) nodes -- larger trees get PASUR_E_CAPACITY (use
+ * pasur_tree_values).  Each GPU holds one 32 MiB array for the process's
+ * lifetime, shared by every call on that GPU: calls that overlap on one GPU
+ * (on any streams) race and must be serialised by the caller. */
+int pasur_tree_values_noalloc(const pasur_fgt *fgt, const double *d_leaf, int dtype,
+                              void *const sigma[9], int mode, double *d_out, void *stream);
 
 /* ---- f2: self-play (section "Experimental Evaluation") ---------------------
  * n_games independent games on one solved subgame, one GPU thread each, from

@@ -85,6 +85,7 @@ def lib():
         L.pasur_average_strategy.argtypes = [vp, vp, vp, vp]
         L.pasur_round_values.argtypes = [vp, vp, i32, i64, vp, vp, vp]
         L.pasur_tree_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+        L.pasur_tree_values_noalloc.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.pasur_plan_create.argtypes = [vp, vp, i32, vp, i64, i64, C.POINTER(vp), vp]
         L.pasur_plan_iterate.argtypes = [vp, i64, i32, vp]
         L.pasur_plan_info.argtypes = [vp, vp]
@@ -339,6 +340,19 @@ def tree_values(fgt: UnfoldedTree, d_leaf, dtype: int, sigma: Optional[List], mo
         sp = (C.c_void_p * 9)(*([None] + [t.data_ptr() for t in sigma[1:]]))
     _check(lib().pasur_tree_values(fgt.h, _p(d_leaf), dtype, sp, mode, _p(d_out),
                                    _stream(stream)), "pasur_tree_values")
+    return d_out
+
+
+def tree_values_noalloc(fgt: UnfoldedTree, d_leaf, dtype: int, sigma: Optional[List], mode: int,
+                        d_out, stream=None):
+    """pasur_tree_values_noalloc: tree_values with no device allocation
+    (levels of at most 2^21 nodes)."""
+    if sigma is None:
+        sp = None
+    else:
+        sp = (C.c_void_p * 9)(*([None] + [t.data_ptr() for t in sigma[1:]]))
+    _check(lib().pasur_tree_values_noalloc(fgt.h, _p(d_leaf), dtype, sp, mode, _p(d_out),
+                                           _stream(stream)), "pasur_tree_values_noalloc")
     return d_out
 
 

@@ -1104,19 +1104,19 @@ extern "C" int pasur_plan_info(const pasur_plan *pl, int64_t info[8]) {
 
 namespace {
 
-template <class T, class L>
-int values_t(const pasur_fgt *f, const L *leaf, void *const sigma[9], int mode, double *out,
-             hipStream_t s) {
+int64_t widest_level(const pasur_fgt *f) {
   int64_t mx = 1;
   for (int l = 0; l <= 7; ++l) mx = f->n[l] > mx ? f->n[l] : mx;
-  double *buf[2] = {nullptr, nullptr};
-  PASUR_TRY_HIP(hipMallocAsync((void **)&buf[0], mx * sizeof(double), s));
-  hipError_t e = hipMallocAsync((void **)&buf[1], mx * sizeof(double), s);
-  if (e != hipSuccess) {
-    (void)hipFreeAsync(buf[0], s);
-    set_error("hipMallocAsync: %s", hipGetErrorString(e));
-    return PASUR_E_NOMEM;
-  }
+  return mx;
+}
+
+// The up-sweep of tree values through two level buffers of at least
+// widest_level(f) doubles each (every level is written in full before it
+// is read, so the buffers need no clearing).
+template <class T, class L>
+void values_run(const pasur_fgt *f, const L *leaf, void *const sigma[9], int mode, double *out,
+                double *buf0, double *buf1, hipStream_t s) {
+  double *buf[2] = {buf0, buf1};
   int cur = 0;
   for (int l = 8; l >= 1; --l) {
     double *dst = l == 1 ? out : buf[cur];
@@ -1129,6 +1129,21 @@ int values_t(const pasur_fgt *f, const L *leaf, void *const sigma[9], int mode, 
           f->n[l - 1], (l - 1) & 1, mode, f->child_begin[l - 1], sg, buf[cur ^ 1], dst);
     cur ^= 1;
   }
+}
+
+template <class T, class L>
+int values_t(const pasur_fgt *f, const L *leaf, void *const sigma[9], int mode, double *out,
+             hipStream_t s) {
+  const int64_t mx = widest_level(f);
+  double *buf[2] = {nullptr, nullptr};
+  PASUR_TRY_HIP(hipMallocAsync((void **)&buf[0], mx * sizeof(double), s));
+  hipError_t e = hipMallocAsync((void **)&buf[1], mx * sizeof(double), s);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(buf[0], s);
+    set_error("hipMallocAsync: %s", hipGetErrorString(e));
+    return PASUR_E_NOMEM;
+  }
+  values_run<T, L>(f, leaf, sigma, mode, out, buf[0], buf[1], s);
   e = hipGetLastError();
   (void)hipFreeAsync(buf[0], s);
   (void)hipFreeAsync(buf[1], s);
@@ -1136,6 +1151,64 @@ int values_t(const pasur_fgt *f, const L *leaf, void *const sigma[9], int mode, 
     set_error("tree values: %s", hipGetErrorString(e));
     return PASUR_E_HIP;
   }
+  return PASUR_OK;
+}
+
+int check_tree_values(const pasur_fgt *f, const double *d_leaf, int dtype, void *const sigma[9],
+                      int mode, double *d_out) {
+  if (!f || !d_leaf || !d_out) {
+    set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  if (mode < 0 || mode > 3 || (dtype != PASUR_F32 && dtype != PASUR_F64)) {
+    set_error("unknown mode or dtype");
+    return PASUR_E_RANGE;
+  }
+  if (mode != PASUR_TV_MINIMAX) {
+    if (!sigma) {
+      set_error("sigma is NULL");
+      return PASUR_E_INVAL;
+    }
+    for (int l = 1; l <= 8; ++l)
+      if (!sigma[l]) {
+        set_error("sigma[%d] is NULL", l);
+        return PASUR_E_INVAL;
+      }
+  }
+  return PASUR_OK;
+}
+
+// ---- pasur_tree_values_noalloc: the level buffers in a fixed device array.
+// Each GPU the library runs on holds its own copy of `scratch` (two level
+// buffers of kNoAllocLevel doubles, 32 MiB) until the process ends.  Host
+// code never uses the array's name as an address: its per-device address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, on the entry point's first call there.
+constexpr int64_t kNoAllocLevel = (int64_t)1 << 21;
+static __device__ __align__(256) double scratch[2 * kNoAllocLevel];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+int scratch_for_current_device(double **out) {
+  int dev = 0;
+  PASUR_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d beyond the %d devices the scratch table covers", dev, kMaxDevices);
+    return PASUR_E_RANGE;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      return PASUR_E_HIP;
+    }
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *out = g_scratch_ptr[dev];
   return PASUR_OK;
 }
 
@@ -1273,28 +1346,32 @@ extern "C" int pasur_round_values(const pasur_fgt *f, const pasur_cfr_state *st,
 
 extern "C" int pasur_tree_values(const pasur_fgt *f, const double *d_leaf, int dtype,
                                  void *const sigma[9], int mode, double *d_out, void *stream) {
-  if (!f || !d_leaf || !d_out) {
-    set_error("null argument");
-    return PASUR_E_INVAL;
-  }
-  if (mode < 0 || mode > 3 || (dtype != PASUR_F32 && dtype != PASUR_F64)) {
-    set_error("unknown mode or dtype");
-    return PASUR_E_RANGE;
-  }
-  if (mode != PASUR_TV_MINIMAX) {
-    if (!sigma) {
-      set_error("sigma is NULL");
-      return PASUR_E_INVAL;
-    }
-    for (int l = 1; l <= 8; ++l)
-      if (!sigma[l]) {
-        set_error("sigma[%d] is NULL", l);
-        return PASUR_E_INVAL;
-      }
-  }
+  PASUR_TRY(check_tree_values(f, d_leaf, dtype, sigma, mode, d_out));
   hipStream_t s = (hipStream_t)stream;
   return dtype == PASUR_F32 ? values_t<float, double>(f, d_leaf, sigma, mode, d_out, s)
                             : values_t<double, double>(f, d_leaf, sigma, mode, d_out, s);
+}
+
+extern "C" int pasur_tree_values_noalloc(const pasur_fgt *f, const double *d_leaf, int dtype,
+                                         void *const sigma[9], int mode, double *d_out,
+                                         void *stream) {
+  PASUR_TRY(check_tree_values(f, d_leaf, dtype, sigma, mode, d_out));
+  const int64_t mx = widest_level(f);
+  if (mx > kNoAllocLevel) {
+    set_error("a tree level of %lld nodes exceeds the %lld-node scratch of "
+              "pasur_tree_values_noalloc (use pasur_tree_values)",
+              (long long)mx, (long long)kNoAllocLevel);
+    return PASUR_E_CAPACITY;
+  }
+  double *p = nullptr;
+  PASUR_TRY(scratch_for_current_device(&p));
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == PASUR_F32)
+    values_run<float, double>(f, d_leaf, sigma, mode, d_out, p, p + kNoAllocLevel, s);
+  else
+    values_run<double, double>(f, d_leaf, sigma, mode, d_out, p, p + kNoAllocLevel, s);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
 }
 
 extern "C" int pasur_profile_enable(int on) {
