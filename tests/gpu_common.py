@@ -69,3 +69,89 @@ def oracle_exploitability(rounds, sbars):
 
 def to_np(t):
     return t.detach().cpu().numpy()
+
+
+NEAR_TIE = 1e-3
+
+
+def tie_groups(f, leaf, tol=NEAR_TIE):
+    """Per level l = 1..8, a group id for every edge: the children of one
+    parent whose minimax values (oracle, exact tree values) agree within tol
+    share an id.  Such actions are equally good, or so nearly equal that
+    DCFR has not separated them after a few thousand iterations; the split
+    of the average strategy among them is not unique (in the last round the
+    leaf values are integers, so only exact ties group)."""
+    cb = f.child_begin()
+    groups = [None]
+    for l in range(1, 9):
+        mm = oracle.tree_values(f.n, cb, leaf, None, oracle.TV_MINIMAX, level=l)
+        b = np.asarray(cb[l - 1], np.int64)
+        gid = np.empty(len(mm), np.int64)
+        nxt = 0
+        for h in range(len(b) - 1):
+            vals = mm[b[h]:b[h + 1]]
+            seen = []
+            for j, v in enumerate(vals):
+                for gv, g in seen:
+                    if abs(gv - v) <= tol:
+                        gid[b[h] + j] = g
+                        break
+                else:
+                    seen.append((v, nxt))
+                    gid[b[h] + j] = nxt
+                    nxt += 1
+        groups.append(gid)
+    return groups
+
+
+def path_reach(child_begin, sigma_bar):
+    """Per level l = 0..7, the probability that play under the average
+    profile passes through each node: the product of sigma-bar along the
+    path from the root (both players' moves)."""
+    cb = [np.asarray(c, np.int64) for c in child_begin]
+    out = [np.ones(len(cb[0]) - 1)]
+    for l in range(1, 8):
+        par = np.repeat(np.arange(len(cb[l - 1]) - 1), np.diff(cb[l - 1]))
+        out.append(out[-1][par] * np.asarray(sigma_bar[l], np.float64))
+    return out
+
+
+def assert_sigma_bar_up_to_ties(gpu_sb, oracle_sb, groups, child_begin, tol, what=""):
+    """Average strategies compared by how often each action is played: for
+    every untied action, |gpu - oracle| times the probability that play
+    under the average profile reaches its parent (the smaller of the two
+    profiles' probabilities) within tol, and the same for the total of every
+    tie group.  Behaviour at a node that play does not reach is not fixed by
+    an equilibrium (it rests on regrets scaled by a vanishing reach and is
+    set by rounding); its effect is what exploitability measures.  Returns
+    (actions in tie groups, actions, largest unweighted difference at
+    parents reached with probability >= 0.5)."""
+    xo = path_reach(child_begin, oracle_sb)
+    xg = path_reach(child_begin, gpu_sb)
+    cb = [np.asarray(c, np.int64) for c in child_begin]
+    tied, total, big = 0, 0, 0.0
+    for l in range(1, 9):
+        g = groups[l]
+        a = np.asarray(gpu_sb[l], np.float64)
+        b = np.asarray(oracle_sb[l], np.float64)
+        par = np.repeat(np.arange(len(cb[l - 1]) - 1), np.diff(cb[l - 1]))
+        w = np.minimum(xo[l - 1], xg[l - 1])[par]
+        size = np.bincount(g)
+        single = size[g] == 1
+        tied += int((~single).sum())
+        total += len(g)
+        d = np.abs(a - b)
+        if single.any():
+            dw = d[single] * w[single]
+            assert dw.max() <= tol, (what, l, int(np.nonzero(single)[0][np.argmax(dw)]),
+                                     float(dw.max()))
+            hi = single & (w >= 0.5)
+            if hi.any():
+                big = max(big, float(d[hi].max()))
+        sa = np.bincount(g, a, len(size))
+        sb = np.bincount(g, b, len(size))
+        gw = np.zeros(len(size))
+        gw[g] = w
+        dg = np.abs(sa - sb) * gw
+        assert dg.max() <= tol, (what, l, "group sums", float(dg.max()))
+    return tied, total, big

@@ -3,17 +3,20 @@ exploitability against the FP64 oracle, through the C ABI.
 
 FP64 state: every array must match the oracle within 1e-9 (the kernels keep
 the oracle's operation order, so in practice they agree exactly).
-FP32 state: root values must match within 1e-5; strategies are checked for
-validity (simplex) and quality (exploitability), because ties between
-equally good actions make the split of probability among them depend on
-rounding (FP32 rounding noise in the regrets exceeds the regret floor)."""
+FP32 state: root values must match within 1e-5, and average strategies
+within 1e-5 as play frequencies (each action's sigma-bar difference times the
+probability that play reaches its parent), with equally good actions
+compared by their total: ties make the split among them depend on rounding
+(FP32 noise in the regrets exceeds the regret floor), and behaviour where
+play does not go is not fixed by an equilibrium.  That behaviour is checked
+through quality instead (exploitability no worse than the oracle's)."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from gpu_common import (oracle_exploitability, oracle_rounds, oracle_solve, require_gpu,
-                        to_np)
+from gpu_common import (assert_sigma_bar_up_to_ties, oracle_exploitability, oracle_rounds,
+                        oracle_solve, require_gpu, tie_groups, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -109,6 +112,50 @@ def test_fp32_state_values_and_strategy_quality(seed):
     # equally good actions may split differently, but the profile must be as
     # good as the oracle's
     assert ex_gpu.max() <= 1.5 * ex_or.max() + 1e-6
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_fp32_sigma_bar_matches_oracle_up_to_ties_last_round(seed):
+    # FP32 state against the FP64 oracle: how often each action is played
+    # (its sigma-bar difference times the probability that play under the
+    # average profile reaches its parent) within 1e-5, and among equally good
+    # actions (same minimax value under one parent) only their total, since
+    # FP32 rounding noise in the regrets exceeds the regret floor and may
+    # split that total differently.
+    pa = require_gpu()
+    deck, roots = synth.last_round_roots(seed)
+    print(f"[cfr fp32] sigma-bar up to ties, last round seed={seed} T=1000", flush=True)
+    s = gpu_solver(pa, deck, 5, roots, pa.PASUR_F32, 1000)
+    rounds = oracle_rounds(deck, 5, roots)
+    (c, leaf, V), = oracle_solve(rounds, 1000)
+    groups = tie_groups(rounds[0][1], leaf)
+    gsb = [None] + [to_np(t) for t in s.rounds[0].state.sigma_bar[1:]]
+    tied, total, big = assert_sigma_bar_up_to_ties(gsb, c.sigma_bar(), groups,
+                                                   rounds[0][1].child_begin(), TOL32_VALUES, seed)
+    print(f"[cfr fp32] {tied} of {total} actions in tie groups; largest difference at parents "
+          f"reached with probability >= 0.5: {big:.2e}", flush=True)
+    assert tied < total
+
+
+@pytest.mark.parametrize("seed", [1, 13])
+def test_fp32_sigma_bar_matches_oracle_up_to_ties_two_rounds(seed):
+    # round 5's leaves are round 6's values, FP32 on the GPU: actions whose
+    # minimax values differ by less than 1e-3 count as tied there
+    pa = require_gpu()
+    deck, roots = synth.two_round_root(seed)
+    print(f"[cfr fp32] sigma-bar up to ties, two rounds seed={seed} T=2000", flush=True)
+    s = gpu_solver(pa, deck, 4, roots, pa.PASUR_F32, 2000)
+    rounds = oracle_rounds(deck, 4, roots)
+    res = oracle_solve(rounds, 2000)
+    for k in (1, 0):
+        c, leaf, V = res[k]
+        groups = tie_groups(rounds[k][1], leaf)
+        gsb = [None] + [to_np(t) for t in s.rounds[k].state.sigma_bar[1:]]
+        tied, total, big = assert_sigma_bar_up_to_ties(gsb, c.sigma_bar(), groups,
+                                                       rounds[k][1].child_begin(), TOL32_VALUES, k)
+        print(f"[cfr fp32] round {k + 5}: {tied} of {total} actions in tie groups; largest "
+              f"difference at parents reached with probability >= 0.5: {big:.2e}", flush=True)
+        assert max_diff(to_np(s.rounds[k].V), V) <= TOL32_VALUES
 
 
 def test_fp32_two_round_values():

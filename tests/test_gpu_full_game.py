@@ -23,7 +23,8 @@ import pytest
 import oracle
 import synth
 from conftest import card_index, cards_of, read_rows
-from gpu_common import oracle_rounds, oracle_solve, require_gpu, roots_from_array, to_np
+from gpu_common import (assert_sigma_bar_up_to_ties, oracle_rounds, oracle_solve, require_gpu,
+                        roots_from_array, tie_groups, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -144,4 +145,45 @@ def test_full_game_at_scale_sampled_parity(seed, min_nodes, iters):
                                            atol=TOL64, err_msg=f"round {r} root {k} level {l}")
             assert abs(V[k] - res[0][2][0]) < TOL64, (r, k, V[k], res[0][2][0])
             print(f"[full game] round {r} root {k}: {sum(orr[0][1].n)} nodes match", flush=True)
+    s.free()
+
+
+def test_full_game_fp32_sampled_parity_up_to_ties():
+    # The benchmark's configuration (deal 40, FP32 state, 1000 iterations per
+    # round, the default schedule): sampled roots of rounds 5 and 6 against
+    # the oracle's solve of each root alone -- how often each untied action
+    # and each tie group (equally good actions under one parent) is played
+    # within 1e-5, root values within 1e-5.
+    pa = require_gpu()
+    import torch
+    deck, roots = synth.full_game_root(40)
+    iters = 1000
+    print(f"[full game] seed 40, FP32 state, {iters} DCFR iterations per round", flush=True)
+    s = pa.SubgameSolver(deck, 0, roots, dtype=pa.PASUR_F32)
+    s.solve(iters)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(41)
+    sample = _sample_reached_roots(deck, rng, per_round=3)
+    for r, picks in sample.items():
+        rr = s.rounds[r]
+        gpu_roots = s.rounds[r - 1].fgt.read(pa.FGT_NEXT_ROOTS)
+        cbs = [rr.fgt.read(pa.FGT_CHILD_BEGIN, l) for l in range(8)]
+        V = to_np(rr.V)
+        for root in picks:
+            k = np.nonzero((gpu_roots["pool"] == root.pool) & (gpu_roots["ca"] == root.ca)
+                           & (gpu_roots["cb"] == root.cb) & (gpu_roots["d"] == root.d)
+                           & (gpu_roots["bonus"] == root.bonus))[0]
+            assert len(k) == 1, root
+            k = int(k[0])
+            orr = oracle_rounds(deck, r, [root])
+            res = oracle_solve(orr, iters)
+            c0, leaf0, V0 = res[0]
+            sl = _subtree_slices(cbs, k)
+            gsb = [None] + [to_np(rr.state.sigma_bar[l][sl[l][0]:sl[l][1]]) for l in range(1, 9)]
+            tied, total, big = assert_sigma_bar_up_to_ties(
+                gsb, c0.sigma_bar(), tie_groups(orr[0][1], leaf0), orr[0][1].child_begin(), 1e-5,
+                (r, k))
+            assert abs(V[k] - V0[0]) <= 1e-5, (r, k, V[k], V0[0])
+            print(f"[full game] fp32 round {r} root {k}: {total} actions ({tied} tied) match; "
+                  f"largest difference at reach >= 0.5: {big:.2e}", flush=True)
     s.free()
