@@ -256,6 +256,27 @@ int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
                       void *const sigma[9], int mode, double *d_out,
                       void *stream);
 
+/* Exploitability of a subgame's average strategies, composed across its
+ * rounds (the paper names exploitability as future work; the definition is
+ * the standard one for two-player zero-sum games).  fgts[0..n_rounds-1] are
+ * consecutive rounds, each the unfolding of the previous one's next-round
+ * roots, the last being round 5; sigma_bar[r*9 + l] (device, `dtype`,
+ * levels 1..8 of round slot r; entries r*9 are unused) are the average
+ * strategies.  For every root of fgts[0], on the device in double:
+ *   d_br_a[k]: Alex's value when he best-responds to Bob's sigma_bar,
+ *   d_br_b[k]: Alex's value when Bob best-responds to Alex's sigma_bar,
+ *   d_v[k]:    Alex's value when both play sigma_bar.
+ * Each round's leaf value is its round points plus the later round's value
+ * of the same kind at the linked root.  Any output may be NULL (not
+ * computed), not all three.  Exploitability in points per game is
+ * (br_a - br_b) / 2 >= 0.  Asynchronous on `stream`; uses stream-ordered
+ * scratch (a level of each round, its leaves and its roots, in double).
+ * PASUR_E_INVAL for null or inconsistent trees, PASUR_E_RANGE for n_rounds
+ * outside 1..6 or an unknown dtype. */
+int pasur_exploitability(const pasur_fgt *const *fgts, int n_rounds, void *const *sigma_bar,
+                         int dtype, double *d_br_a, double *d_br_b, double *d_v,
+                         void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation and arguments as pasur_tree_values, with its two level

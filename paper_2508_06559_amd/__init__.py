@@ -86,6 +86,7 @@ def lib():
         L.pasur_round_values.argtypes = [vp, vp, i32, i64, vp, vp, vp]
         L.pasur_tree_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.pasur_tree_values_noalloc.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+        L.pasur_exploitability.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
         L.pasur_plan_create.argtypes = [vp, vp, i32, vp, i64, i64, C.POINTER(vp), vp]
         L.pasur_plan_iterate.argtypes = [vp, i64, i32, vp]
         L.pasur_plan_info.argtypes = [vp, vp]
@@ -354,6 +355,21 @@ def tree_values_noalloc(fgt: UnfoldedTree, d_leaf, dtype: int, sigma: Optional[L
     _check(lib().pasur_tree_values_noalloc(fgt.h, _p(d_leaf), dtype, sp, mode, _p(d_out),
                                            _stream(stream)), "pasur_tree_values_noalloc")
     return d_out
+
+
+def exploitability(fgts, sigma_bars, dtype: int, br_a=None, br_b=None, v=None, stream=None):
+    """pasur_exploitability: fgts are consecutive rounds ending at round 5,
+    sigma_bars[r][l] (l = 1..8) device tensors of their average strategies;
+    br_a, br_b, v: device double tensors of fgts[0]'s root count (None: not
+    computed)."""
+    n = len(fgts)
+    hs = (C.c_void_p * n)(*[f.h for f in fgts])
+    sb = (C.c_void_p * (9 * n))()
+    for r in range(n):
+        for l in range(1, 9):
+            sb[9 * r + l] = _p(sigma_bars[r][l])
+    _check(lib().pasur_exploitability(hs, n, sb, dtype, _p(br_a), _p(br_b), _p(v),
+                                      _stream(stream)), "pasur_exploitability")
 
 
 class Plan:

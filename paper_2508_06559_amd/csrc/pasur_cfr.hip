@@ -978,9 +978,12 @@ int plan_build(pasur_plan *pl, const pasur_fgt *const *fgts, const pasur_cfr_sta
   void *kern = pl->block == 256   ? seg_kernel<T, 256>(paper)
                : pl->block == 512 ? seg_kernel<T, 512>(paper)
                                   : seg_kernel<T, 1024>(paper);
+  // The attribute is a ceiling shared by every plan of this instance, so it
+  // is raised to the whole budget (plans may be launched in any order); each
+  // launch still asks for its own lds_bytes.
   PASUR_TRY_HIP(hipFuncSetAttribute((const void *)kern,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)pl->lds_bytes));
+                                    (int)(kLdsPerWorkgroup - kStaticLds)));
   return PASUR_OK;
 }
 
@@ -1350,6 +1353,101 @@ extern "C" int pasur_tree_values(const pasur_fgt *f, const double *d_leaf, int d
   hipStream_t s = (hipStream_t)stream;
   return dtype == PASUR_F32 ? values_t<float, double>(f, d_leaf, sigma, mode, d_out, s)
                             : values_t<double, double>(f, d_leaf, sigma, mode, d_out, s);
+}
+
+namespace {
+
+int check_exploitability(const pasur_fgt *const *fgts, int n_rounds, void *const *sigma_bar,
+                         int dtype, const double *d_br_a, const double *d_br_b,
+                         const double *d_v) {
+  if (!fgts || !sigma_bar) {
+    set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  if (!d_br_a && !d_br_b && !d_v) {
+    set_error("no output requested");
+    return PASUR_E_INVAL;
+  }
+  if (n_rounds < 1 || n_rounds > 6) {
+    set_error("n_rounds %d outside 1..6", n_rounds);
+    return PASUR_E_RANGE;
+  }
+  if (dtype != PASUR_F32 && dtype != PASUR_F64) {
+    set_error("unknown dtype %d", dtype);
+    return PASUR_E_RANGE;
+  }
+  for (int r = 0; r < n_rounds; ++r) {
+    const pasur_fgt *f = fgts[r];
+    if (!f) {
+      set_error("fgts[%d] is NULL", r);
+      return PASUR_E_INVAL;
+    }
+    if (f->n[0] < 1) {
+      set_error("fgts[%d] has no roots", r);
+      return PASUR_E_INVAL;
+    }
+    if (r > 0 && (f->round != fgts[r - 1]->round + 1 || f->n[0] != fgts[r - 1]->n_next)) {
+      set_error("fgts[%d] is not the unfolding of fgts[%d]'s next-round roots", r, r - 1);
+      return PASUR_E_INVAL;
+    }
+    for (int l = 1; l <= 8; ++l)
+      if (!sigma_bar[r * 9 + l]) {
+        set_error("sigma_bar[%d*9+%d] is NULL", r, l);
+        return PASUR_E_INVAL;
+      }
+  }
+  if (fgts[n_rounds - 1]->round != 5) {
+    set_error("the last tree must be round 5 (the hand's last round)");
+    return PASUR_E_INVAL;
+  }
+  return PASUR_OK;
+}
+
+// One mode over all rounds, last first: each round's leaves are its round
+// points plus the next round's value of the same mode at the linked root.
+int composed_values(const pasur_fgt *const *fgts, int n_rounds, void *const *sigma_bar,
+                    int dtype, int mode, double *out, hipStream_t s) {
+  double *V = nullptr;  // the later round's root values
+  for (int r = n_rounds - 1; r >= 0; --r) {
+    const pasur_fgt *f = fgts[r];
+    double *leaf = nullptr, *res = out;
+    hipError_t e = hipMallocAsync((void **)&leaf, f->n[8] * sizeof(double), s);
+    if (e == hipSuccess && r > 0) e = hipMallocAsync((void **)&res, f->n[0] * sizeof(double), s);
+    int st = PASUR_OK;
+    if (e != hipSuccess) {
+      set_error("hipMallocAsync: %s", hipGetErrorString(e));
+      st = PASUR_E_NOMEM;
+    } else {
+      k_leaf_util<double><<<grid_for(f->n[8]), kThreads, 0, s>>>(f->n[8], f->leaf_base, f->link,
+                                                                 V, leaf);
+      st = dtype == PASUR_F32
+               ? values_t<float, double>(f, leaf, sigma_bar + r * 9, mode, res, s)
+               : values_t<double, double>(f, leaf, sigma_bar + r * 9, mode, res, s);
+    }
+    if (leaf) (void)hipFreeAsync(leaf, s);
+    if (V) (void)hipFreeAsync(V, s);
+    V = r > 0 ? res : nullptr;
+    if (st != PASUR_OK) {
+      if (V && V != out) (void)hipFreeAsync(V, s);
+      return st;
+    }
+  }
+  return PASUR_OK;
+}
+
+}  // namespace
+
+extern "C" int pasur_exploitability(const pasur_fgt *const *fgts, int n_rounds,
+                                    void *const *sigma_bar, int dtype, double *d_br_a,
+                                    double *d_br_b, double *d_v, void *stream) {
+  PASUR_TRY(check_exploitability(fgts, n_rounds, sigma_bar, dtype, d_br_a, d_br_b, d_v));
+  hipStream_t s = (hipStream_t)stream;
+  double *outs[3] = {d_br_a, d_br_b, d_v};
+  const int modes[3] = {PASUR_TV_BR_A, PASUR_TV_BR_B, PASUR_TV_EXPECT};
+  for (int m = 0; m < 3; ++m)
+    if (outs[m]) PASUR_TRY(composed_values(fgts, n_rounds, sigma_bar, dtype, modes[m], outs[m], s));
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
 }
 
 extern "C" int pasur_tree_values_noalloc(const pasur_fgt *f, const double *d_leaf, int dtype,

@@ -12,11 +12,10 @@ from __future__ import annotations
 from dataclasses import dataclass
 from typing import List, Optional
 
-from . import (PASUR_F32, PASUR_F64, PLAY_SIGMA_BAR, RM_FLOOR, TV_BR_A, TV_BR_B, TV_EXPECT,
-               V_ITERATE_MEAN, V_SIGMA_BAR, ES_FRONTIER, CfrState, es_iterate, selfplay,
-               Plan, UnfoldedTree, average_strategy, build_round_tree, cfr_init, cfr_iterate,
-               leaf_utilities, paper_params, round_values, roots_to_device, tree_values,
-               unfold_scores, _torch)
+from . import (PASUR_F32, PASUR_F64, PLAY_SIGMA_BAR, RM_FLOOR, V_ITERATE_MEAN, V_SIGMA_BAR,
+               ES_FRONTIER, CfrState, es_iterate, exploitability, selfplay, Plan, UnfoldedTree,
+               average_strategy, build_round_tree, cfr_init, cfr_iterate, leaf_utilities,
+               paper_params, round_values, roots_to_device, unfold_scores, _torch)
 
 
 @dataclass
@@ -107,21 +106,15 @@ class SubgameSolver:
 
     def exploitability(self):
         """Composed best responses of both players against the average
-        strategies of every round; returns (BR_A, BR_B, v) at the start
-        round's roots as device double tensors.  Exploitability (points per
-        game) is (BR_A - BR_B) / 2."""
+        strategies of every round (pasur_exploitability); returns (BR_A, BR_B,
+        v) at the start round's roots as device double tensors.
+        Exploitability (points per game) is (BR_A - BR_B) / 2."""
         torch = self.torch
-        out = {}
-        for mode in (TV_BR_A, TV_BR_B, TV_EXPECT):
-            V = None
-            for rr in reversed(self.rounds):
-                leaf = torch.empty(rr.fgt.n[8], dtype=torch.float64, device="cuda")
-                leaf_utilities(rr.fgt, V, PASUR_F64, leaf, self.stream)
-                res = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
-                tree_values(rr.fgt, leaf, self.dtype, rr.state.sigma_bar, mode, res, self.stream)
-                V = res
-            out[mode] = V
-        return out[TV_BR_A], out[TV_BR_B], out[TV_EXPECT]
+        n0 = self.rounds[0].fgt.n[0]
+        out = [torch.empty(n0, dtype=torch.float64, device="cuda") for _ in range(3)]
+        exploitability([rr.fgt for rr in self.rounds], [rr.state.sigma_bar for rr in self.rounds],
+                       self.dtype, out[0], out[1], out[2], self.stream)
+        return tuple(out)
 
     def selfplay(self, n_games: int, seed: int, policy_a: int = PLAY_SIGMA_BAR,
                  policy_b: int = PLAY_SIGMA_BAR, root: int = 0, strategies=None):

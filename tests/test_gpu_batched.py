@@ -84,3 +84,62 @@ def test_plan_rejects_bad_ranges():
     with pytest.raises(pa.PasurError, match="dtype"):
         pa.Plan([st, st64], t_first=1, t_last=10)
     p.free()
+
+
+def test_batched_fp64_matches_oracle():
+    # every deal of an FP64 batched solve against the oracle's solve of that
+    # deal alone: state, average strategies and round values within 1e-9
+    pa = require_gpu()
+    import torch
+    import oracle
+    from gpu_common import oracle_rounds, oracle_solve
+    seeds = [1, 3, 13]
+    probs = problems(seeds)
+    print(f"[batched] FP64 vs oracle, deals {seeds}, 300 iterations", flush=True)
+    b = pa.BatchSolver(probs, 4, 300, dtype=pa.PASUR_F64)
+    b.solve()
+    torch.cuda.synchronize()
+    for seed, (deck, roots), sv in zip(seeds, probs, b.deals):
+        res = oracle_solve(oracle_rounds(deck, 4, roots), 300)
+        for k, rr in enumerate(sv.rounds):
+            c, leaf, V = res[k]
+            st = rr.state
+            assert np.array_equal(to_np(st.u[8]), leaf), (seed, k)
+            for l in range(1, 9):
+                for name, mine, field in (("sigma", st.sigma, oracle.CF_SIGMA),
+                                          ("R", st.R, oracle.CF_R),
+                                          ("Sbar", st.Sbar, oracle.CF_SBAR),
+                                          ("sigma_bar", st.sigma_bar, oracle.CF_SIGMA_BAR)):
+                    np.testing.assert_allclose(to_np(mine[l]), c.get(field, l), rtol=0, atol=1e-9,
+                                               err_msg=f"deal {seed} round {k + 5} {name} {l}")
+            for l in range(8):
+                np.testing.assert_allclose(to_np(st.u[l]), c.get(oracle.CF_U, l), rtol=0, atol=1e-9)
+            np.testing.assert_allclose(to_np(rr.V), V, rtol=0, atol=1e-9)
+    b.free()
+
+
+def test_plans_launch_in_any_order():
+    # A plan with a larger LDS footprint, created before one with a smaller
+    # footprint, must still launch (the dynamic-LDS ceiling is not the last
+    # plan's), and give the same state as when built alone.
+    pa = require_gpu()
+    import torch
+    deck, roots = synth.two_round_root(1)
+    big = pa.SubgameSolver(deck, 4, roots, dtype=pa.PASUR_F32).rounds[1]
+    sdeck, sroots = synth.last_round_roots(3)
+    small = pa.SubgameSolver(sdeck, 5, sroots, dtype=pa.PASUR_F32).rounds[0]
+    outs = []
+    for with_small in (False, True):
+        st = pa.CfrState(big.fgt, pa.PASUR_F32)
+        pa.leaf_utilities(big.fgt, None, pa.PASUR_F32, st.u[8])
+        pa.cfr_init(st)
+        pa_big = pa.Plan([st], t_first=1, t_last=50)
+        if with_small:
+            st2 = pa.CfrState(small.fgt, pa.PASUR_F32)
+            pa_small = pa.Plan([st2], t_first=1, t_last=50)
+            assert pa_small.lds_bytes < pa_big.lds_bytes
+        pa_big.iterate(1, 50)
+        torch.cuda.synchronize()
+        outs.append([to_np(t).copy() for t in st.sigma[1:] + st.R[1:] + st.Sbar[1:]])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)

@@ -282,3 +282,38 @@ def test_schedules_are_bit_identical(dtype_name):
     for k in range(2, len(results)):
         for a, b in zip(results[k], ref[k % 2]):
             assert np.array_equal(a, b)
+
+
+def test_exploitability_entry_point():
+    # pasur_exploitability against the oracle's composition, with outputs
+    # requested one at a time, and its consistency checks on real trees
+    pa = require_gpu()
+    import torch
+    deck, roots = synth.two_round_root(3)
+    s = gpu_solver(pa, deck, 4, roots, pa.PASUR_F32, 300)
+    rounds = oracle_rounds(deck, 4, roots)
+    sb = [[np.ones(1)] + [to_np(t).astype(np.float64) for t in rr.state.sigma_bar[1:]]
+          for rr in s.rounds]
+    ref = oracle_exploitability(rounds, sb)
+    fg = [rr.fgt for rr in s.rounds]
+    sbs = [rr.state.sigma_bar for rr in s.rounds]
+    n0 = fg[0].n[0]
+    for i in range(3):
+        outs = [None, None, None]
+        outs[i] = torch.full((n0,), float("nan"), dtype=torch.float64, device="cuda")
+        pa.exploitability(fg, sbs, pa.PASUR_F32, *outs)
+        torch.cuda.synchronize()
+        assert max_diff(to_np(outs[i]), ref[i]) <= TOL64, i
+    assert np.all(ref[0] >= ref[1])
+    out = torch.empty(n0, dtype=torch.float64, device="cuda")
+    with pytest.raises(pa.PasurError, match="round 5"):
+        pa.exploitability(fg[:1], sbs[:1], pa.PASUR_F32, out)
+    with pytest.raises(pa.PasurError, match="not the unfolding"):
+        pa.exploitability(fg[::-1], sbs[::-1], pa.PASUR_F32, out)
+    d2, r2 = synth.two_round_root(1)
+    s2 = pa.SubgameSolver(d2, 4, r2, dtype=pa.PASUR_F32)
+    if s2.rounds[1].fgt.n[0] != fg[1].n[0]:
+        with pytest.raises(pa.PasurError, match="not the unfolding"):
+            pa.exploitability([fg[0], s2.rounds[1].fgt], sbs, pa.PASUR_F32, out)
+    s2.free()
+    s.free()
