@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpasur.so")
 SOURCES = ["pasur_util.hip", "pasur_tree.hip", "pasur_cfr.hip", "pasur_mlp.hip", "pasur_play.hip",
-           "pasur_es.hip", "pasur_infoset.hip", "pasur_sweep.hip"]
+           "pasur_es.hip", "pasur_infoset.hip", "pasur_sweep.hip", "pasur_sort.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -55,6 +55,13 @@ void dev_free(T *&p) {
 int scan_counts(const int32_t *d_counts, int64_t n, int32_t *d_out,
                 int64_t *total, hipStream_t stream);
 
+// Stable LSD radix sort of (key, value) pairs by key; every key bit at or
+// above end_bit must be zero.  The result is in keys_out/vals_out, and
+// keys/vals are overwritten.  Synchronises `stream`.
+template <class K>
+int radix_sort_pairs(K *keys, K *keys_out, int32_t *vals, int32_t *vals_out, int64_t n,
+                     int end_bit, hipStream_t stream);
+
 // Bit masks over the 52 card indices.
 constexpr uint64_t kNumericMask = (1ull << 40) - 1;       // A..10, 40 cards
 constexpr uint64_t kJackMask = 0xFull << 40;

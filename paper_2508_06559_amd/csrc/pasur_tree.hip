@@ -5,7 +5,6 @@
 // parent, so children land parent-major in canonical order without atomics.
 #include "pasur_internal.hpp"
 
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstdlib>
@@ -635,26 +634,6 @@ __global__ void k_next_roots(int64_t n, const uint64_t *__restrict__ keys,
   next[u] = r;
 }
 
-// Inclusive positions from an exclusive scan: pos[k+1]-1 is the id of k.
-template <class KeyT>
-int sort_pairs(KeyT *keys_in, KeyT *keys_out, int32_t *vals_in, int32_t *vals_out, int64_t n,
-               int end_bit, hipStream_t stream) {
-  size_t tmp_bytes = 0;
-  PASUR_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys_in, keys_out, vals_in,
-                                                   vals_out, (int)n, 0, end_bit, stream));
-  void *tmp = nullptr;
-  PASUR_TRY_HIP(hipMalloc(&tmp, tmp_bytes ? tmp_bytes : 1));
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys_in, keys_out, vals_in,
-                                                    vals_out, (int)n, 0, end_bit, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  (void)hipFree(tmp);
-  if (e != hipSuccess) {
-    set_error("radix sort: %s", hipGetErrorString(e));
-    return PASUR_E_HIP;
-  }
-  return PASUR_OK;
-}
-
 __global__ void k_iota(int64_t n, int32_t *v) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) v[j] = (int32_t)j;
@@ -710,7 +689,7 @@ int unfold_impl(const pasur_gt *gt, const pasur_root *d_roots, int64_t n_roots, 
   PASUR_TRY(s.alloc(&pos, n_roots + 1));
   k_root_keys<<<grid_for(n_roots), kThreads, 0, stream>>>(n_roots, d_roots, keys);
   k_iota<<<grid_for(n_roots), kThreads, 0, stream>>>(n_roots, iv);
-  PASUR_TRY(sort_pairs<uint32_t>(keys, keys_sorted, iv, iv2, n_roots, 16, stream));
+  PASUR_TRY(radix_sort_pairs<uint32_t>(keys, keys_sorted, iv, iv2, n_roots, 16, stream));
   k_key_flags<<<grid_for(n_roots), kThreads, 0, stream>>>(n_roots, keys_sorted, flags);
   int64_t ns = 0;
   PASUR_TRY(scan_counts(flags, n_roots, pos, &ns, stream));
@@ -815,7 +794,7 @@ int unfold_impl(const pasur_gt *gt, const pasur_root *d_roots, int64_t n_roots, 
   PASUR_TRY_HIP(hipGetLastError());
   if (r < 5) {
     const int nbits = __builtin_popcountll(dealt) + 16;
-    PASUR_TRY(sort_pairs<uint64_t>(lkeys, lkeys2, lidx, lidx2, nl, nbits, stream));
+    PASUR_TRY(radix_sort_pairs<uint64_t>(lkeys, lkeys2, lidx, lidx2, nl, nbits, stream));
     int32_t *lflags = nullptr, *lpos = nullptr;
     PASUR_TRY(s.alloc(&lflags, nl));
     PASUR_TRY(s.alloc(&lpos, nl + 1));
