@@ -23,6 +23,8 @@ GT_POOL, GT_HANDS, GT_RS, GT_PARENT, GT_CHILD_BEGIN, GT_ACT_CARD, GT_ACT_CAP = r
 FGT_GT, FGT_SID, FGT_PARENT, FGT_CHILD_BEGIN, FGT_SCORE_TAB, FGT_NEXT_ROOTS, FGT_LINK = range(7)
 CF_SIGMA, CF_R, CF_SBAR, CF_U, CF_REACHA, CF_REACHB, CF_VACC, CF_SIGMA_BAR = range(8)
 TV_EXPECT, TV_BR_A, TV_BR_B, TV_MINIMAX = range(4)
+LITERAL_BONUS0 = 1  # leaf utilities: the printed final_util (-7 when nobody reached 7 clubs)
+SNIPPET_TOL, SNIPPET_AVG = 1, 2  # Params.flags: the executed forms of CodeSnippet FindUtility
 CFR_DCFR, CFR_PLUS, CFR_VANILLA = range(3)
 RM_FLOOR, RM_POSITIVE = range(2)
 
@@ -73,7 +75,7 @@ def lib():
         L.or_fgt_n_next.argtypes = [vp]
         L.or_fgt_copy.argtypes = [vp, i32, i32, vp]
         L.or_fgt_free.argtypes = [vp]
-        L.or_leaf_utilities.argtypes = [vp, vp, vp, vp]
+        L.or_leaf_utilities.argtypes = [vp, vp, vp, C.c_int, vp]
         L.or_cfr_create.restype = vp
         L.or_cfr_create.argtypes = [vp, vp, vp, C.POINTER(C.c_int)]
         L.or_cfr_run.argtypes = [vp, vp, i64, i32]
@@ -100,7 +102,8 @@ def _check(st: int, what: str):
 
 class _Params(C.Structure):
     _fields_ = [("variant", C.c_int), ("rm_mode", C.c_int), ("alpha", C.c_double),
-                ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double)]
+                ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double),
+                ("flags", C.c_int)]
 
 
 @dataclass
@@ -113,9 +116,11 @@ class Params:
     beta: float = 0.0
     gamma: float = 2.0
     eps: float = 1e-8
+    flags: int = 0  # SNIPPET_TOL | SNIPPET_AVG (DCFR only)
 
     def c(self):
-        return _Params(self.variant, self.rm_mode, self.alpha, self.beta, self.gamma, self.eps)
+        return _Params(self.variant, self.rm_mode, self.alpha, self.beta, self.gamma, self.eps,
+                       self.flags)
 
 
 def subset11_count():
@@ -230,11 +235,12 @@ class FGT:
     def child_begin(self) -> List[np.ndarray]:
         return [self.get(FGT_CHILD_BEGIN, l) for l in range(8)]
 
-    def leaf_utilities(self, V_next=None) -> np.ndarray:
+    def leaf_utilities(self, V_next=None, literal_bonus0: bool = False) -> np.ndarray:
         out = np.zeros(max(self.n[8], 1), np.float64)
         vn = None if V_next is None else np.ascontiguousarray(np.asarray(V_next, np.float64))
         _check(lib().or_leaf_utilities(self.gt.h, self.h, None if vn is None else _ptr(vn),
-                                       _ptr(out)), "leaf_utilities")
+                                       LITERAL_BONUS0 if literal_bonus0 else 0, _ptr(out)),
+               "leaf_utilities")
         return out[: self.n[8]]
 
 

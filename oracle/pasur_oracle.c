@@ -699,14 +699,16 @@ int or_fgt_copy(const or_fgt *f, int field, int level, void *dst) {
 /* ------------------------------------------------------------------------
  * Leaf utilities (equations final_util and passuputil), Alex's point
  * difference.  Final round: the 7-club bonus (+7 Alex, -7 Bob, 0 if nobody
- * reached 7 clubs) of the combined score plus the round's points.  Earlier
- * rounds: the value of the linked next-round root plus the round's points.
- * The inherited point difference is not part of the utility: points are
- * added round by round.
+ * reached 7 clubs; -7 there too with OR_LITERAL_BONUS0, the equation's
+ * printed 7(2(bonus mod 2) - 1)) of the combined score plus the round's
+ * points.  Earlier rounds: the value of the linked next-round root plus the
+ * round's points.  The inherited point difference is not part of the
+ * utility: points are added round by round.
  * ---------------------------------------------------------------------- */
-int or_leaf_utilities(const or_gt *g, const or_fgt *f, const double *V_next,
+int or_leaf_utilities(const or_gt *g, const or_fgt *f, const double *V_next, int flags,
                       double *leaf_u) {
-  if (!g || !f || !leaf_u) return OR_EINVAL;
+  if (!g || !f || !leaf_u || (flags & ~OR_LITERAL_BONUS0)) return OR_EINVAL;
+  double b0 = (flags & OR_LITERAL_BONUS0) ? -7.0 : 0.0;
   int last = (g->round == 5);
   if (!last && !V_next) return OR_EINVAL;
   for (int64_t i = 0; i < f->n[8]; i++) {
@@ -716,7 +718,7 @@ int or_leaf_utilities(const or_gt *g, const or_fgt *f, const double *V_next,
     if (last) {
       int8_t nxt[4];
       or_combine_score(f->score_tab + 4 * f->sid[8][i], rs, nxt);
-      double b = nxt[3] == 1 ? 7.0 : (nxt[3] == 2 ? -7.0 : 0.0);
+      double b = nxt[3] == 1 ? 7.0 : (nxt[3] == 2 ? -7.0 : b0);
       leaf_u[i] = b + pts;
     } else {
       leaf_u[i] = V_next[f->link[i]] + pts;
@@ -824,6 +826,10 @@ static double o_dcfr_factor(double t_minus_1, double expo) {
 
 int or_cfr_run(or_cfr *c, const or_params *p, int64_t t0, int n_iters) {
   if (!c || !p || t0 < 1 || n_iters < 0) return OR_EINVAL;
+  if ((p->flags & ~(OR_SNIPPET_TOL | OR_SNIPPET_AVG)) ||
+      (p->flags && p->variant != CFR_DCFR)) return OR_EINVAL;
+  int snip_tol = (p->flags & OR_SNIPPET_TOL) != 0;
+  int snip_avg = (p->flags & OR_SNIPPET_AVG) != 0;
   for (int64_t t = t0; t < t0 + n_iters; t++) {
     /* 1. reach probabilities, levels 1..7 (FindReachProbability) */
     for (int64_t j = 0; j < c->n[0]; j++) { c->reachA[0][j] = 1.0; c->reachB[0][j] = 1.0; }
@@ -842,7 +848,8 @@ int or_cfr_run(or_cfr *c, const or_params *p, int64_t t0, int n_iters) {
     }
     /* 2. utilities, regrets, regret matching, average (FindUtility) */
     double tm1 = (double)(t - 1);
-    double avg_w = pow(tm1 / (double)t, p->gamma);
+    double avg_w = snip_avg ? 1.0 - 1.0 / pow((double)t, p->gamma)
+                            : pow(tm1 / (double)t, p->gamma);
     for (int l = 8; l >= 1; l--) {
       int mover = (l - 1) % 2;
       double sgn = mover == 0 ? 1.0 : -1.0;
@@ -858,8 +865,8 @@ int or_cfr_run(or_cfr *c, const or_params *p, int64_t t0, int n_iters) {
           double r = sgn * opp * (c->u[l][q] - uh);
           double R = c->R[l][q];
           if (p->variant == CFR_DCFR) {
-            double d = R > 0.0 ? o_dcfr_factor(tm1, p->alpha)
-                               : o_dcfr_factor(tm1, p->beta);
+            int pos = snip_tol ? R >= 1e-5 : R > 0.0;
+            double d = pos ? o_dcfr_factor(tm1, p->alpha) : o_dcfr_factor(tm1, p->beta);
             R = d * R + r;
           } else if (p->variant == CFR_PLUS) {
             R = R + r;
@@ -884,6 +891,7 @@ int or_cfr_run(or_cfr *c, const or_params *p, int64_t t0, int n_iters) {
           else w = 1.0;
           double add = own * c->sigma[l][q];
           if (p->variant == CFR_PLUS) add *= (double)t; /* linear averaging */
+          if (snip_avg) add *= s_new;
           c->Sbar[l][q] = w * c->Sbar[l][q] + add;
           c->sigma[l][q] = s_new;
         }

@@ -86,15 +86,27 @@ int64_t or_fgt_n_scores(const or_fgt *f);
 int64_t or_fgt_n_next(const or_fgt *f);
 int or_fgt_copy(const or_fgt *f, int field, int level, void *dst);
 void or_fgt_free(or_fgt *f);
-int or_leaf_utilities(const or_gt *g, const or_fgt *f, const double *V_next,
+/* flags: OR_LITERAL_BONUS0 takes equation final_util as printed, which
+ * gives -7 (not 0) to a final score where nobody reached 7 clubs. */
+enum { OR_LITERAL_BONUS0 = 1 };
+int or_leaf_utilities(const or_gt *g, const or_fgt *f, const double *V_next, int flags,
                       double *leaf_u);
 
 /* ---- CFR on an unfolded round tree ----------------------------------- */
 enum { CFR_DCFR = 0, CFR_PLUS = 1, CFR_VANILLA = 2 };
 enum { RM_FLOOR = 0, RM_POSITIVE = 1 };
+/* flags (DCFR only), the executed forms of CodeSnippet FindUtility where it
+ * differs from the equations:
+ *   OR_SNIPPET_TOL: a regret counts as positive for the discount when
+ *     R >= 1e-5 (the snippet's TOL) instead of R > 0;
+ *   OR_SNIPPET_AVG: Sbar <- (1 - 1/t^gamma) Sbar + pi_p(h) sigma^t(a)
+ *     sigma^{t+1}(a), the snippet's weight and term (its reach already holds
+ *     sigma^t(a), and it multiplies by the freshly matched strategy). */
+enum { OR_SNIPPET_TOL = 1, OR_SNIPPET_AVG = 2 };
 typedef struct {
   int variant, rm_mode;
   double alpha, beta, gamma, eps;
+  int flags;
 } or_params;
 enum { CF_SIGMA, CF_R, CF_SBAR, CF_U, CF_REACHA, CF_REACHB, CF_VACC,
        CF_SIGMA_BAR };

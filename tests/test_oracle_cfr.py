@@ -325,3 +325,62 @@ def test_two_round_composition():
             assert ex <= prev + 1e-12
         prev = ex
     assert prev < 0.1
+
+
+def test_snippet_tol_flag_by_hand():
+    # OR_SNIPPET_TOL: the discount's sign test is R >= 1e-5 (the snippet's
+    # TOL) instead of R > 0.  The game of the hand-worked DCFR run with every
+    # leaf scaled by s = 2^-20, so every regret is below 1e-5: regret matching
+    # is scale-free, so sigma is as before, and the first discount that
+    # differs is at t=3 (alpha and beta discounts are both 1/2 at t=2), where
+    # the positive regrets (1/2 s, 1/2 s, 1/4 s) are halved instead of
+    # multiplied by c = 2^1.5/(2^1.5+1); no new regret is added to them there.
+    s = 2.0 ** -20
+    n, cb, leaves = padded_tree([2, 2], [3 * s, -1 * s, 0, 2 * s])
+    cc = 2 ** 1.5 / (2 ** 1.5 + 1)
+    plain = oracle.CFR(n, cb, leaves)
+    plain.run(3, oracle.Params(rm_mode=oracle.RM_POSITIVE))
+    np.testing.assert_allclose(plain.get(oracle.CF_R, 1), [-1.25 * s, cc / 2 * s], rtol=1e-14, atol=0)
+    c = oracle.CFR(n, cb, leaves)
+    c.run(3, oracle.Params(rm_mode=oracle.RM_POSITIVE, flags=oracle.SNIPPET_TOL))
+    np.testing.assert_allclose(c.get(oracle.CF_R, 1), [-1.25 * s, 0.25 * s], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(c.get(oracle.CF_R, 2), [-1.25 * s, 0.25 * s, 0.125 * s, -2.625 * s],
+                               rtol=1e-14, atol=0)
+    np.testing.assert_array_equal(c.get(oracle.CF_SIGMA, 1), plain.get(oracle.CF_SIGMA, 1))
+    # unscaled, every positive regret is far above 1e-5: the flag changes nothing
+    n, cb, leaves = padded_tree([2, 2], [3, -1, 0, 2])
+    a, b = oracle.CFR(n, cb, leaves), oracle.CFR(n, cb, leaves)
+    a.run(3, oracle.Params(rm_mode=oracle.RM_POSITIVE))
+    b.run(3, oracle.Params(rm_mode=oracle.RM_POSITIVE, flags=oracle.SNIPPET_TOL))
+    for l in (1, 2):
+        np.testing.assert_array_equal(a.get(oracle.CF_R, l), b.get(oracle.CF_R, l))
+
+
+def test_snippet_avg_flag_by_hand():
+    # OR_SNIPPET_AVG: Sbar <- (1 - 1/t^2) Sbar + pi_p sigma^t sigma^{t+1}.
+    # Same game and regrets as the hand-worked DCFR run, so the strategies
+    # are sigma^1 uniform, sigma^2 = root (1/2,1/2), a1:b (0,1), a2:b (1,0),
+    # sigma^3 = sigma^4 = root (0,1), a1:b (0,1), a2:b (1,0); weights 0, 3/4,
+    # 8/9; both movers' own reach at their nodes is 1:
+    #   root: t=1 (1/4,1/4); t=2 (3/16, 3/16+1/2); t=3 (1/6, 11/18+1)
+    #         -> average (3/32, 29/32)
+    #   a1:b: t=1 (0, 1/2 * 1); t=2 (0, 3/8+1); t=3 (0, 11/9+1);  a2:b mirrored.
+    n, cb, leaves = padded_tree([2, 2], [3, -1, 0, 2])
+    c = oracle.CFR(n, cb, leaves)
+    c.run(3, oracle.Params(rm_mode=oracle.RM_POSITIVE, flags=oracle.SNIPPET_AVG))
+    np.testing.assert_allclose(c.get(oracle.CF_SBAR, 1), [1 / 6, 29 / 18], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SBAR, 2), [0, 20 / 9, 20 / 9, 0], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA_BAR, 1), [3 / 32, 29 / 32], atol=1e-14)
+    np.testing.assert_allclose(c.get(oracle.CF_SIGMA_BAR, 2), [0, 1, 1, 0], atol=1e-14)
+    # the averaging does not feed back: regrets equal the plain run's
+    cc = 2 ** 1.5 / (2 ** 1.5 + 1)
+    np.testing.assert_allclose(c.get(oracle.CF_R, 2), [-1.25, cc / 2, cc / 4, -2.625], atol=1e-14)
+
+
+def test_snippet_flags_need_dcfr():
+    n, cb, leaves = padded_tree([2, 2], [3, -1, 0, 2])
+    c = oracle.CFR(n, cb, leaves)
+    with pytest.raises(oracle.OracleError):
+        c.run(1, oracle.Params(variant=oracle.CFR_PLUS, flags=oracle.SNIPPET_AVG))
+    with pytest.raises(oracle.OracleError):
+        c.run(1, oracle.Params(flags=8))

@@ -324,3 +324,33 @@ def test_deck9_first_turn_support(golden_dir):
         bob_best = min(v2[q] for q in kids)
         for q in kids:
             assert (v2[q] == bob_best) == (replies[(a2[q], c2[q])] > 0), (c, a2[q])
+
+
+def test_literal_bonus0_flag():
+    # Equation final_util as printed gives 7(2(bonus mod 2) - 1): -7 also for
+    # bonus 0 (nobody reached 7 clubs).  A last round with no club among the
+    # pool and the eight hand cards cannot award the bonus, so every leaf of
+    # a root with no bonus yet ends at bonus 0: the printed form lowers its
+    # utility by exactly 7; a root whose bonus Alex already holds keeps +7
+    # either way.
+    nonclubs = [c for c in range(52) if c % 4]
+    clubs = [c for c in range(52) if c % 4 == 0]
+    deck = nonclubs[:4] + clubs + nonclubs[4:]
+    assert all(c % 4 for c in deck[44:])
+    pool = synth.mask_of(deck[:4])
+    roots = [synth.Root(pool, 0, 0, 0, 0), synth.Root(pool, 0, 0, 0, 1)]
+    gt = oracle.GT(deck, 5, [pool])
+    f = oracle.FGT(gt, roots)
+    plain = f.leaf_utilities()
+    literal = f.leaf_utilities(literal_bonus0=True)
+    # the two roots' leaves: root k's subtree through the level ranges
+    lo, hi = [0, 1], [1, 2]
+    for cb in f.child_begin():
+        lo = [int(cb[x]) for x in lo]
+        hi = [int(cb[x]) for x in hi]
+    assert hi[0] == lo[1] and hi[1] == f.n[8]
+    np.testing.assert_array_equal(literal[:hi[0]] - plain[:hi[0]], -7.0)
+    np.testing.assert_array_equal(literal[lo[1]:], plain[lo[1]:])
+    # with the bonus held, every leaf is +7 plus the round's points, and the
+    # same round points sit under the bonus-0 root
+    np.testing.assert_array_equal(plain[lo[1]:] - 7.0, plain[:hi[0]])
