@@ -137,12 +137,16 @@ void pasur_fgt_free(pasur_fgt *fgt);
 /* ---- a4: leaf utilities -----------------------------------------------------
  * Equations final_util and passuputil: Alex's point difference at every FGT
  * leaf.  Round 5: bonus (+7 Alex, -7 Bob, 0 none) of the combined score plus
- * the round's points (Apt + 5 Asr) - (Bpt + 5 Bsr).  Rounds 0..4:
+ * the round's points (Apt + 5 Asr) - (Bpt + 5 Bsr); with
+ * PASUR_LEAF_LITERAL_BONUS0 in `flags`, equation final_util as printed,
+ * 7 (2 (bonus mod 2) - 1), which gives -7 for "none" too.  Rounds 0..4:
  * d_V_next[link] + the round's points, with d_V_next (device, double, one
  * value per next-round root) the next round's root values.  Writes n[8]
- * values of type `dtype` to d_leaf (device). */
-int pasur_leaf_utilities(const pasur_fgt *fgt, const double *d_V_next,
-                         int dtype, void *d_leaf, void *stream);
+ * values of type `dtype` to d_leaf (device).  Unknown flag bits are
+ * PASUR_E_RANGE. */
+enum { PASUR_LEAF_LITERAL_BONUS0 = 1 };
+int pasur_leaf_utilities(const pasur_fgt *fgt, const double *d_V_next, int dtype, int flags,
+                         void *d_leaf, void *stream);
 
 /* ---- a5..a10: DCFR on one round ---------------------------------------------
  * Section "CFR Algorithm" (CodeSnippets CFR, FindReachProbability,
@@ -197,7 +201,17 @@ typedef struct {
                    256, 512 or 1024 */
   int seg_nodes; /* persistent schedule: a workgroup takes a run of consecutive
                     roots of up to seg_nodes nodes (0: one root each) */
+  int flags;     /* pasur_cfr_flags, 0 for the equations' DCFR */
 } pasur_cfr_params;
+/* The executed forms of CodeSnippet FindUtility where they differ from the
+ * equations (DCFR only; honoured by PASUR_SCHED_LEVEL_SYNC, which AUTO picks
+ * when any is set; the other schedules and plans reject them):
+ *   SNIPPET_TOL: a regret is discounted as positive when R >= 1e-5 (the
+ *     snippet's TOL) rather than R > 0;
+ *   SNIPPET_AVG: Sbar <- (1 - 1/t^gamma) Sbar + pi_p(h) sigma^t(a)
+ *     sigma^{t+1}(a): the snippet's weight, and its term, whose reach holds
+ *     sigma^t(a) and which multiplies by the newly matched strategy. */
+typedef enum { PASUR_CFR_SNIPPET_TOL = 1, PASUR_CFR_SNIPPET_AVG = 2 } pasur_cfr_flags;
 
 /* R = 0, Sbar = 0, sigma uniform over every node's children, vacc = 0. */
 int pasur_cfr_init(const pasur_fgt *fgt, const pasur_cfr_state *st, void *stream);
@@ -267,15 +281,16 @@ int pasur_tree_values(const pasur_fgt *fgt, const double *d_leaf, int dtype,
  *   d_br_b[k]: Alex's value when Bob best-responds to Alex's sigma_bar,
  *   d_v[k]:    Alex's value when both play sigma_bar.
  * Each round's leaf value is its round points plus the later round's value
- * of the same kind at the linked root.  Any output may be NULL (not
+ * of the same kind at the linked root (last round: as pasur_leaf_utilities
+ * with `leaf_flags`).  Any output may be NULL (not
  * computed), not all three.  Exploitability in points per game is
  * (br_a - br_b) / 2 >= 0.  Asynchronous on `stream`; uses stream-ordered
  * scratch (a level of each round, its leaves and its roots, in double).
  * PASUR_E_INVAL for null or inconsistent trees, PASUR_E_RANGE for n_rounds
  * outside 1..6 or an unknown dtype. */
 int pasur_exploitability(const pasur_fgt *const *fgts, int n_rounds, void *const *sigma_bar,
-                         int dtype, double *d_br_a, double *d_br_b, double *d_v,
-                         void *stream);
+                         int dtype, int leaf_flags, double *d_br_a, double *d_br_b,
+                         double *d_v, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

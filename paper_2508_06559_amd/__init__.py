@@ -39,14 +39,21 @@ SCHED_ROOT, SCHED_LEVEL_SYNC, SCHED_ROOT_GLOBAL, SCHED_STREAM, SCHED_AUTO = 0, 1
 class CfrParams(C.Structure):
     _fields_ = [("variant", C.c_int), ("rm_mode", C.c_int), ("alpha", C.c_double),
                 ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double),
-                ("schedule", C.c_int), ("block", C.c_int), ("seg_nodes", C.c_int)]
+                ("schedule", C.c_int), ("block", C.c_int), ("seg_nodes", C.c_int),
+                ("flags", C.c_int)]
 
 
-def paper_params(schedule: int = SCHED_AUTO, block: int = 0, seg_nodes: int = 0) -> CfrParams:
+SNIPPET_TOL, SNIPPET_AVG = 1, 2  # CfrParams.flags (pasur_cfr_flags)
+LEAF_LITERAL_BONUS0 = 1          # leaf-utility flags
+
+
+def paper_params(schedule: int = SCHED_AUTO, block: int = 0, seg_nodes: int = 0,
+                 flags: int = 0) -> CfrParams:
     """DCFR with the paper's constants (alpha 1.5, beta 0, gamma 2) and its
     regret-matching floor (1e-8); by default the library picks the schedule
-    per round (persistent segments, or streaming sweeps for large rounds)."""
-    return CfrParams(DCFR, RM_FLOOR, 1.5, 0.0, 2.0, 1e-8, schedule, block, seg_nodes)
+    per round (persistent segments, or streaming sweeps for large rounds).
+    ``flags``: SNIPPET_TOL / SNIPPET_AVG, the snippet's executed forms."""
+    return CfrParams(DCFR, RM_FLOOR, 1.5, 0.0, 2.0, 1e-8, schedule, block, seg_nodes, flags)
 
 
 class _State(C.Structure):
@@ -79,14 +86,14 @@ def lib():
         L.pasur_fgt_next_roots.restype = vp
         L.pasur_fgt_free.argtypes = [vp]
         L.pasur_fgt_free.restype = None
-        L.pasur_leaf_utilities.argtypes = [vp, vp, i32, vp, vp]
+        L.pasur_leaf_utilities.argtypes = [vp, vp, i32, i32, vp, vp]
         L.pasur_cfr_init.argtypes = [vp, vp, vp]
         L.pasur_cfr_iterate.argtypes = [vp, vp, vp, i64, i32, vp]
         L.pasur_average_strategy.argtypes = [vp, vp, vp, vp]
         L.pasur_round_values.argtypes = [vp, vp, i32, i64, vp, vp, vp]
         L.pasur_tree_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.pasur_tree_values_noalloc.argtypes = [vp, vp, i32, vp, i32, vp, vp]
-        L.pasur_exploitability.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
+        L.pasur_exploitability.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp, vp]
         L.pasur_plan_create.argtypes = [vp, vp, i32, vp, i64, i64, C.POINTER(vp), vp]
         L.pasur_plan_iterate.argtypes = [vp, i64, i32, vp]
         L.pasur_plan_info.argtypes = [vp, vp]
@@ -299,9 +306,11 @@ class CfrState:
         return int(sum(t.numel() * t.element_size() for t in ts))
 
 
-def leaf_utilities(fgt: UnfoldedTree, d_V_next, dtype: int, d_out, stream=None):
+def leaf_utilities(fgt: UnfoldedTree, d_V_next, dtype: int, d_out, stream=None,
+                   literal_bonus0: bool = False):
     vp = None if d_V_next is None else _p(d_V_next)
-    _check(lib().pasur_leaf_utilities(fgt.h, vp, dtype, _p(d_out), _stream(stream)),
+    flags = LEAF_LITERAL_BONUS0 if literal_bonus0 else 0
+    _check(lib().pasur_leaf_utilities(fgt.h, vp, dtype, flags, _p(d_out), _stream(stream)),
            "pasur_leaf_utilities")
 
 
@@ -357,7 +366,8 @@ def tree_values_noalloc(fgt: UnfoldedTree, d_leaf, dtype: int, sigma: Optional[L
     return d_out
 
 
-def exploitability(fgts, sigma_bars, dtype: int, br_a=None, br_b=None, v=None, stream=None):
+def exploitability(fgts, sigma_bars, dtype: int, br_a=None, br_b=None, v=None, stream=None,
+                   literal_bonus0: bool = False):
     """pasur_exploitability: fgts are consecutive rounds ending at round 5,
     sigma_bars[r][l] (l = 1..8) device tensors of their average strategies;
     br_a, br_b, v: device double tensors of fgts[0]'s root count (None: not
@@ -368,7 +378,8 @@ def exploitability(fgts, sigma_bars, dtype: int, br_a=None, br_b=None, v=None, s
     for r in range(n):
         for l in range(1, 9):
             sb[9 * r + l] = _p(sigma_bars[r][l])
-    _check(lib().pasur_exploitability(hs, n, sb, dtype, _p(br_a), _p(br_b), _p(v),
+    flags = LEAF_LITERAL_BONUS0 if literal_bonus0 else 0
+    _check(lib().pasur_exploitability(hs, n, sb, dtype, flags, _p(br_a), _p(br_b), _p(v),
                                       _stream(stream)), "pasur_exploitability")
 
 

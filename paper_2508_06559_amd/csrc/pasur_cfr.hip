@@ -82,7 +82,9 @@ __global__ void k_down(int64_t n, int mover, const int32_t *__restrict__ parent,
 
 // FindUtility, one level, one thread per parent h (children cb[h]..cb[h+1]):
 //   u(h) = sum sigma^t u;  r = s_p pi_{-p}(h) (u(q) - u(h));
-//   R <- d R + r;  sigma^{t+1} = max(R, eps) / sum;  Sbar <- w Sbar + pi_p(h) sigma^t.
+//   R <- d R + r;  sigma^{t+1} = max(R, eps) / sum;  Sbar <- w Sbar + pi_p(h) sigma^t
+// (with PASUR_CFR_SNIPPET_AVG the term also carries sigma^{t+1}, as stored).
+constexpr double kSnippetTol = 1e-5;
 template <class T>
 __global__ void k_up(int64_t np, int mover, const int32_t *__restrict__ cb,
                      T *__restrict__ sigma, T *__restrict__ R, T *__restrict__ Sbar,
@@ -102,7 +104,8 @@ __global__ void k_up(int64_t np, int mover, const int32_t *__restrict__ cb,
     const double r = sgn * opp * ((double)u_child[q] - uh);
     double Rq = (double)R[q];
     if (ic.variant == PASUR_DCFR) {
-      const double d = Rq > 0.0 ? ic.dpos : ic.dneg;
+      const bool pos = (ic.flags & PASUR_CFR_SNIPPET_TOL) ? Rq >= kSnippetTol : Rq > 0.0;
+      const double d = pos ? ic.dpos : ic.dneg;
       Rq = d * Rq + r;
     } else if (ic.variant == PASUR_CFR_PLUS) {
       Rq = Rq + r;
@@ -125,6 +128,7 @@ __global__ void k_up(int64_t np, int mover, const int32_t *__restrict__ cb,
     const double s_new = sum > 0.0 ? x / sum : inv_k;
     double add = own * (double)sigma[q];
     if (ic.variant == PASUR_CFR_PLUS) add *= ic.avg_t;
+    if (ic.flags & PASUR_CFR_SNIPPET_AVG) add *= (double)(T)s_new;
     Sbar[q] = (T)(ic.avg_w * (double)Sbar[q] + add);
     sigma[q] = (T)s_new;
   }
@@ -721,10 +725,11 @@ __global__ void k_avg_strategy(int64_t np, const int32_t *__restrict__ cb,
 template <class T>
 __global__ void k_leaf_util(int64_t n, const int16_t *__restrict__ base,
                             const int32_t *__restrict__ link, const double *__restrict__ V,
-                            T *__restrict__ out) {
+                            const int8_t *__restrict__ bonus0_literal, T *__restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double pts = (double)base[i];
+  double pts = (double)base[i];
+  if (bonus0_literal && bonus0_literal[i] == 0) pts -= 7.0;
   out[i] = (T)(V ? V[link[i]] + pts : pts);
 }
 
@@ -1029,6 +1034,10 @@ extern "C" int pasur_plan_create(const pasur_fgt *const *fgts,
     set_error("plans use the persistent segment schedule");
     return PASUR_E_RANGE;
   }
+  if (p->flags) {
+    set_error("the snippet flags run on PASUR_SCHED_LEVEL_SYNC only, not in plans");
+    return PASUR_E_RANGE;
+  }
   const int dtype = states[0]->dtype;
   for (int i = 0; i < n_items; ++i) {
     if (!fgts[i] || !states[i]) {
@@ -1244,7 +1253,23 @@ extern "C" int pasur_cfr_iterate(const pasur_fgt *f, const pasur_cfr_state *st,
     set_error("unknown schedule or block size");
     return PASUR_E_RANGE;
   }
+  if (p->flags & ~(PASUR_CFR_SNIPPET_TOL | PASUR_CFR_SNIPPET_AVG)) {
+    set_error("unknown CFR flags %d", p->flags);
+    return PASUR_E_RANGE;
+  }
   hipStream_t s = (hipStream_t)stream;
+  if (p->flags) {
+    if (p->variant != PASUR_DCFR) {
+      set_error("the snippet flags apply to DCFR only");
+      return PASUR_E_RANGE;
+    }
+    if (p->schedule != PASUR_SCHED_LEVEL_SYNC && p->schedule != PASUR_SCHED_AUTO) {
+      set_error("the snippet flags run on PASUR_SCHED_LEVEL_SYNC (or AUTO) only");
+      return PASUR_E_RANGE;
+    }
+    return st->dtype == PASUR_F32 ? iterate_t<float>(f, st, p, t0, n_iters, s)
+                                  : iterate_t<double>(f, st, p, t0, n_iters, s);
+  }
   if (p->schedule == PASUR_SCHED_STREAM ||
       (p->schedule == PASUR_SCHED_AUTO && sweep_pays(f)))
     return sweep_iterate(const_cast<pasur_fgt *>(f), st, p, t0, n_iters, s);
@@ -1291,7 +1316,7 @@ extern "C" int pasur_average_strategy(const pasur_fgt *f, const pasur_cfr_state 
 }
 
 extern "C" int pasur_leaf_utilities(const pasur_fgt *f, const double *d_V_next, int dtype,
-                                    void *d_leaf, void *stream) {
+                                    int flags, void *d_leaf, void *stream) {
   if (!f || !d_leaf) {
     set_error("null argument");
     return PASUR_E_INVAL;
@@ -1300,18 +1325,23 @@ extern "C" int pasur_leaf_utilities(const pasur_fgt *f, const double *d_V_next, 
     set_error("unknown dtype %d", dtype);
     return PASUR_E_RANGE;
   }
+  if (flags & ~PASUR_LEAF_LITERAL_BONUS0) {
+    set_error("unknown leaf-utility flags %d", flags);
+    return PASUR_E_RANGE;
+  }
   if (f->round < 5 && !d_V_next) {
     set_error("rounds 0..4 need the next round's root values");
     return PASUR_E_INVAL;
   }
   const double *V = f->round < 5 ? d_V_next : nullptr;
+  const int8_t *b0 = f->round == 5 && (flags & PASUR_LEAF_LITERAL_BONUS0) ? f->leaf_bonus : nullptr;
   hipStream_t s = (hipStream_t)stream;
   if (dtype == PASUR_F32)
     k_leaf_util<float><<<grid_for(f->n[8]), kThreads, 0, s>>>(f->n[8], f->leaf_base, f->link, V,
-                                                              (float *)d_leaf);
+                                                              b0, (float *)d_leaf);
   else
     k_leaf_util<double><<<grid_for(f->n[8]), kThreads, 0, s>>>(f->n[8], f->leaf_base, f->link, V,
-                                                               (double *)d_leaf);
+                                                               b0, (double *)d_leaf);
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
 }
@@ -1358,7 +1388,7 @@ extern "C" int pasur_tree_values(const pasur_fgt *f, const double *d_leaf, int d
 namespace {
 
 int check_exploitability(const pasur_fgt *const *fgts, int n_rounds, void *const *sigma_bar,
-                         int dtype, const double *d_br_a, const double *d_br_b,
+                         int dtype, int leaf_flags, const double *d_br_a, const double *d_br_b,
                          const double *d_v) {
   if (!fgts || !sigma_bar) {
     set_error("null argument");
@@ -1374,6 +1404,10 @@ int check_exploitability(const pasur_fgt *const *fgts, int n_rounds, void *const
   }
   if (dtype != PASUR_F32 && dtype != PASUR_F64) {
     set_error("unknown dtype %d", dtype);
+    return PASUR_E_RANGE;
+  }
+  if (leaf_flags & ~PASUR_LEAF_LITERAL_BONUS0) {
+    set_error("unknown leaf-utility flags %d", leaf_flags);
     return PASUR_E_RANGE;
   }
   for (int r = 0; r < n_rounds; ++r) {
@@ -1406,7 +1440,7 @@ int check_exploitability(const pasur_fgt *const *fgts, int n_rounds, void *const
 // One mode over all rounds, last first: each round's leaves are its round
 // points plus the next round's value of the same mode at the linked root.
 int composed_values(const pasur_fgt *const *fgts, int n_rounds, void *const *sigma_bar,
-                    int dtype, int mode, double *out, hipStream_t s) {
+                    int dtype, int leaf_flags, int mode, double *out, hipStream_t s) {
   double *V = nullptr;  // the later round's root values
   for (int r = n_rounds - 1; r >= 0; --r) {
     const pasur_fgt *f = fgts[r];
@@ -1418,8 +1452,10 @@ int composed_values(const pasur_fgt *const *fgts, int n_rounds, void *const *sig
       set_error("hipMallocAsync: %s", hipGetErrorString(e));
       st = PASUR_E_NOMEM;
     } else {
+      const int8_t *b0 =
+          f->round == 5 && (leaf_flags & PASUR_LEAF_LITERAL_BONUS0) ? f->leaf_bonus : nullptr;
       k_leaf_util<double><<<grid_for(f->n[8]), kThreads, 0, s>>>(f->n[8], f->leaf_base, f->link,
-                                                                 V, leaf);
+                                                                 V, b0, leaf);
       st = dtype == PASUR_F32
                ? values_t<float, double>(f, leaf, sigma_bar + r * 9, mode, res, s)
                : values_t<double, double>(f, leaf, sigma_bar + r * 9, mode, res, s);
@@ -1438,14 +1474,16 @@ int composed_values(const pasur_fgt *const *fgts, int n_rounds, void *const *sig
 }  // namespace
 
 extern "C" int pasur_exploitability(const pasur_fgt *const *fgts, int n_rounds,
-                                    void *const *sigma_bar, int dtype, double *d_br_a,
-                                    double *d_br_b, double *d_v, void *stream) {
-  PASUR_TRY(check_exploitability(fgts, n_rounds, sigma_bar, dtype, d_br_a, d_br_b, d_v));
+                                    void *const *sigma_bar, int dtype, int leaf_flags,
+                                    double *d_br_a, double *d_br_b, double *d_v, void *stream) {
+  PASUR_TRY(check_exploitability(fgts, n_rounds, sigma_bar, dtype, leaf_flags, d_br_a, d_br_b,
+                                 d_v));
   hipStream_t s = (hipStream_t)stream;
   double *outs[3] = {d_br_a, d_br_b, d_v};
   const int modes[3] = {PASUR_TV_BR_A, PASUR_TV_BR_B, PASUR_TV_EXPECT};
   for (int m = 0; m < 3; ++m)
-    if (outs[m]) PASUR_TRY(composed_values(fgts, n_rounds, sigma_bar, dtype, modes[m], outs[m], s));
+    if (outs[m])
+      PASUR_TRY(composed_values(fgts, n_rounds, sigma_bar, dtype, leaf_flags, modes[m], outs[m], s));
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
 }

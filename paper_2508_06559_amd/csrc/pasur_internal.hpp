@@ -131,6 +131,7 @@ struct IterConsts {
   double avg_t;       // multiplier of the new term (t for CFR+, else 1)
   double eps;
   int variant, rm_mode;
+  int flags;  // pasur_cfr_flags (DCFR only)
 };
 
 struct IterK {
@@ -144,11 +145,17 @@ inline IterConsts consts_for(const pasur_cfr_params *p, int64_t t) {
   double pb = std::pow(tm1, p->beta);
   ic.dpos = pa / (pa + 1.0);
   ic.dneg = pb / (pb + 1.0);
-  ic.avg_w = p->variant == PASUR_DCFR ? std::pow(tm1 / (double)t, p->gamma) : 1.0;
+  if (p->variant != PASUR_DCFR)
+    ic.avg_w = 1.0;
+  else if (p->flags & PASUR_CFR_SNIPPET_AVG)
+    ic.avg_w = 1.0 - 1.0 / std::pow((double)t, p->gamma);
+  else
+    ic.avg_w = std::pow(tm1 / (double)t, p->gamma);
   ic.avg_t = (double)t;
   ic.eps = p->eps;
   ic.variant = p->variant;
   ic.rm_mode = p->rm_mode;
+  ic.flags = p->flags;
   return ic;
 }
 
@@ -282,6 +289,7 @@ struct pasur_fgt {
   pasur_root *next_roots;
   int32_t *link;
   int16_t *leaf_base;
+  int8_t *leaf_bonus;  // round 5: the final 7-club bonus state of each leaf
   // root_off[l][j] .. root_off[l][j+1]: level-l nodes of root j's subtree
   // (levels are root-major), on the device and copied to the host
   int64_t n_roots;

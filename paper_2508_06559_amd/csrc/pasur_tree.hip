@@ -578,7 +578,8 @@ __device__ inline void combine_score(const int8_t *s, uint64_t rs, int *ca, int 
 __global__ void k_leaf_pass(int64_t n, int round, const int32_t *__restrict__ f_gt,
                             const int32_t *__restrict__ f_sid, const int8_t *__restrict__ tab,
                             const uint64_t *__restrict__ gt_rs, const uint64_t *__restrict__ gt_pool,
-                            uint64_t dealt, int16_t *__restrict__ base, uint64_t *__restrict__ keys,
+                            uint64_t dealt, int16_t *__restrict__ base,
+                            int8_t *__restrict__ bonus_out, uint64_t *__restrict__ keys,
                             int32_t *__restrict__ idx) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -587,6 +588,7 @@ __global__ void k_leaf_pass(int64_t n, int round, const int32_t *__restrict__ f_
   combine_score(tab + 4 * f_sid[i], gt_rs[t], &ca, &cb, &d, &bonus, &pts);
   if (round == 5) {
     base[i] = (int16_t)((bonus == 1 ? 7 : (bonus == 2 ? -7 : 0)) + pts);
+    bonus_out[i] = (int8_t)bonus;
     return;
   }
   base[i] = (int16_t)pts;
@@ -653,6 +655,7 @@ extern "C" void pasur_fgt_free(pasur_fgt *f) {
   dev_free(f->next_roots);
   dev_free(f->link);
   dev_free(f->leaf_base);
+  dev_free(f->leaf_bonus);
   for (int l = 0; l < 9; ++l) dev_free(f->root_off[l]);
   std::free(f->h_root_off);
   sweep_index_free(f->sweep);
@@ -772,6 +775,7 @@ int unfold_impl(const pasur_gt *gt, const pasur_root *d_roots, int64_t n_roots, 
   // --- leaves: base utilities and next-round linkage
   const int64_t nl = f->n[8];
   PASUR_TRY(dev_alloc(&f->leaf_base, nl));
+  if (gt->round == 5) PASUR_TRY(dev_alloc(&f->leaf_bonus, nl));
   uint64_t *lkeys = nullptr, *lkeys2 = nullptr;
   int32_t *lidx = nullptr, *lidx2 = nullptr;
   const int r = gt->round;
@@ -790,7 +794,7 @@ int unfold_impl(const pasur_gt *gt, const pasur_root *d_roots, int64_t n_roots, 
   }
   k_leaf_pass<<<grid_for(nl), kThreads, 0, stream>>>(nl, r, f->gt[8], f->sid[8], f->score_tab,
                                                      gt->rs[8], gt->pool[8], dealt, f->leaf_base,
-                                                     lkeys, lidx);
+                                                     f->leaf_bonus, lkeys, lidx);
   PASUR_TRY_HIP(hipGetLastError());
   if (r < 5) {
     const int nbits = __builtin_popcountll(dealt) + 16;

@@ -31,11 +31,12 @@ class SubgameSolver:
     """All rounds from ``start_round`` to 5 of one deal."""
 
     def __init__(self, deck, start_round: int, roots, dtype: int = PASUR_F32, stream=None,
-                 keep_gt: bool = False):
+                 keep_gt: bool = False, literal_bonus0: bool = False):
         torch = _torch()
         self.deck = list(int(c) for c in deck)
         self.start = start_round
         self.dtype = dtype
+        self.literal_bonus0 = literal_bonus0  # leaf utilities: the printed final_util
         self.stream = stream
         self.rounds: List[RoundResult] = []
         d_roots = roots_to_device(roots)
@@ -69,7 +70,7 @@ class SubgameSolver:
         for rr in reversed(self.rounds):
             st = rr.state if rr.state is not None else CfrState(rr.fgt, self.dtype)
             rr.state = st
-            leaf_utilities(rr.fgt, V, self.dtype, st.u[8], self.stream)
+            leaf_utilities(rr.fgt, V, self.dtype, st.u[8], self.stream, self.literal_bonus0)
             cfr_init(st, self.stream)
             if round_events is not None:
                 ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -95,7 +96,7 @@ class SubgameSolver:
         for rr in reversed(self.rounds):
             st = rr.state if rr.state is not None else CfrState(rr.fgt, self.dtype)
             rr.state = st
-            leaf_utilities(rr.fgt, V, self.dtype, st.u[8], self.stream)
+            leaf_utilities(rr.fgt, V, self.dtype, st.u[8], self.stream, self.literal_bonus0)
             cfr_init(st, self.stream)
             es_iterate(st, iters, seed, rm_mode, eps, schedule=schedule, stream=self.stream)
             average_strategy(st, self.stream)
@@ -113,7 +114,7 @@ class SubgameSolver:
         n0 = self.rounds[0].fgt.n[0]
         out = [torch.empty(n0, dtype=torch.float64, device="cuda") for _ in range(3)]
         exploitability([rr.fgt for rr in self.rounds], [rr.state.sigma_bar for rr in self.rounds],
-                       self.dtype, out[0], out[1], out[2], self.stream)
+                       self.dtype, out[0], out[1], out[2], self.stream, self.literal_bonus0)
         return tuple(out)
 
     def selfplay(self, n_games: int, seed: int, policy_a: int = PLAY_SIGMA_BAR,

@@ -194,13 +194,23 @@ def test_infoset_checks(lib):
 def test_exploitability_checks(lib):
     vp = C.c_void_p
     f = lib.pasur_exploitability
-    f.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp, vp, vp]
+    f.argtypes = [vp, C.c_int, vp, C.c_int, C.c_int, vp, vp, vp, vp]
     fg = (vp * 1)(None)
     sb = (vp * 9)(*([None] + [DUMMY.value] * 8))
-    expect(lib, f(None, 1, sb, 0, DUMMY, None, None, None), E_INVAL, ["null"])
-    expect(lib, f(fg, 1, None, 0, DUMMY, None, None, None), E_INVAL, ["null"])
-    expect(lib, f(fg, 1, sb, 0, None, None, None, None), E_INVAL, ["no output"])
-    expect(lib, f(fg, 0, sb, 0, DUMMY, None, None, None), E_RANGE, ["n_rounds 0"])
-    expect(lib, f(fg, 7, sb, 0, DUMMY, None, None, None), E_RANGE, ["n_rounds 7"])
-    expect(lib, f(fg, 1, sb, 9, None, DUMMY, None, None), E_RANGE, ["dtype 9"])
-    expect(lib, f(fg, 1, sb, 1, None, None, DUMMY, None), E_INVAL, ["fgts[0] is NULL"])
+    expect(lib, f(None, 1, sb, 0, 0, DUMMY, None, None, None), E_INVAL, ["null"])
+    expect(lib, f(fg, 1, None, 0, 0, DUMMY, None, None, None), E_INVAL, ["null"])
+    expect(lib, f(fg, 1, sb, 0, 0, None, None, None, None), E_INVAL, ["no output"])
+    expect(lib, f(fg, 0, sb, 0, 0, DUMMY, None, None, None), E_RANGE, ["n_rounds 0"])
+    expect(lib, f(fg, 7, sb, 0, 0, DUMMY, None, None, None), E_RANGE, ["n_rounds 7"])
+    expect(lib, f(fg, 1, sb, 9, 0, None, DUMMY, None, None), E_RANGE, ["dtype 9"])
+    expect(lib, f(fg, 1, sb, 1, 6, None, DUMMY, None, None), E_RANGE, ["flags 6"])
+    expect(lib, f(fg, 1, sb, 1, 1, None, None, DUMMY, None), E_INVAL, ["fgts[0] is NULL"])
+
+
+def test_leaf_utility_checks(lib):
+    vp = C.c_void_p
+    f = lib.pasur_leaf_utilities
+    f.argtypes = [vp, vp, C.c_int, C.c_int, vp, vp]
+    expect(lib, f(None, None, 0, 0, DUMMY, None), E_INVAL, ["null"])
+    expect(lib, f(DUMMY, None, 3, 0, DUMMY, None), E_RANGE, ["dtype 3"])
+    expect(lib, f(DUMMY, None, 0, 2, DUMMY, None), E_RANGE, ["flags 2"])
