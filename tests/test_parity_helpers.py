@@ -120,3 +120,67 @@ def test_accepts_resplit_inside_a_tie_group_but_not_across(solved):
                 assert_sigma_bar_up_to_ties(bad, sb, g, cb, 1e-5)
             return
     pytest.skip("no reached tie group with an untied sibling in this tree")
+
+
+# ---- the element-wise MLP bounds (tests/mlp_bounds.py), with planted mistakes
+
+def _mlp_problem(seed=3, M=900):
+    from oracle import mlp as omlp
+    rng = np.random.default_rng(seed)
+    X = rng.integers(0, 2, (M, omlp.N_IN)).astype(np.float64)
+    X[:, 156:167] = rng.normal(0, 0.5, (M, 11))
+    X = omlp.bf16_round(X)
+    W = omlp.init_weights(rng)
+    W[1] = rng.normal(0, 0.1, 256)
+    W[3] = rng.normal(0, 0.1, 256)
+    W[5] = rng.normal(0, 0.1, 2)
+    W = [np.asarray(w, np.float32).astype(np.float64) for w in W]
+    dY = rng.normal(0, 1e-3, (M, 2))
+    return W, X, dY
+
+
+def test_mlp_forward_bounds_catch_planted_mistakes():
+    from mlp_bounds import forward_bounds, layer_bounds
+    from oracle import mlp as omlp
+    W, X, _ = _mlp_problem()
+    (H1, H2, Y), (A1, A2, bY) = forward_bounds(W, X)
+    assert np.array_equal(H1, omlp.forward(W, X)[0])
+    # layer by layer, only a small share of activations may round either way
+    H1l, A1l = layer_bounds(X, W[0], W[1], True)
+    H2l, A2l = layer_bounds(H1, W[2], W[3], True)
+    Yl, bYl = layer_bounds(H2, W[4], W[5], False)
+    assert np.array_equal(H1l, H1) and np.array_equal(H2l, H2)
+    assert np.mean(A1l > 0) < 5e-2 and np.mean(A2l > 0) < 5e-2
+    # one activation one bfloat16 step off where no rounding point is near
+    i, j = map(int, np.argwhere((A2l == 0) & (H2 > 0))[0])
+    bad = omlp.bf16_round(H2[i, j] * (1 + 2 ** -7))
+    assert bad != H2[i, j] and abs(bad - H2[i, j]) > A2l[i, j]
+    # an output off by a hundred-thousandth of the sum of its terms' sizes
+    k = int(np.argmax(np.abs(Y[:, 0])))
+    assert 1e-5 * (np.abs(H2[k]) @ np.abs(omlp.bf16_round(W[4][:, 0]))) > bYl[k, 0]
+    # the carried (chain) bound is looser but still below a 1% error
+    assert abs(Y[k, 0]) * 1e-2 > bY[k, 0]
+
+
+def test_mlp_backward_bounds_catch_planted_mistakes():
+    from mlp_bounds import backward_bounds
+    from oracle import mlp as omlp
+    W, X, dY = _mlp_problem()
+    H1, H2, _ = omlp.forward(W, X)
+    g = omlp.backward(W, X, H1, H2, dY)
+    b = backward_bounds(W, X, H1, H2, dY)
+    assert all(np.all(bi >= 0) for bi in b)
+    # one dropped term of dW1 (one row of the reduction over rows)
+    Xq = omlp.bf16_round(X)
+    G2q = omlp.bf16_round((omlp.bf16_round(dY) @ omlp.bf16_round(W[4]).T) * (H2 > 0))
+    G1q = omlp.bf16_round((G2q @ omlp.bf16_round(W[2]).T) * (H1 > 0))
+    terms = np.abs(Xq[:, 0, None] * G1q)  # dW1[0, :] terms per row
+    m, j = np.unravel_index(np.argmax(terms), terms.shape)
+    assert terms[m, j] > b[0][0, j]
+    # a column of dW2 taken from its neighbour
+    assert np.any(np.abs(g[2][:, 1] - g[2][:, 0]) > b[2][:, 0])
+    # a row of dW3 dropped, and db1 shifted by one row's gradient
+    assert np.any(np.abs(g[4][3]) > b[4][3])
+    G1 = (G2q @ omlp.bf16_round(W[2]).T) * (H1 > 0)
+    r = int(np.argmax(np.abs(G1).sum(axis=1)))
+    assert np.any(np.abs(G1[r]) > b[1])
