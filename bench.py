@@ -1,27 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark: full-width DCFR node-updates/s on one MI355X.
 
-Default workload (two-round): one step = the whole hot path on one seeded
-two-round subgame (the last two rounds of deal 1, every round-6 card state
-times every inherited score): build both rounds' game trees, unfold them,
-link the leaves to next-round roots, leaf utilities, 2000 DCFR iterations
-per round (last round first), average strategies, round values passed
-backward, and the composed exploitability of the average strategies.
-Inputs are resident on the GPU before the timed region; K steps are timed
-between device synchronisations.  Other workloads (--workload): batched (64
-deals in one persistent launch per round, HIP-graph replay), full-game (all
-six rounds of one deal), paper-scale (32 full games as one batch),
-warm-start (learned warm start vs plain DCFR), selfplay (games/s and fair
-values on a solved full game), es (external-sampling CFR on a full game),
-infoset (infoset rows of a full game; strategy models on them), mlp (the
-network's MFMA kernels alone), variants (DCFR, CFR+ and vanilla CFR
-convergence), copy (counter calibration).
+Default workload (full-game): one step = the whole hot path on the full game
+of seeded deal 40 (all six rounds from the initial deal, 8.5e8 unfolded
+nodes): build every round's game tree, unfold it, link the leaves to
+next-round roots, leaf utilities, 1000 DCFR iterations per round (last round
+first), average strategies, round values passed backward, and the composed
+exploitability of the average strategies.  The deal's roots are resident on
+the GPU before the timed region; K steps are timed between device
+synchronisations.  Other workloads (--workload): two-round (the last two
+rounds of one deal from a seeded legal playout), batched (64 deals from
+playouts, rounds 4-6, one persistent launch per round, HIP-graph replay),
+paper-scale (32 full games as one batch), warm-start (learned warm start vs
+plain DCFR), selfplay (games/s and fair values on a solved full game), es
+(external-sampling CFR on a full game), infoset (infoset rows of a full
+game; strategy models on them), mlp (the network's MFMA kernels alone),
+variants (DCFR, CFR+ and vanilla CFR convergence), copy (counter
+calibration).
 
 Prints one JSON line: the metric and its value, the step time, the
 dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
 against the MI355X peak, with counter-measured HBM traffic per launch and
 its rate, `traffic_GBs`, when recorded for this kernel source) and, for the
-default workload, the FP64 CPU oracle's rate on the host (cpu_baseline).
+full-game and two-round workloads, the FP64 CPU oracle's rate on the host
+(cpu_baseline).
 """
 import argparse
 import json
@@ -72,6 +74,26 @@ def counted_traffic(args, workload="two-round"):
     if workload == "full-game" and args.sched != "auto":
         return None
     return rec["bytes"]
+
+
+def playout_problem(seed, rnd):
+    """Deal ``seed`` and the root of round ``rnd`` reached by the seeded legal
+    playout (synth.playout_draws), played by the library's own round trees."""
+    import paper_2508_06559_amd as pa
+    import synth
+    deck = synth.deal(seed)
+    g = pa.playout_root(deck, rnd, synth.playout_draws(seed, 5))
+    return deck, [synth.Root(int(g["pool"]), int(g["ca"]), int(g["cb"]), int(g["d"]),
+                             int(g["bonus"]))]
+
+
+def oracle_playout_problem(seed, rnd):
+    """The same start state played by the oracle's own move generator (for
+    the CPU baseline: no oracle input comes from the HIP path)."""
+    import synth
+    from oracle.playout import playout_root
+    deck = synth.deal(seed)
+    return deck, [playout_root(deck, rnd, synth.playout_draws(seed, 5))]
 
 
 HBM_PEAK_GBS = 8000.0
@@ -189,8 +211,8 @@ def cpu_baseline(deck, roots, iters):
 
 
 def bench_batched(args):
-    """64 seeded deals (seeds 100..163), rounds 4-6 from a synthetic round-4
-    start, 1000 DCFR iterations per round; the backward solve of all deals is
+    """64 seeded deals (seeds 100..163), rounds 4-6 from the round-4 start of
+    a seeded legal playout, 1000 DCFR iterations per round; the backward solve of all deals is
     captured in one HIP graph and replayed.  Schedules are autotuned first."""
     import torch
     import paper_2508_06559_amd as pa
@@ -200,7 +222,7 @@ def bench_batched(args):
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
     iters = 1000 if args.iters == 2000 else args.iters
-    probs = [synth.subgame_roots(seed, 3) for seed in range(100, 164)]
+    probs = [playout_problem(seed, 3) for seed in range(100, 164)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b = pa.BatchSolver(probs, 3, iters, dtype=dtype)
@@ -242,7 +264,7 @@ def bench_batched(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"batched: 64 seeded deals (seeds 100-163), rounds 4-6, {sum(sizes)} "
+        "config": {"workload": f"batched: 64 seeded deals (seeds 100-163), rounds 4-6 from seeded legal playouts, {sum(sizes)} "
                                f"nodes ({min(sizes)}..{max(sizes)} per deal), {iters} DCFR iterations "
                                f"per round, backward solve of all deals replayed as one HIP graph",
                    "state": args.state, "build_seconds": build_s,
@@ -525,7 +547,7 @@ def bench_warm(args):
     import synth
 
     t0 = time.perf_counter()
-    train = [synth.two_round_root(s) for s in range(10000, 10000 + args.train_deals)]
+    train = [playout_problem(s, 4) for s in range(10000, 10000 + args.train_deals)]
     units = learn.training_units(train, 1000)
     torch.cuda.synchronize()
     data_s = time.perf_counter() - t0
@@ -559,7 +581,7 @@ def bench_warm(args):
     fwd_tflops = 5 * per_row * big.shape[0] / (a.elapsed_time(b) * 1e-3) / 1e12
     del big, Yb
     grid = tuple(range(6, 64, 2)) + (64, 80, 96, 128, 192, 256)
-    test = [synth.two_round_root(s) for s in range(20000, 20000 + args.test_deals)]
+    test = [playout_problem(s, 4) for s in range(20000, 20000 + args.test_deals)]
     levels = [int(x) for x in args.warm_levels.split(",")]
     res = {"plain": [], "warm": []}
     res.update({f"warm_levels_{L}": [] for L in levels[1:]})
@@ -876,8 +898,8 @@ def bench_infoset(args):
 
     # strategy models
     ntr, nte = args.model_train_deals, args.model_test_deals
-    train = [synth.two_round_root(s_) for s_ in range(30000, 30000 + ntr)]
-    test = [synth.two_round_root(s_) for s_ in range(40000, 40000 + nte)]
+    train = [playout_problem(s_, 4) for s_ in range(30000, 30000 + ntr)]
+    test = [playout_problem(s_, 4) for s_ in range(40000, 40000 + nte)]
     tm = time.perf_counter()
     models = {}
     for feats in ("edge", "infoset"):
@@ -1021,7 +1043,7 @@ def bench_variants(args):
 
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
-    deck, roots = synth.two_round_root(args.seed)
+    deck, roots = playout_problem(args.seed, 4)
     rules = {"dcfr": pa.paper_params(),
              "cfr_plus": pa.CfrParams(pa.CFR_PLUS, pa.RM_POSITIVE, 0.0, 0.0, 0.0, 0.0, pa.SCHED_ROOT, 0, 0),
              "vanilla": pa.CfrParams(pa.CFR_VANILLA, pa.RM_POSITIVE, 0.0, 0.0, 0.0, 0.0, pa.SCHED_ROOT, 0, 0)}
@@ -1145,7 +1167,7 @@ def main():
     params = pa.paper_params({"root": pa.SCHED_ROOT, "level": pa.SCHED_LEVEL_SYNC,
                               "root-global": pa.SCHED_ROOT_GLOBAL, "stream": pa.SCHED_STREAM,
                               "auto": pa.SCHED_AUTO}[args.sched], args.block)
-    deck, roots = synth.two_round_root(args.seed)
+    deck, roots = playout_problem(args.seed, 4)
     d_roots = pa.roots_to_device(roots)  # resident before timing
     torch.cuda.synchronize()
 
@@ -1211,7 +1233,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"last two rounds of seeded deal {args.seed}: full unfolded trees "
+            "workload": f"last two rounds of seeded deal {args.seed} from a seeded legal playout "
+                        f"of rounds 1-4: full unfolded trees "
                         f"({nodes} nodes, {edges} edges), {args.iters} DCFR iterations per round, "
                         f"backward round values, composed exploitability",
             "state": args.state,
@@ -1240,7 +1263,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(deck, roots, args.iters)
+        odeck, oroots = oracle_playout_problem(args.seed, 4)
+        out["cpu_baseline"] = cpu_baseline(odeck, oroots, args.iters)
         log(f"[bench] cpu baseline done in {out['cpu_baseline']['seconds']:.1f} s")
     print(json.dumps(out), flush=True)
 

@@ -600,4 +600,4 @@ def profile_read():
     return k[: n.value], lv[: n.value], ms[: n.value], work[: n.value]
 
 
-from .solver import SubgameSolver, RoundResult, BatchSolver  # noqa: E402  (drivers over the calls above)
+from .solver import SubgameSolver, RoundResult, BatchSolver, playout_root  # noqa: E402  (drivers over the calls above)

@@ -13,7 +13,8 @@ from dataclasses import dataclass
 from typing import List, Optional
 
 from . import (PASUR_F32, PASUR_F64, PLAY_SIGMA_BAR, RM_FLOOR, V_ITERATE_MEAN, V_SIGMA_BAR,
-               ES_FRONTIER, CfrState, es_iterate, exploitability, selfplay, Plan, UnfoldedTree,
+               ES_FRONTIER, FGT_CHILD_BEGIN, FGT_LINK, FGT_NEXT_ROOTS, ROOT_DTYPE, CfrState,
+               es_iterate, exploitability, selfplay, Plan, UnfoldedTree,
                average_strategy, build_round_tree, cfr_init, cfr_iterate, leaf_utilities,
                paper_params, round_values, roots_to_device, unfold_scores, _torch)
 
@@ -137,6 +138,42 @@ class SubgameSolver:
             if rr.gt is not None:
                 rr.gt.free()
         self.rounds = []
+
+
+def playout_root(deck, rnd: int, draws, stream=None):
+    """Start state of round ``rnd`` reached by a seeded legal playout from the
+    initial deal (section "Pasur"): each round's tree is built and unfolded
+    by the library from the current root alone (pasur_build_round_tree,
+    pasur_unfold_scores), move i takes the child ``draws[i] mod k`` of the
+    current node among its k children (canonical order), and the leaf's link
+    gives the next round's root.  Returns (pool, ca, cb, d, bonus) as a
+    ROOT_DTYPE record."""
+    import numpy as np
+    root = np.zeros(1, ROOT_DTYPE)
+    root[0] = (_initial_pool(deck), 0, 0, 0, 0, 0)
+    i = 0
+    for r in range(rnd):
+        d_root = roots_to_device(root)
+        gt = build_round_tree(deck, r, d_root, 1, stream)
+        f = unfold_scores(gt, d_root, 1, stream)
+        gt.free()
+        node = 0
+        for l in range(8):
+            cb = f.read(FGT_CHILD_BEGIN, l)
+            b, e = int(cb[node]), int(cb[node + 1])
+            node = b + int(draws[i]) % (e - b)
+            i += 1
+        link = f.read(FGT_LINK)
+        root = f.read(FGT_NEXT_ROOTS)[int(link[node]):int(link[node]) + 1].copy()
+        f.free()
+    return root[0]
+
+
+def _initial_pool(deck) -> int:
+    m = 0
+    for c in deck[:4]:
+        m |= 1 << int(c)
+    return m
 
 
 class BatchSolver:

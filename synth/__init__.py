@@ -175,6 +175,15 @@ def subgame_roots(seed: int, rnd: int):
     return deck, [Root(pool, ca, cb, d, bonus)]
 
 
+def playout_draws(seed: int, rounds: int) -> List[int]:
+    """Random 64-bit draws for a seeded playout of ``rounds`` rounds from the
+    initial deal (eight moves per round): move i takes the legal move number
+    ``draws[i] mod k`` among the k legal moves in canonical order.  Only the
+    random numbers live here; each side plays the moves with its own rules."""
+    rng = SplitMix64(seed ^ 0x3C6EF372FE94F82B)
+    return [rng.next() for _ in range(8 * rounds)]
+
+
 # Deck of the paper's worked example (table "Initial setup for a single game
 # instance" and the first row of every round of the step-by-step gameplay
 # figure): pool, then per round Alex's and Bob's four cards.
