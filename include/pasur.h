@@ -102,6 +102,21 @@ typedef enum {
 } pasur_gt_field;
 /* Synchronous copy of one GT array of one level into host memory. */
 int pasur_gt_read(const pasur_gt *gt, int field, int level, void *host_dst);
+/* Read-only device view of a game tree's arrays (no copy): the same arrays
+ * as pasur_gt_read, owned by the handle and valid until pasur_gt_free.
+ * Entries of levels a field does not have are NULL. */
+typedef struct {
+  int round;
+  int64_t n[9];
+  const uint64_t *pool[9];
+  const uint8_t *hands[9];
+  const uint64_t *rs[9];
+  const int32_t *parent[9];
+  const int32_t *child_begin[8];
+  const uint8_t *act_card[9];
+  const uint64_t *act_cap[9];
+} pasur_gt_view;
+int pasur_gt_get_view(const pasur_gt *gt, pasur_gt_view *out);
 void pasur_gt_free(pasur_gt *gt);
 
 /* ---- a2 + a3: unfolding and between-round linkage -------------------------
@@ -129,6 +144,27 @@ typedef enum {
   PASUR_FGT_LEAF_BASE = 7    /* int16 per leaf: round points (+ bonus in round 5) */
 } pasur_fgt_field;
 int pasur_fgt_read(const pasur_fgt *fgt, int field, int level, void *host_dst);
+/* Read-only device view of an unfolded tree's arrays (no copy), owned by the
+ * handle and valid until pasur_fgt_free: per level the FGT node's GT node,
+ * score id, parent (levels 1..8) and child range (levels 0..7, n+1
+ * entries); the score table (4 int8 per score), the next-round roots and
+ * each leaf's link into them (NULL for round 5), and the leaves' round
+ * points.  Callers that keep their own copies size them from `n`. */
+typedef struct {
+  int round;
+  int64_t n[9];
+  const int32_t *gt[9];
+  const int32_t *sid[9];
+  const int32_t *parent[9];
+  const int32_t *child_begin[8];
+  const int8_t *score_tab;
+  int64_t n_scores;
+  const pasur_root *next_roots;
+  int64_t n_next;
+  const int32_t *link;
+  const int16_t *leaf_base;
+} pasur_fgt_view;
+int pasur_fgt_get_view(const pasur_fgt *fgt, pasur_fgt_view *out);
 /* Device pointer to the next-round roots (owned by the handle, n_next
  * entries, canonical order); NULL for round 5. */
 const pasur_root *pasur_fgt_next_roots(const pasur_fgt *fgt);
@@ -447,6 +483,9 @@ int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X, const uint
 int pasur_mlp_loss(const float *Y, const float *target_sigma, const float *target_value,
                    const int32_t *seg, int64_t n_parents, int64_t n_rows, float value_weight,
                    float *dY, float *loss, void *stream);
+/* Plain SGD on an FP32 master array, w <- w - lr g; refreshes its BF16 copy
+ * when w_bf16 != NULL. */
+int pasur_sgd_step(float *w, const float *g, uint16_t *w_bf16, int64_t n, float lr, void *stream);
 /* Adam on an FP32 master array; refreshes its BF16 copy when w_bf16 != NULL. */
 int pasur_adam_step(float *w, const float *g, float *m, float *v, uint16_t *w_bf16, int64_t n,
                     float lr, float beta1, float beta2, float eps, int64_t step, void *stream);

@@ -94,6 +94,9 @@ def lib():
         L.pasur_tree_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.pasur_tree_values_noalloc.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.pasur_exploitability.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp, vp]
+        L.pasur_gt_get_view.argtypes = [vp, vp]
+        L.pasur_fgt_get_view.argtypes = [vp, vp]
+        L.pasur_sgd_step.argtypes = [vp, vp, vp, i64, C.c_float, vp]
         L.pasur_plan_create.argtypes = [vp, vp, i32, vp, i64, i64, C.POINTER(vp), vp]
         L.pasur_plan_iterate.argtypes = [vp, i64, i32, vp]
         L.pasur_plan_info.argtypes = [vp, vp]
@@ -381,6 +384,42 @@ def exploitability(fgts, sigma_bars, dtype: int, br_a=None, br_b=None, v=None, s
     flags = LEAF_LITERAL_BONUS0 if literal_bonus0 else 0
     _check(lib().pasur_exploitability(hs, n, sb, dtype, flags, _p(br_a), _p(br_b), _p(v),
                                       _stream(stream)), "pasur_exploitability")
+
+
+class GtView(C.Structure):
+    """pasur_gt_view: device pointers of a game tree's arrays (borrowed)."""
+    _fields_ = [("round", C.c_int), ("n", C.c_int64 * 9), ("pool", C.c_void_p * 9),
+                ("hands", C.c_void_p * 9), ("rs", C.c_void_p * 9), ("parent", C.c_void_p * 9),
+                ("child_begin", C.c_void_p * 8), ("act_card", C.c_void_p * 9),
+                ("act_cap", C.c_void_p * 9)]
+
+
+class FgtView(C.Structure):
+    """pasur_fgt_view: device pointers of an unfolded tree's arrays (borrowed,
+    valid until the tree is freed)."""
+    _fields_ = [("round", C.c_int), ("n", C.c_int64 * 9), ("gt", C.c_void_p * 9),
+                ("sid", C.c_void_p * 9), ("parent", C.c_void_p * 9),
+                ("child_begin", C.c_void_p * 8), ("score_tab", C.c_void_p),
+                ("n_scores", C.c_int64), ("next_roots", C.c_void_p), ("n_next", C.c_int64),
+                ("link", C.c_void_p), ("leaf_base", C.c_void_p)]
+
+
+def gt_view(gt) -> GtView:
+    v = GtView()
+    _check(lib().pasur_gt_get_view(gt.h, C.byref(v)), "pasur_gt_get_view")
+    return v
+
+
+def fgt_view(fgt) -> FgtView:
+    v = FgtView()
+    _check(lib().pasur_fgt_get_view(fgt.h, C.byref(v)), "pasur_fgt_get_view")
+    return v
+
+
+def sgd_step(w, g, wb, lr, stream=None):
+    """pasur_sgd_step on torch tensors (wb: int16 BF16 bit patterns or None)."""
+    _check(lib().pasur_sgd_step(_p(w), _p(g), _p(wb), w.numel(), lr, _stream(stream)),
+           "pasur_sgd_step")
 
 
 class Plan:

@@ -640,6 +640,15 @@ __global__ void k_adam(int64_t n, float *__restrict__ w, const float *__restrict
   if (wb) wb[i] = (__bf16)wi;
 }
 
+__global__ void k_sgd(int64_t n, float *__restrict__ w, const float *__restrict__ g,
+                      __bf16 *__restrict__ wb, float lr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float wi = w[i] - lr * g[i];
+  w[i] = wi;
+  if (wb) wb[i] = (__bf16)wi;
+}
+
 // Warm start of one level: sigma = softmax of the predicted logits over
 // each parent's children; R = kappa_r * sigma; Sbar = kappa_s * sigma.
 template <class T>
@@ -1026,6 +1035,18 @@ extern "C" int pasur_adam_step(float *w, const float *g, float *m, float *v, uin
   const float c2 = 1.f - std::pow(beta2, (float)step);
   k_adam<<<blocks(n), 256, 0, (hipStream_t)stream>>>(n, w, g, m, v, (__bf16 *)w_bf16, lr, beta1,
                                                      beta2, eps, c1, c2);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+extern "C" int pasur_sgd_step(float *w, const float *g, uint16_t *w_bf16, int64_t n, float lr,
+                              void *stream) {
+  if (!w || !g || n < 0) {
+    set_error("bad SGD arguments");
+    return PASUR_E_INVAL;
+  }
+  if (n == 0) return PASUR_OK;
+  k_sgd<<<blocks(n), 256, 0, (hipStream_t)stream>>>(n, w, g, (__bf16 *)w_bf16, lr);
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
 }

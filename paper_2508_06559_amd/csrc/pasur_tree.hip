@@ -892,3 +892,46 @@ extern "C" int pasur_fgt_read(const pasur_fgt *f, int field, int level, void *ho
   PASUR_TRY_HIP(hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
   return PASUR_OK;
 }
+
+extern "C" int pasur_gt_get_view(const pasur_gt *g, pasur_gt_view *out) {
+  if (!g || !out) {
+    pasur::set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->round = g->round;
+  for (int l = 0; l < 9; ++l) {
+    out->n[l] = g->n[l];
+    out->pool[l] = g->pool[l];
+    out->hands[l] = g->hands[l];
+    out->rs[l] = g->rs[l];
+    out->parent[l] = g->parent[l];
+    out->act_card[l] = g->act_card[l];
+    out->act_cap[l] = g->act_cap[l];
+    if (l < 8) out->child_begin[l] = g->child_begin[l];
+  }
+  return PASUR_OK;
+}
+
+extern "C" int pasur_fgt_get_view(const pasur_fgt *f, pasur_fgt_view *out) {
+  if (!f || !out) {
+    pasur::set_error("null argument");
+    return PASUR_E_INVAL;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->round = f->round;
+  for (int l = 0; l < 9; ++l) {
+    out->n[l] = f->n[l];
+    out->gt[l] = f->gt[l];
+    out->sid[l] = f->sid[l];
+    out->parent[l] = f->parent[l];
+    if (l < 8) out->child_begin[l] = f->child_begin[l];
+  }
+  out->score_tab = f->score_tab;
+  out->n_scores = f->n_scores;
+  out->next_roots = f->round < 5 ? f->next_roots : nullptr;
+  out->n_next = f->round < 5 ? f->n_next : 0;
+  out->link = f->round < 5 ? f->link : nullptr;
+  out->leaf_base = f->leaf_base;
+  return PASUR_OK;
+}

@@ -214,3 +214,17 @@ def test_leaf_utility_checks(lib):
     expect(lib, f(None, None, 0, 0, DUMMY, None), E_INVAL, ["null"])
     expect(lib, f(DUMMY, None, 3, 0, DUMMY, None), E_RANGE, ["dtype 3"])
     expect(lib, f(DUMMY, None, 0, 2, DUMMY, None), E_RANGE, ["flags 2"])
+
+
+def test_view_and_sgd_checks(lib):
+    vp = C.c_void_p
+    for name in ("pasur_gt_get_view", "pasur_fgt_get_view"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp]
+        expect(lib, f(None, DUMMY), E_INVAL, ["null"])
+        expect(lib, f(DUMMY, None), E_INVAL, ["null"])
+    f = lib.pasur_sgd_step
+    f.argtypes = [vp, vp, vp, C.c_int64, C.c_float, vp]
+    expect(lib, f(None, DUMMY, None, 4, 0.1, None), E_INVAL, ["SGD"])
+    expect(lib, f(DUMMY, DUMMY, None, -1, 0.1, None), E_INVAL, ["SGD"])
+    assert f(DUMMY, DUMMY, None, 0, 0.1, None) == 0  # nothing to do, no launch
