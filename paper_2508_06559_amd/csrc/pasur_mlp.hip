@@ -721,9 +721,71 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 // in feature order.
 constexpr int IM = 128;                 // rows per workgroup
 constexpr int kInferWaves = 16;         // four waves per SIMD in the one workgroup that fits a CU
+constexpr int kInferDepth = 1;          // K steps of weight fragments in flight per wave
 constexpr int XS = kIn + 8, HS = kHid + 8;  // LDS row strides (bf16), 16-byte aligned
 
-template <int WAVES>
+// One hidden layer of the fused inference for a wave's 16*TA output features
+// and all 16*TB rows: the weight fragments (A operand, from global memory)
+// run DEPTH K steps ahead in a ring of registers, so that their L2 latency
+// hides behind the MFMAs of the steps in between; activations (B operand)
+// come from LDS.  Writes bf16(relu(acc + bias)) into Hs after every wave has
+// read As.
+template <int K, int TA, int TB, int DEPTH>
+__device__ __forceinline__ void infer_layer(const __bf16 *__restrict__ Wt, const __bf16 *As, int as,
+                                            const float *__restrict__ bias, __bf16 *Hs, int n_base,
+                                            int lane) {
+  constexpr int NS = K / 32;
+  const int lr = lane & 15, lk = 8 * (lane >> 4);
+  f32x4 acc[TA][TB];
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ring[DEPTH][TA];
+#pragma unroll
+  for (int st = 0; st < DEPTH; ++st)
+    if (st < NS)
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+        ring[st][a] = *reinterpret_cast<const bf16x8 *>(Wt + (int64_t)(n_base + 16 * a + lr) * K +
+                                                        32 * st + lk);
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {
+    bf16x8 wcur[TA];
+#pragma unroll
+    for (int a = 0; a < TA; ++a) wcur[a] = ring[st % DEPTH][a];
+    if (st + DEPTH < NS) {
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+        ring[st % DEPTH][a] = *reinterpret_cast<const bf16x8 *>(
+            Wt + (int64_t)(n_base + 16 * a + lr) * K + 32 * (st + DEPTH) + lk);
+    }
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      const bf16x8 x = *reinterpret_cast<const bf16x8 *>(As + (16 * b + lr) * as + 32 * st + lk);
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[a], x, acc[a][b], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // every wave has read As before Hs is (over)written
+#pragma unroll
+  for (int a = 0; a < TA; ++a) {
+    const int n = n_base + 16 * a + 4 * (lane >> 4);
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      const int m = 16 * b + lr;
+      typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+      bf16x4 h;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = (__bf16)fmaxf(acc[a][b][i] + bias[n + i], 0.f);
+      *reinterpret_cast<bf16x4 *>(Hs + m * HS + n) = h;
+    }
+  }
+  __syncthreads();
+}
+
+template <int WAVES, int DEPTH>
 __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *__restrict__ X,
                                                    const __bf16 *__restrict__ W1t,
                                                    const float *__restrict__ b1,
@@ -751,63 +813,28 @@ __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *_
   }
   __syncthreads();
   const int n_base = wave * 16 * TA;   // this wave's output features
-  const int lr = lane & 15, lk = 8 * (lane >> 4);
-  auto layer = [&](const __bf16 *__restrict__ Wt, int K, const __bf16 *As, int as,
-                   const float *__restrict__ bias) {
-    f32x4 acc[TA][TB];
+  infer_layer<kIn, TA, TB, DEPTH>(W1t, Xs, XS, b1, Hs, n_base, lane);   // H1 in Hs
+  infer_layer<kHid, TA, TB, DEPTH>(W2t, Hs, HS, b2, Hs, n_base, lane);  // H2 in Hs
+  // last layer (256 -> 2) on the matrix cores as well: wave v < IM/16 takes
+  // rows 16v..16v+15; the A operand is W3 transposed and padded to 16
+  // outputs (rows 2..15 zero), built from W3 in registers; outputs 0 and 1
+  // of row 16v + (lane & 15) land in elements 0 and 1 of lanes 0..15.
+  if (wave < IM / 16) {
+    const int lr = lane & 15, lk = 8 * (lane >> 4);
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int a = 0; a < TA; ++a)
+    for (int k0 = 0; k0 < kHid; k0 += 32) {
+      bf16x8 wa;
 #pragma unroll
-      for (int b = 0; b < TB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 wcur[TA], wnext[TA];
-#pragma unroll
-    for (int a = 0; a < TA; ++a)
-      wcur[a] = *reinterpret_cast<const bf16x8 *>(Wt + (int64_t)(n_base + 16 * a + lr) * K + lk);
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      if (k0 + 32 < K) {
-#pragma unroll
-        for (int a = 0; a < TA; ++a)
-          wnext[a] = *reinterpret_cast<const bf16x8 *>(Wt + (int64_t)(n_base + 16 * a + lr) * K +
-                                                       k0 + 32 + lk);
-      }
-#pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        const bf16x8 x = *reinterpret_cast<const bf16x8 *>(As + (16 * b + lr) * as + k0 + lk);
-#pragma unroll
-        for (int a = 0; a < TA; ++a)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[a], x, acc[a][b], 0, 0, 0);
-      }
-#pragma unroll
-      for (int a = 0; a < TA; ++a) wcur[a] = wnext[a];
+      for (int i = 0; i < 8; ++i) wa[i] = lr < kOut ? W3[(k0 + lk + i) * kOut + lr] : (__bf16)0.f;
+      const bf16x8 x = *reinterpret_cast<const bf16x8 *>(Hs + (16 * wave + lr) * HS + k0 + lk);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, x, acc, 0, 0, 0);
     }
-    __syncthreads();  // every wave has read As before Hs is (over)written
-#pragma unroll
-    for (int a = 0; a < TA; ++a) {
-      const int n = n_base + 16 * a + 4 * (lane >> 4);
-#pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        const int m = 16 * b + lr;
-        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-        bf16x4 h;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) h[i] = (__bf16)fmaxf(acc[a][b][i] + bias[n + i], 0.f);
-        *reinterpret_cast<bf16x4 *>(Hs + m * HS + n) = h;
-      }
+    const int m = m0 + 16 * wave + lr;
+    if (lane < 16 && m < M) {
+      Y[(int64_t)m * kOut + 0] = acc[0] + b3[0];
+      Y[(int64_t)m * kOut + 1] = acc[1] + b3[1];
     }
-    __syncthreads();
-  };
-  layer(W1t, kIn, Xs, XS, b1);   // H1 in Hs
-  layer(W2t, kHid, Hs, HS, b2);  // H2 in Hs
-  // last layer: thread t -> row t / 2, output t % 2
-  const int r = tid >> 1, o = tid & 1;
-  if (tid < 2 * IM && m0 + r < M) {
-    float y = 0.f;
-    for (int n = 0; n < kHid; n += 8) {
-      const bf16x8 h = *reinterpret_cast<const bf16x8 *>(Hs + r * HS + n);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) y += (float)h[i] * (float)W3[(n + i) * kOut + o];
-    }
-    Y[(int64_t)(m0 + r) * kOut + o] = y + b3[o];
   }
 }
 
@@ -1320,7 +1347,7 @@ extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, in
     return PASUR_E_RANGE;
   }
   std::call_once(lds_once[dev], [&] {
-    lds_err[dev] = hipFuncSetAttribute((const void *)k_mlp_infer<kInferWaves>,
+    lds_err[dev] = hipFuncSetAttribute((const void *)k_mlp_infer<kInferWaves, kInferDepth>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInferLds);
   });
   if (lds_err[dev] != hipSuccess) {
@@ -1342,7 +1369,7 @@ extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, in
     k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid,
                                                          Wt + (size_t)kIn * kHid);
   }
-  k_mlp_infer<kInferWaves><<<(unsigned)((M + IM - 1) / IM), 64 * kInferWaves, kInferLds, s>>>(
+  k_mlp_infer<kInferWaves, kInferDepth><<<(unsigned)((M + IM - 1) / IM), 64 * kInferWaves, kInferLds, s>>>(
       (int)M, (const __bf16 *)X, W1t, w->b1, W2t, w->b2, (const __bf16 *)w->W3, w->b3, Y);
   e = hipGetLastError();
   if (Wt) (void)hipFreeAsync(Wt, s);
