@@ -540,7 +540,10 @@ def bench_warm(args):
     deals (seeds 20000..) measure the seconds (and iterations) DCFR needs to
     reach exploitability <= 1e-3 at the round-5 root, plain vs warm-started
     (inference included, exploitability checks excluded, plain DCFR as the
-    fallback).  Also reports the MFMA throughput of the network's GEMMs."""
+    fallback).  Also reports the MFMA throughput of the network's GEMMs, and
+    plain DCFR's exploitability after 1..16 iterations on the first 32
+    held-out deals (what the network's starting profile is worth in
+    iterations)."""
     import torch
     import paper_2508_06559_amd as pa
     from paper_2508_06559_amd import learn
@@ -586,6 +589,10 @@ def bench_warm(args):
     res = {"plain": [], "warm": []}
     res.update({f"warm_levels_{L}": [] for L in levels[1:]})
     ex0 = {"uniform": [], "network": []}
+    # plain DCFR's exploitability after a few iterations: how many iterations
+    # the network's starting profile is worth
+    early = (1, 2, 3, 4, 6, 8, 10, 12, 16)
+    ex_early = {T: [] for T in early}
     for k, (deck, roots) in enumerate(test):
         res["plain"].append(learn.seconds_to_target(deck, 4, roots, 1e-3, grid, None))
         res["warm"].append(learn.seconds_to_target(deck, 4, roots, 1e-3, grid, model,
@@ -596,6 +603,10 @@ def bench_warm(args):
         if k < 32:
             ex0["uniform"].append(learn.initial_profile_exploitability(deck, roots, None))
             ex0["network"].append(learn.initial_profile_exploitability(deck, roots, model))
+            for T in early:
+                sv = learn.solve_subgame(deck, 4, roots, T)
+                ex_early[T].append(learn.exploitability(sv))
+                sv.free()
         if k % 32 == 31:
             log(f"[bench] evaluated {k + 1}/{len(test)} held-out deals")
 
@@ -637,12 +648,18 @@ def bench_warm(args):
                                          if k.startswith("warm_levels_")},
                    "speedup_median_seconds": sp["median_seconds"] / sw["median_seconds"],
                    "initial_profile_exploitability_median": {k: float(np.median(v)) for k, v in ex0.items()},
+                   "plain_exploitability_after_iterations": {
+                       str(T): {"median": float(np.median(v)), "p25": float(np.percentile(v, 25)),
+                                "p75": float(np.percentile(v, 75))} for T, v in ex_early.items()},
                    "final_train_loss": hist[-1], "data_seconds": data_s},
         "roofline": {"bound": "mfma", "kernel": "k_mlp_infer (fused 3-layer inference, BF16 MFMA "
                                                 "16x16x32, FP32 accumulate), 2^20 rows",
                      "achieved": inf_tflops, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": inf_tflops / 2500.0, "traffic": None,
-                     "forward_pass_TFLOPs": fwd_tflops, "training_TFLOPs": train_tflops},
+                     "forward_pass_TFLOPs": fwd_tflops,
+                     # one epoch over units of ~8,000 rows: launch-bound, not
+                     # the GEMM rate (the mlp workload times 2^18-row steps)
+                     "training_epoch_TFLOPs": train_tflops},
     }
     print(json.dumps(out), flush=True)
 
