@@ -634,6 +634,7 @@ def bench_warm(args):
 
     sp, sw = summ(res["plain"]), summ(res["warm"])
     sw.update(paired(res["warm"]))
+    full = bench_warm_full_games(args, levels[0], log) if args.full_test_games > 0 else None
     out = {
         "metric": METRIC, "value": sw["median_seconds"], "unit": "s to exploitability 1e-3 (warm start)",
         "n_gpus": 1, "steps": len(test), "warmup": 0, "ms_per_step": sw["median_seconds"] * 1e3,
@@ -651,7 +652,8 @@ def bench_warm(args):
                    "plain_exploitability_after_iterations": {
                        str(T): {"median": float(np.median(v)), "p25": float(np.percentile(v, 25)),
                                 "p75": float(np.percentile(v, 75))} for T, v in ex_early.items()},
-                   "final_train_loss": hist[-1], "data_seconds": data_s},
+                   "final_train_loss": hist[-1], "data_seconds": data_s,
+                   "full_games": full},
         "roofline": {"bound": "mfma", "kernel": "k_mlp_infer (fused 3-layer inference, BF16 MFMA "
                                                 "16x16x32, FP32 accumulate), 2^20 rows",
                      "achieved": inf_tflops, "peak": 2500.0, "unit": "TFLOP/s",
@@ -662,6 +664,82 @@ def bench_warm(args):
                      "training_epoch_TFLOPs": train_tflops},
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_warm_full_games(args, max_level, log):
+    """The warm start on whole games: a network trained on DCFR solutions
+    (--full-iters iterations per round) of --full-train-games seeded full
+    games (seeds 10000..), then on --full-test-games held-out full games
+    (seeds 20000..) the iterations and seconds DCFR needs to reach
+    exploitability <= 1e-3 at the initial deal, plain vs warm-started (levels
+    1..max_level of every round), trees built once per deal outside the
+    timed solves.  Also plain DCFR's exploitability after its first
+    iterations and that of the network's starting profile."""
+    import torch
+    from paper_2508_06559_amd import learn
+    from paper_2508_06559_amd.solver import SubgameSolver
+    import synth
+
+    t0 = time.perf_counter()
+    train = [synth.full_game_root(s_) for s_ in range(10000, 10000 + args.full_train_games)]
+    units = learn.training_units(train, args.full_iters, start_round=0)
+    rows = sum(u.n_rows for u in units)
+    log(f"[bench] full-game training data: {len(units)} units, {rows} rows, "
+        f"{time.perf_counter() - t0:.1f} s")
+    model = learn.WarmStartMLP(1)
+    hist = learn.train(model, units, args.epochs, seed=1, log=log)
+    del units
+    grid = tuple(range(8, 64, 2)) + (64, 72, 80, 96, 112, 128, 160, 192, 256)
+    early = (1, 2, 4, 8, 16, 32)
+    warm = learn.WarmParams(max_level=max_level)
+    res = {"plain": [], "warm": []}
+    ex_early = {T: [] for T in early}
+    ex0 = {"uniform": [], "network": []}
+    build = []
+    nodes = []
+    for k, s_ in enumerate(range(20000, 20000 + args.full_test_games)):
+        deck, roots = synth.full_game_root(s_)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        sv = SubgameSolver(deck, 0, roots, keep_gt=True)
+        torch.cuda.synchronize()
+        build.append(time.perf_counter() - tb)
+        nodes.append(sum(sum(n) for n in sv.sizes()))
+        res["plain"].append(learn.iterations_to_target(sv, 1e-3, grid, None))
+        res["warm"].append(learn.iterations_to_target(sv, 1e-3, grid, model, warm))
+        for T in early:
+            learn.solve_built(sv, T)
+            ex_early[T].append(learn.exploitability(sv))
+        sv.free()
+        ex0["uniform"].append(learn.initial_profile_exploitability(deck, roots, None, start_round=0))
+        ex0["network"].append(learn.initial_profile_exploitability(deck, roots, model, start_round=0))
+        log(f"[bench] full game {s_}: {nodes[-1]:.3g} nodes, plain {res['plain'][-1]['iters']} "
+            f"iterations {res['plain'][-1]['solve_seconds']:.3f} s, warm {res['warm'][-1]['iters']} "
+            f"iterations {res['warm'][-1]['solve_seconds']:.3f} s")
+
+    def q(v):
+        v = np.asarray(v, dtype=float)
+        return {"median": float(np.median(v)), "p25": float(np.percentile(v, 25)),
+                "p75": float(np.percentile(v, 75))}
+
+    ok = [(w, p_) for w, p_ in zip(res["warm"], res["plain"])
+          if w["iters"] is not None and p_["iters"] is not None]
+    ratio = [w["solve_seconds"] / p_["solve_seconds"] for w, p_ in ok]
+    return {"workload": f"{args.full_train_games} seeded full games for training ({rows} rows, "
+                        f"{args.full_iters} DCFR iterations per round), {args.full_test_games} "
+                        f"held-out full games, iteration grid {list(grid)}, warm levels 1..{max_level}",
+            "nodes": q(nodes), "tree_build_seconds": q(build),
+            "plain_iters": q([p_["iters"] for _, p_ in ok]),
+            "warm_iters": q([w["iters"] for w, _ in ok]),
+            "plain_solve_seconds": q([p_["solve_seconds"] for _, p_ in ok]),
+            "warm_solve_seconds": q([w["solve_seconds"] for w, _ in ok]),
+            "per_deal_ratio_warm_over_plain": q(ratio),
+            "fraction_of_deals_warm_faster": float(np.mean(np.array(ratio) < 1.0)),
+            "warm_fallbacks": int(sum(w["fallback"] for w in res["warm"])),
+            "reached": len(ok),
+            "initial_profile_exploitability": {k_: q(v) for k_, v in ex0.items()},
+            "plain_exploitability_after_iterations": {str(T): q(v) for T, v in ex_early.items()},
+            "final_train_loss": hist[-1]}
 
 
 def bench_selfplay(args):
@@ -1131,6 +1209,12 @@ def main():
     ap.add_argument("--train-deals", type=int, default=512)
     ap.add_argument("--test-deals", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--full-train-games", type=int, default=48,
+                    help="warm-start: seeded full games the full-game network trains on")
+    ap.add_argument("--full-test-games", type=int, default=16,
+                    help="warm-start: held-out full games (0 skips the full-game arm)")
+    ap.add_argument("--full-iters", type=int, default=200,
+                    help="warm-start: DCFR iterations per round of the full-game training solves")
     ap.add_argument("--deals", type=int, default=32, help="paper-scale: number of full games")
     ap.add_argument("--model-train-deals", type=int, default=64, help="infoset: deals the models learn from")
     ap.add_argument("--model-test-deals", type=int, default=16, help="infoset: held-out deals")

@@ -249,19 +249,33 @@ def solve_subgame(deck, start_round: int, roots, iters: int, dtype: int = PASUR_
     sv = SubgameSolver(deck, start_round, roots, dtype=dtype, keep_gt=True)
     torch.cuda.synchronize()
     sv.build_seconds = time.perf_counter() - t_build
+    return solve_built(sv, iters, model, warm, params, fresh_state=True)
+
+
+def solve_built(sv: SubgameSolver, iters: int, model: Optional[WarmStartMLP] = None,
+                warm: WarmParams = WarmParams(), params=None, fresh_state: bool = False):
+    """The backward solve of solve_subgame on a solver whose trees are built
+    (keep_gt=True); a round's state is allocated when it has none (or when
+    fresh_state) and re-initialised otherwise, so one solver serves a grid
+    of iteration counts."""
+    torch = _torch()
     params = params if params is not None else paper_params()
+    dtype = sv.dtype
     V = None
     for rr in reversed(sv.rounds):
-        rr.state = CfrState(rr.fgt, dtype)
+        if fresh_state or rr.state is None:
+            rr.state = CfrState(rr.fgt, dtype)
         leaf_utilities(rr.fgt, V, dtype, rr.state.u[8])
         cfr_init(rr.state)
+        rr.state.t = 1
         t0 = 1
         if model is not None:
             warm_start_round(model, rr, warm.kappa_r, warm.kappa_s, warm.max_level)
             t0 = warm.t_virtual + 1
         cfr_iterate(rr.state, iters, params, t0=t0)
         average_strategy(rr.state)
-        rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
+        if fresh_state or rr.V is None:
+            rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
         # round value: mean of the iterate values of the iterations run (the
         # paper's g_UTL / NUM_ITER); vacc holds exactly `iters` terms
         rr.state.t = 1 + iters
@@ -312,6 +326,36 @@ def seconds_to_target(deck, start_round: int, roots, target: float, grid: Sequen
             "fallback": False}
 
 
+def iterations_to_target(sv: SubgameSolver, target: float, grid: Sequence[int],
+                         model: Optional[WarmStartMLP] = None, warm: WarmParams = WarmParams()):
+    """seconds_to_target on one built solver (keep_gt=True) reused for every
+    iteration count of the grid: the smallest count whose solve reaches
+    exploitability <= target, and the seconds of that solve (warm start,
+    iterations, average strategies, values; trees and exploitability checks
+    excluded).  A warm start that misses the target on the whole grid falls
+    back to plain DCFR and is charged both."""
+    torch = _torch()
+    spent = 0.0
+    for T in grid:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solve_built(sv, T, model, warm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ex = exploitability(sv)
+        if ex <= target:
+            return {"iters": T, "solve_seconds": el, "exploitability": ex, "fallback": False}
+        if model is not None:
+            spent += el
+    if model is not None:
+        r = iterations_to_target(sv, target, grid, None)
+        if r["iters"] is not None:
+            r["solve_seconds"] += spent
+            r["fallback"] = True
+        return r
+    return {"iters": None, "solve_seconds": None, "exploitability": ex, "fallback": False}
+
+
 def train(model: WarmStartMLP, units: List[Unit], epochs: int, seed: int = 0, lr: float = 2e-3,
           log=None):
     """Adam over shuffled units; lr stepped down at 1/2 and 3/4 of the epochs."""
@@ -329,12 +373,12 @@ def train(model: WarmStartMLP, units: List[Unit], epochs: int, seed: int = 0, lr
 
 
 def training_units(problems, iters: int, parents_per_level: int = 600, seed0: int = 0,
-                   features: str = "edge"):
-    """Solve every (deck, roots) two-round problem with plain DCFR and sample
-    training units from the solution."""
+                   features: str = "edge", start_round: int = 4):
+    """Solve every (deck, roots) problem (two-round by default; start_round 0:
+    full games) with plain DCFR and sample training units from the solution."""
     units = []
     for k, (deck, roots) in enumerate(problems):
-        sv = SubgameSolver(deck, 4, roots, keep_gt=True)
+        sv = SubgameSolver(deck, start_round, roots, keep_gt=True)
         sv.solve(iters)
         units += make_units(sv, seed0 + k, parents_per_level, features)
         sv.free()
@@ -342,10 +386,10 @@ def training_units(problems, iters: int, parents_per_level: int = 600, seed0: in
 
 
 def initial_profile_exploitability(deck, roots, model: Optional[WarmStartMLP],
-                                   features: str = "edge"):
+                                   features: str = "edge", start_round: int = 4):
     """Exploitability of the profile DCFR starts from: uniform, or the
     network's prediction."""
-    sv = SubgameSolver(deck, 4, roots, keep_gt=True)
+    sv = SubgameSolver(deck, start_round, roots, keep_gt=True)
     for rr in sv.rounds:
         rr.state = CfrState(rr.fgt, PASUR_F32)
         cfr_init(rr.state)

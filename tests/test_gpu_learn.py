@@ -107,3 +107,32 @@ def test_round_warm_start_matches_per_level_calls(trained, max_level):
             assert np.array_equal(g_s, init[l]), l
             assert not g_r.any() and not g_b.any(), l
     sv.free()
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_reused_solver_equals_fresh_solve(trained, warm):
+    """solve_built on one solver reused over an iteration grid (the whole-game
+    warm-start measurement) leaves exactly the states, average strategies and
+    round values of a fresh solve of the last count: cfr_init resets every
+    array a longer earlier solve wrote."""
+    pa = require_gpu()
+    import torch
+    from paper_2508_06559_amd import learn
+    model, _ = trained
+    m = model if warm else None
+    wp = learn.WarmParams(max_level=3)
+    deck, roots = synth.two_round_root(20004)
+    sv = pa.SubgameSolver(deck, 4, roots, keep_gt=True)
+    learn.solve_built(sv, 20, m, wp)
+    learn.solve_built(sv, 12, m, wp)
+    ref = learn.solve_subgame(deck, 4, roots, 12, model=m, warm=wp)
+    torch.cuda.synchronize()
+    for a, b in zip(sv.rounds, ref.rounds):
+        assert np.array_equal(to_np(a.V), to_np(b.V)), a.round
+        for l in range(1, 9):
+            for name in ("sigma", "R", "Sbar", "sigma_bar"):
+                assert np.array_equal(to_np(getattr(a.state, name)[l]),
+                                      to_np(getattr(b.state, name)[l])), (a.round, name, l)
+    assert learn.exploitability(sv) == learn.exploitability(ref)
+    sv.free()
+    ref.free()
