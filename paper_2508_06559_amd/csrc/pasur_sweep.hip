@@ -688,15 +688,17 @@ struct UpArgs {
 // regrets, average sums and utilities (coalesced), one thread per parent
 // runs the parent's update over its children in child order (the oracle's
 // loops), and the regrets and average sums leave through LDS (coalesced).
-// The next tile's loads (children, CSR, the parents' reaches) are issued
-// into registers before the current tile is computed.
+// With BND, the tail's heads in the tile (a short list, about one in 37
+// children) then take their next strategy, a thread per head; a per-child
+// test inside the parents' loops would hold nearly every wave for a few
+// heads.  The next tile's loads (children, CSR, the parents' reaches) are
+// issued into registers before the current tile is computed.
 template <class T, bool PAPER, bool BND>
 __global__ void __launch_bounds__(kBlk)
     k_sw_up_tile(int64_t n_tile, const int32_t *__restrict__ ts, const int32_t *__restrict__ tc,
                  UpArgs<T> a, IterK ik, int variant, int rm_mode, double eps) {
   __shared__ T sR[kTile], sS[kTile], su[kTile], ss[kTile];
   __shared__ int32_t scb[kTile + 1];
-  __shared__ int32_t shd[BND ? kTile : 1];  // index among the tail's heads, or -1
   if (PAPER) {
     variant = PASUR_DCFR;
     rm_mode = PASUR_RM_FLOOR;
@@ -749,6 +751,8 @@ __global__ void __launch_bounds__(kBlk)
   if (w < n_tile) fetch(w);
   for (; w < n_tile; w += gridDim.x) {
     const TileMeta m = nm;
+    const int32_t hr0 = phr0, hn = phn;  // the tile's heads: act[hr0 + r], r < hn
+    int32_t hj[kPer];                    // their children within the tile
     T ca[kPer], cbb[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -758,7 +762,6 @@ __global__ void __launch_bounds__(kBlk)
         sS[j] = pS[k];
         su[j] = pu[k];
         if (first) ss[j] = pg[k];
-        if (BND) shd[j] = -1;
       }
       ca[k] = pa[k];
       cbb[k] = pb[k];
@@ -774,7 +777,7 @@ __global__ void __launch_bounds__(kBlk)
       for (int k = 0; k < kPer; ++k)
         if (tid + k * kBlk < phn) {
           su[phj[k]] = phu[k];
-          shd[phj[k]] = phr0 + tid + k * kBlk;
+          hj[k] = phj[k];
         }
     }
     __syncthreads();
@@ -804,26 +807,39 @@ __global__ void __launch_bounds__(kBlk)
       }
       const double opp = a.mover == 0 ? (double)cbb[k] : (double)ca[k];
       const double own = a.mover == 0 ? (double)ca[k] : (double)cbb[k];
-      double sum = 0.0;
 
       for (int j = b; j < e; ++j) {
         const double r = sgn * opp * ((double)su[j] - uh);
-        const T Rs = (T)regret_update<PAPER>((double)sR[j], r, ik, variant);
-        sR[j] = Rs;
-        sum += rm_x((double)Rs, rm_mode, eps);
+        sR[j] = (T)regret_update<PAPER>((double)sR[j], r, ik, variant);
         double add = own * (double)ss[j];
         if (!PAPER && variant == PASUR_CFR_PLUS) add *= ik.avg_t;
         sS[j] = (T)(ik.avg_w * (double)sS[j] + add);
       }
-      if (BND)
-        for (int j = b; j < e; ++j) {
-          const int32_t r = shd[j];
-          if (r >= 0) a.sg_act[r] = (T)sig_from<T>(rm_x((double)sR[j], rm_mode, eps), sum, kk);
-        }
       a.u_par[h] = (T)uh;
       if (a.vacc) a.vacc[h] += uh;
     }
     __syncthreads();
+    if (BND) {
+      // the heads' next strategy from their updated regrets: a thread per
+      // head finds the head's parent in the tile's CSR (binary search) and
+      // takes the regret-matching sum over the siblings in child order
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int r = tid + k * kBlk;
+        if (r >= hn) break;
+        const int j = hj[k];
+        int lo = 0, hi = m.np - 1;  // the parent i with scb[i] <= j < scb[i + 1]
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (scb[mid] <= j) lo = mid;
+          else hi = mid - 1;
+        }
+        const int b = scb[lo], e = scb[lo + 1];
+        double sum = 0.0;
+        for (int q = b; q < e; ++q) sum += rm_x((double)sR[q], rm_mode, eps);
+        a.sg_act[hr0 + r] = (T)sig_from<T>(rm_x((double)sR[j], rm_mode, eps), sum, e - b);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int j = tid + k * kBlk;
