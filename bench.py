@@ -16,7 +16,7 @@ plain DCFR), selfplay (games/s and fair values on a solved full game), es
 (external-sampling CFR on a full game), infoset (infoset rows of a full
 game; strategy models on them), mlp (the network's MFMA kernels alone),
 variants (DCFR, CFR+ and vanilla CFR convergence), copy (counter
-calibration).
+calibration), copy-rate (the HBM rate of a plain device copy).
 
 Prints one JSON line: the metric and its value, the step time, the
 dominant kernel's roofline (achieved algorithmic bytes or FLOPs per second
@@ -53,7 +53,7 @@ TRAFFIC = {
                 "bytes": 1.226e12},
     # the full game's dominant streaming kernel (average over its launches)
     "full-game": {"source": "paper_2508_06559_amd/csrc/pasur_sweep.hip",
-                  "sha256": "254fdc290d0d10bf97cde322f2949b2f51efb72502f91bd862f5dc3f31c37ea4",
+                  "sha256": "bf9e950bc9c6c389f7013d15a33cfb35c7e8e098d859225b340c110ee5a88908",
                   "bytes": 2.134e9},
 }
 
@@ -1201,7 +1201,8 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["two-round", "batched", "warm-start", "full-game",
-                                           "paper-scale", "selfplay", "es", "infoset", "mlp", "variants", "copy"],
+                                           "paper-scale", "selfplay", "es", "infoset", "mlp", "variants", "copy",
+                                           "copy-rate"],
                     default="full-game",
                     help="full-game: the headline configuration (all six rounds of one deal); "
                          "two-round: rounds 5-6 of one deal; batched: 64 deals, rounds 4-6; "
@@ -1262,6 +1263,21 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"workload": "copy", "bytes_per_launch_each_way": 1 << 28, "launches": 4}))
+        return
+    if args.workload == "copy-rate":
+        # the HBM rate a plain device copy reaches (2 GiB each way per launch)
+        x = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(20):
+            y.copy_(x)
+        b.record()
+        b.synchronize()
+        s_ = a.elapsed_time(b) * 1e-3 / 20
+        print(json.dumps({"workload": "copy-rate", "bytes_per_launch": 2 * x.numel() * 4,
+                          "seconds_per_launch": s_, "TB_per_s": 2 * x.numel() * 4 / s_ / 1e12}))
         return
     dtype = pa.PASUR_F32 if args.state == "f32" else pa.PASUR_F64
     T = 4 if args.state == "f32" else 8
