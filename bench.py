@@ -486,10 +486,13 @@ def bench_full(args):
 
 def bench_paper_scale(args):
     """Full games of --deals seeded deals (seeds 1..N) solved together: every
-    round of every game built and unfolded, then one persistent launch per
-    round over all games (a batched plan), 1000 DCFR iterations per round.
-    With the default 32 deals this is about 10^9 FGT nodes, the paper's
-    average per deck, resident in HBM at once."""
+    round of every game built and unfolded, then per round one persistent
+    launch over the games' trees below --stream-min-nodes (a batched plan)
+    and the streaming sweeps for each game's larger tree of that round, 1000
+    DCFR iterations per round.  With the default 32 deals this is about 4e9
+    FGT nodes (1.3e8 per deck on average; the paper reports about 1e9 per
+    deck), all resident in HBM at once.  --stream-min-nodes 0 puts every
+    round in the plan."""
     import torch
     import paper_2508_06559_amd as pa
     import synth
@@ -500,15 +503,17 @@ def bench_paper_scale(args):
     free0, total = torch.cuda.mem_get_info()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b = pa.BatchSolver(probs, 0, iters, dtype=dtype)
+    b = pa.BatchSolver(probs, 0, iters, dtype=dtype,
+                       stream_min_nodes=args.stream_min_nodes if args.stream_min_nodes > 0 else None)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    n_streamed = sum(sum(st) for st in b.streamed)
     used = free0 - torch.cuda.mem_get_info()[0]
     per_deal = [sum(sum(rr.fgt.n) for rr in sv.rounds) for sv in b.deals]
     nodes = sum(per_deal)
     edges = b.edges()
     log(f"[bench] paper scale: {args.deals} full games, {nodes} nodes, built in {build_s:.1f} s, "
-        f"{used / 2**30:.1f} GiB of HBM")
+        f"{used / 2**30:.1f} GiB of HBM, {n_streamed} round trees streamed")
     for w in range(args.warmup):
         b.solve()
         torch.cuda.synchronize()
@@ -527,7 +532,10 @@ def bench_paper_scale(args):
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"paper scale: full games of {args.deals} seeded deals (seeds 1-"
                                   f"{args.deals}) solved as one batch, {nodes} FGT nodes, {iters} DCFR "
-                                  f"iterations per round",
+                                  f"iterations per round; round trees of at least "
+                                  f"{args.stream_min_nodes} nodes ({n_streamed} of "
+                                  f"{args.deals * 6}) on the streaming sweeps, the rest in one "
+                                  f"persistent launch per round",
                       "state": args.state, "nodes": nodes, "nodes_per_deal": per_deal,
                       "hbm_bytes_in_use": used,
                       "build_seconds": build_s, "exploitability_points_first_deals": ex}}
@@ -1210,6 +1218,9 @@ def main():
     ap.add_argument("--train-deals", type=int, default=512)
     ap.add_argument("--test-deals", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--stream-min-nodes", type=int, default=10_000_000,
+                    help="paper-scale: round trees this large run the streaming sweeps "
+                         "(0: every round in the batched plan)")
     ap.add_argument("--full-train-games", type=int, default=48,
                     help="warm-start: seeded full games the full-game network trains on")
     ap.add_argument("--full-test-games", type=int, default=16,

@@ -12,8 +12,8 @@ from __future__ import annotations
 from dataclasses import dataclass
 from typing import List, Optional
 
-from . import (PASUR_F32, PASUR_F64, PLAY_SIGMA_BAR, RM_FLOOR, V_ITERATE_MEAN, V_SIGMA_BAR,
-               ES_FRONTIER, FGT_CHILD_BEGIN, FGT_LINK, FGT_NEXT_ROOTS, ROOT_DTYPE, CfrState,
+from . import (PASUR_F32, PASUR_F64, PLAY_SIGMA_BAR, RM_FLOOR, SCHED_STREAM, V_ITERATE_MEAN,
+               V_SIGMA_BAR, ES_FRONTIER, CfrParams, FGT_CHILD_BEGIN, FGT_LINK, FGT_NEXT_ROOTS, ROOT_DTYPE, CfrState,
                es_iterate, exploitability, selfplay, Plan, UnfoldedTree,
                average_strategy, build_round_tree, cfr_init, cfr_iterate, leaf_utilities,
                paper_params, round_values, roots_to_device, unfold_scores, _torch)
@@ -182,16 +182,25 @@ class BatchSolver:
     persistent launch per round over the trees of all deals (a plan), with
     per-deal leaf utilities, initialisation, average strategies and round
     values around it.  ``capture()`` records the whole backward solve into a
-    HIP graph (torch.cuda.CUDAGraph) so that ``replay()`` is one graph launch."""
+    HIP graph (torch.cuda.CUDAGraph) so that ``replay()`` is one graph launch.
+
+    ``stream_min_nodes``: a deal's round with at least this many FGT nodes
+    is left out of the round's plan and solved on its own with the streaming
+    schedule (whole games, whose late rounds are far larger than a
+    persistent launch keeps busy); such a batch cannot be captured."""
 
     def __init__(self, problems, start_round: int, iters: int, dtype: int = PASUR_F32,
-                 params=None, value_mode: int = V_ITERATE_MEAN):
+                 params=None, value_mode: int = V_ITERATE_MEAN,
+                 stream_min_nodes: Optional[int] = None):
         torch = _torch()
         self.torch = torch
         self.iters = iters
         self.value_mode = value_mode
         self.deals = [SubgameSolver(deck, start_round, roots, dtype=dtype) for deck, roots in problems]
         self.n_rounds = 6 - start_round
+        # per round slot: the deals whose round is streamed (not in the plan)
+        self.streamed = [[stream_min_nodes is not None and sum(sv.rounds[k].fgt.n) >= stream_min_nodes
+                          for sv in self.deals] for k in range(self.n_rounds)]
         for sv in self.deals:
             for rr in sv.rounds:
                 rr.state = CfrState(rr.fgt, dtype)
@@ -201,19 +210,26 @@ class BatchSolver:
 
     def round_states(self):
         """States covered by each round's plan (round slot k = start_round + k)."""
-        return [[sv.rounds[k].state for sv in self.deals] for k in range(self.n_rounds)]
+        return [[sv.rounds[k].state for sv, st in zip(self.deals, self.streamed[k]) if not st]
+                for k in range(self.n_rounds)]
 
     def set_params(self, params=None):
         """One CfrParams for every round, or a list with one per round slot;
         (re)creates the per-round plans."""
         for p in self.plans:
-            p.free()
+            if p is not None:
+                p.free()
         if params is None:
             params = paper_params()
         plist = list(params) if isinstance(params, (list, tuple)) else [params] * self.n_rounds
         self.params = plist
-        self.plans = [Plan(states, plist[k], 1, self.iters)
+        self.plans = [Plan(states, plist[k], 1, self.iters) if states else None
                       for k, states in enumerate(self.round_states())]
+        self.stream_params = []
+        for p in plist:
+            q = CfrParams.from_buffer_copy(p)
+            q.schedule = SCHED_STREAM
+            self.stream_params.append(q)
         self.graph = None
 
     def edges(self) -> int:
@@ -226,7 +242,11 @@ class BatchSolver:
                 V = None if k == self.n_rounds - 1 else sv.rounds[k + 1].V
                 leaf_utilities(rr.fgt, V, rr.state.dtype, rr.state.u[8], stream)
                 cfr_init(rr.state, stream)
-            self.plans[k].iterate(1, self.iters, stream)
+            if self.plans[k] is not None:
+                self.plans[k].iterate(1, self.iters, stream)
+            for sv, st in zip(self.deals, self.streamed[k]):
+                if st:
+                    cfr_iterate(sv.rounds[k].state, self.iters, self.stream_params[k], stream=stream)
             for sv in self.deals:
                 rr = sv.rounds[k]
                 average_strategy(rr.state, stream)
@@ -236,6 +256,9 @@ class BatchSolver:
         self._backward()
 
     def capture(self):
+        if any(any(st) for st in self.streamed):
+            raise ValueError("a batch with streamed rounds cannot be captured (the streaming "
+                             "schedule builds its index and allocates on first use)")
         torch = self.torch
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
@@ -255,7 +278,8 @@ class BatchSolver:
 
     def free(self):
         for p in self.plans:
-            p.free()
+            if p is not None:
+                p.free()
         self.plans = []
         self.graph = None
         for sv in self.deals:

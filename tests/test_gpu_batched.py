@@ -45,6 +45,52 @@ def test_batched_equals_individual_solves(dtype_name, seg_nodes):
     b.free()
 
 
+@pytest.mark.parametrize("which", ["all", "largest"])
+def test_batched_streamed_rounds_equal_per_round_schedules(which):
+    """Rounds at or above stream_min_nodes leave the round's plan and run the
+    streaming schedule deal by deal; every deal then equals its own backward
+    solve with the same schedule per round (streaming sweeps for those
+    rounds, persistent segments for the rest), bit for bit, and such a
+    batch refuses HIP-graph capture."""
+    pa = require_gpu()
+    import torch
+    dtype, iters = pa.PASUR_F32, 300
+    probs = problems([1, 2, 3, 5])
+    sizes = []
+    for deck, roots in probs:
+        sv = pa.SubgameSolver(deck, 4, roots, dtype=dtype)
+        sizes.append([sum(rr.fgt.n) for rr in sv.rounds])
+        sv.free()
+    # "largest": only the round-6 tree of the largest deal is streamed
+    thr = 1 if which == "all" else max(sz[1] for sz in sizes)
+    print(f"[batched] streamed rounds ({which}): threshold {thr}, sizes {sizes}", flush=True)
+    b = pa.BatchSolver(probs, 4, iters, dtype=dtype, stream_min_nodes=thr)
+    assert any(any(st) for st in b.streamed)
+    b.solve()
+    torch.cuda.synchronize()
+    for (deck, roots), sv, sz in zip(probs, b.deals, sizes):
+        ref = pa.SubgameSolver(deck, 4, roots, dtype=dtype)
+        V = None
+        for k in (1, 0):
+            rr = ref.rounds[k]
+            rr.state = pa.CfrState(rr.fgt, dtype)
+            pa.leaf_utilities(rr.fgt, V, dtype, rr.state.u[8])
+            pa.cfr_init(rr.state)
+            sched = pa.SCHED_STREAM if sz[k] >= thr else pa.SCHED_AUTO
+            pa.cfr_iterate(rr.state, iters, pa.paper_params(sched))
+            pa.average_strategy(rr.state)
+            rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
+            pa.round_values(rr.state, pa.V_ITERATE_MEAN, rr.V)
+            V = rr.V
+        torch.cuda.synchronize()
+        for x, y in zip(state_arrays(sv.rounds), state_arrays(ref.rounds)):
+            assert np.array_equal(x, y)
+        ref.free()
+    with pytest.raises(ValueError, match="captured"):
+        b.capture()
+    b.free()
+
+
 def test_graph_replays_match_eager():
     pa = require_gpu()
     import torch
