@@ -457,9 +457,11 @@ int pasur_gemm_bf16(int M, int N, int K, const uint16_t *A, int64_t sar, int64_t
                     const uint16_t *B, int64_t sbr, int64_t sbc, float *Cf, uint16_t *Cb,
                     int64_t ldc, const float *bias, int relu, void *stream);
 /* Forward for M rows of X [M][192] (BF16): H1, H2 [M][256] (BF16, after
- * ReLU), Y [M][2] (FP32: logit, value).  With H2 16-byte aligned the output
- * layer runs as two dot products per row, else as a GEMM (same arithmetic,
- * FP32 accumulation in another order). */
+ * ReLU), Y [M][2] (FP32: logit, value).  With X, H1 and H2 16-byte aligned
+ * all three layers run in the fused kernel of pasur_mlp_infer, which also
+ * writes H1 and H2 (uses stream-ordered scratch for the transposed weights
+ * unless w carries them); otherwise two GEMMs and the output layer (same
+ * arithmetic, FP32 accumulation in another order). */
 int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
                       uint16_t *H1, uint16_t *H2, float *Y, void *stream);
 /* Inference only: Y [M][2] (FP32) for M rows of X [M][192] (BF16), the same

@@ -785,7 +785,22 @@ __device__ __forceinline__ void infer_layer(const __bf16 *__restrict__ Wt, const
   __syncthreads();
 }
 
-template <int WAVES, int DEPTH>
+// A tile's hidden layer (IM rows of Hs, LDS) to H [M][256] in global memory
+// as 16-byte row pieces, rows below M only.
+template <int NT>
+__device__ __forceinline__ void store_hidden(const __bf16 *Hs, __bf16 *__restrict__ H, int m0,
+                                             int M, int tid) {
+  for (int e = tid; e < IM * (kHid / 8); e += NT) {
+    const int r = e / (kHid / 8), c = (e % (kHid / 8)) * 8;
+    if (m0 + r < M)
+      *reinterpret_cast<bf16x8 *>(H + (int64_t)(m0 + r) * kHid + c) =
+          *reinterpret_cast<const bf16x8 *>(Hs + r * HS + c);
+  }
+}
+
+// STORE: the training forward pass, which also writes H1 and H2 (for the
+// backward pass) from LDS as they are formed.
+template <int WAVES, int DEPTH, bool STORE>
 __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *__restrict__ X,
                                                    const __bf16 *__restrict__ W1t,
                                                    const float *__restrict__ b1,
@@ -793,7 +808,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *_
                                                    const float *__restrict__ b2,
                                                    const __bf16 *__restrict__ W3,
                                                    const float *__restrict__ b3,
-                                                   float *__restrict__ Y) {
+                                                   float *__restrict__ Y, __bf16 *__restrict__ H1,
+                                                   __bf16 *__restrict__ H2) {
   extern __shared__ __align__(16) unsigned char smem[];
   __bf16 *Xs = reinterpret_cast<__bf16 *>(smem);          // [IM][XS]
   __bf16 *Hs = Xs + IM * XS;                               // [IM][HS]
@@ -814,7 +830,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *_
   __syncthreads();
   const int n_base = wave * 16 * TA;   // this wave's output features
   infer_layer<kIn, TA, TB, DEPTH>(W1t, Xs, XS, b1, Hs, n_base, lane);   // H1 in Hs
+  // (layer 2 reads Hs and passes a barrier before it overwrites it)
+  if (STORE) store_hidden<NT>(Hs, H1, m0, M, tid);
   infer_layer<kHid, TA, TB, DEPTH>(W2t, Hs, HS, b2, Hs, n_base, lane);  // H2 in Hs
+  if (STORE) store_hidden<NT>(Hs, H2, m0, M, tid);
   // last layer (256 -> 2) on the matrix cores as well: wave v < IM/16 takes
   // rows 16v..16v+15; the A operand is W3 transposed and padded to 16
   // outputs (rows 2..15 zero), built from W3 in registers; outputs 0 and 1
@@ -922,6 +941,12 @@ extern "C" int pasur_gemm_bf16(int M, int N, int K, const uint16_t *A, int64_t s
   return gemm(g, 1, (hipStream_t)stream);
 }
 
+namespace {
+template <bool STORE>
+int fused_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M, float *Y, uint16_t *H1,
+                  uint16_t *H2, hipStream_t s);
+}  // namespace
+
 extern "C" int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
                                  uint16_t *H1, uint16_t *H2, float *Y, void *stream) {
   if (!w || !X || !H1 || !H2 || !Y || M < 0 || M > INT32_MAX) {
@@ -930,6 +955,10 @@ extern "C" int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, 
   }
   if (M == 0) return PASUR_OK;
   hipStream_t s = (hipStream_t)stream;
+  if (((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(H1) |
+        reinterpret_cast<uintptr_t>(H2)) & 15) == 0)
+    // all three layers in the fused kernel, H1 and H2 written from LDS
+    return fused_forward<true>(w, X, M, Y, H1, H2, s);
   const int m = (int)M;
   PASUR_TRY(pasur_gemm_bf16(m, kHid, kIn, X, kIn, 1, w->W1, kHid, 1, nullptr, H1, kHid, w->b1, 1, s));
   PASUR_TRY(pasur_gemm_bf16(m, kHid, kHid, H1, kHid, 1, w->W2, kHid, 1, nullptr, H2, kHid, w->b2, 1, s));
@@ -1329,14 +1358,15 @@ extern "C" int pasur_mlp_transpose(const pasur_mlp_weights *w, uint16_t *W1t, ui
   return PASUR_OK;
 }
 
-extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
-                               float *Y, void *stream) {
-  if (!w || !X || !Y || M < 0 || M > INT32_MAX) {
-    set_error("bad MLP inference arguments");
-    return PASUR_E_INVAL;
-  }
-  if (M == 0) return PASUR_OK;
-  hipStream_t s = (hipStream_t)stream;
+namespace {
+
+// The fused kernel over M > 0 rows (inference, or with STORE the training
+// forward that also writes H1 and H2): transposed weights from the caller's
+// cache, else transposed here into stream-ordered scratch.
+template <bool STORE>
+int fused_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M, float *Y, uint16_t *H1,
+                  uint16_t *H2, hipStream_t s) {
+  auto kern = k_mlp_infer<kInferWaves, kInferDepth, STORE>;
   // the kernel's LDS exceeds the default limit: raise it once per device
   static std::once_flag lds_once[kMaxDevices];
   static hipError_t lds_err[kMaxDevices];
@@ -1347,11 +1377,11 @@ extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, in
     return PASUR_E_RANGE;
   }
   std::call_once(lds_once[dev], [&] {
-    lds_err[dev] = hipFuncSetAttribute((const void *)k_mlp_infer<kInferWaves, kInferDepth>,
+    lds_err[dev] = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInferLds);
   });
   if (lds_err[dev] != hipSuccess) {
-    set_error("MLP inference LDS: %s", hipGetErrorString(lds_err[dev]));
+    set_error("MLP fused forward LDS: %s", hipGetErrorString(lds_err[dev]));
     return PASUR_E_HIP;
   }
   __bf16 *Wt = nullptr;
@@ -1360,7 +1390,7 @@ extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, in
   if (!W1t || !W2t) {
     e = hipMallocAsync((void **)&Wt, sizeof(__bf16) * (size_t)(kIn + kHid) * kHid, s);
     if (e != hipSuccess) {
-      set_error("MLP inference workspace: %s", hipGetErrorString(e));
+      set_error("MLP fused forward workspace: %s", hipGetErrorString(e));
       return PASUR_E_NOMEM;
     }
     W1t = Wt;
@@ -1369,13 +1399,26 @@ extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, in
     k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid,
                                                          Wt + (size_t)kIn * kHid);
   }
-  k_mlp_infer<kInferWaves, kInferDepth><<<(unsigned)((M + IM - 1) / IM), 64 * kInferWaves, kInferLds, s>>>(
-      (int)M, (const __bf16 *)X, W1t, w->b1, W2t, w->b2, (const __bf16 *)w->W3, w->b3, Y);
+  kern<<<(unsigned)((M + IM - 1) / IM), 64 * kInferWaves, kInferLds, s>>>(
+      (int)M, (const __bf16 *)X, W1t, w->b1, W2t, w->b2, (const __bf16 *)w->W3, w->b3, Y,
+      (__bf16 *)H1, (__bf16 *)H2);
   e = hipGetLastError();
   if (Wt) (void)hipFreeAsync(Wt, s);
   if (e != hipSuccess) {
-    set_error("MLP inference: %s", hipGetErrorString(e));
+    set_error("MLP fused forward: %s", hipGetErrorString(e));
     return PASUR_E_HIP;
   }
   return PASUR_OK;
+}
+
+}  // namespace
+
+extern "C" int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
+                               float *Y, void *stream) {
+  if (!w || !X || !Y || M < 0 || M > INT32_MAX) {
+    set_error("bad MLP inference arguments");
+    return PASUR_E_INVAL;
+  }
+  if (M == 0) return PASUR_OK;
+  return fused_forward<false>(w, X, M, Y, nullptr, nullptr, (hipStream_t)stream);
 }
