@@ -365,64 +365,6 @@ __global__ void __launch_bounds__(64) k_col_merge(const float *__restrict__ part
   if (lane == 0) out[n] = s;
 }
 
-// Backward of the second ReLU layer: dH2 = (dY W3^T) * (H2 > 0) in BF16, the
-// output layer's gradient formed here (dY rounded to BF16, the two products
-// added in FP32), and db2's column sums of dH2 over row chunk blockIdx.x into
-// part[chunk][n] (k_col_merge adds the chunks).  Wave w takes rows r0 + w,
-// r0 + w + 4, ... in order; lane l columns 4l .. 4l+3 (one row per wave
-// step); the four waves' sums are added in wave order, so the result is
-// deterministic.
-__global__ void __launch_bounds__(256) k_relu_back_colsum(const float *__restrict__ dY,
-                                                          const __bf16 *__restrict__ W3,
-                                                          const __bf16 *__restrict__ H, int64_t M,
-                                                          int64_t chunk, __bf16 *__restrict__ outb,
-                                                          float *__restrict__ part) {
-  static_assert(kHid == 256 && kOut == 2, "one wave spans a row of 4 x 64 columns");
-  __shared__ float4 red[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(M, r0 + chunk);
-  float w3[4][2];
-  for (int j = 0; j < 4; ++j) {
-    w3[j][0] = (float)W3[(4 * lane + j) * kOut];
-    w3[j][1] = (float)W3[(4 * lane + j) * kOut + 1];
-  }
-  float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
-  for (int64_t m = r0 + w; m < r1; m += 4) {
-    const int64_t i = m * kHid + 4 * lane;
-    float4 g;
-    const float y0 = (float)(__bf16)dY[2 * m], y1 = (float)(__bf16)dY[2 * m + 1];
-    g.x = y0 * w3[0][0] + y1 * w3[0][1];
-    g.y = y0 * w3[1][0] + y1 * w3[1][1];
-    g.z = y0 * w3[2][0] + y1 * w3[2][1];
-    g.w = y0 * w3[3][0] + y1 * w3[3][1];
-    const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H + i);
-    const float vx = (float)h[0] > 0.f ? g.x : 0.f, vy = (float)h[1] > 0.f ? g.y : 0.f;
-    const float vz = (float)h[2] > 0.f ? g.z : 0.f, vw = (float)h[3] > 0.f ? g.w : 0.f;
-    sx += vx;
-    sy += vy;
-    sz += vz;
-    sw += vw;
-    bf16x4 b;
-    b[0] = (__bf16)vx;
-    b[1] = (__bf16)vy;
-    b[2] = (__bf16)vz;
-    b[3] = (__bf16)vw;
-    *reinterpret_cast<bf16x4 *>(outb + i) = b;
-  }
-  red[w][lane] = make_float4(sx, sy, sz, sw);
-  __syncthreads();
-  if (w == 0) {
-    float4 t = red[0][lane];
-    for (int k = 1; k < 4; ++k) {
-      const float4 u = red[k][lane];
-      t.x += u.x;
-      t.y += u.y;
-      t.z += u.z;
-      t.w += u.w;
-    }
-    *reinterpret_cast<float4 *>(part + (int64_t)blockIdx.x * kHid + 4 * lane) = t;
-  }
-}
 
 // Output layer (kHid -> kOut = 2) of the forward pass: Y[m] = H2[m] W3 + b3
 // with FP32 accumulation.  Half a wave per row: lane l of the half reads
@@ -465,28 +407,42 @@ __global__ void __launch_bounds__(256) k_out_forward(const __bf16 *__restrict__ 
   }
 }
 
-// Output-layer gradients, partial sums over row chunk blockIdx.x:
-// dW3[k][o] = sum_m H2[m][k] dY[m][o] (dY rounded to BF16, as the layer's
-// other products) into part[chunk][2k + o], and db3[o] = sum_m dY[m][o]
-// (FP32) into partb[chunk][o]; k_col_merge adds the chunks.  Wave w takes rows
-// r0 + w, r0 + w + 4, ... in order, lane l the features 4l .. 4l+3; the four
-// waves' sums are added in wave order.
-__global__ void __launch_bounds__(256) k_out_backward_part(const __bf16 *__restrict__ H2,
-                                                           const float *__restrict__ dY, int64_t M,
-                                                           int64_t chunk, float *__restrict__ part,
-                                                           float *__restrict__ partb) {
+// The output layer's backward and the second ReLU layer's, in one pass over
+// row chunk blockIdx.x of H2 and dY (dY rounded to BF16 for the products):
+//   dW3[k][o] = sum_m H2[m][k] dY[m][o] into part3[chunk][2k + o] and
+//   db3[o] = sum_m dY[m][o] (FP32) into partb[chunk][o];
+//   dH2 = (dY W3^T) * (H2 > 0) in BF16 (the two products added in FP32) and
+//   db2's column sums of dH2 into partr[chunk][n].
+// k_col_merge adds the chunks.  Wave w takes rows r0 + w, r0 + w + 4, ... in
+// order, lane l the features 4l .. 4l+3; the four waves' sums are added in
+// wave order.
+__global__ void __launch_bounds__(256) k_out_relu_back(const __bf16 *__restrict__ H2,
+                                                       const float *__restrict__ dY,
+                                                       const __bf16 *__restrict__ W3, int64_t M,
+                                                       int64_t chunk, float *__restrict__ part3,
+                                                       float *__restrict__ partb,
+                                                       __bf16 *__restrict__ G2,
+                                                       float *__restrict__ partr) {
   static_assert(kHid == 256 && kOut == 2, "one wave spans a row of 4 x 64 features");
   __shared__ float red[4][64][8];
+  __shared__ float4 redr[4][64];
   __shared__ float redb[4][2];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(M, r0 + chunk);
+  float w3[4][2];
+  for (int j = 0; j < 4; ++j) {
+    w3[j][0] = (float)W3[(4 * lane + j) * kOut];
+    w3[j][1] = (float)W3[(4 * lane + j) * kOut + 1];
+  }
   float acc[8];
   for (int i = 0; i < 8; ++i) acc[i] = 0.f;
   float sb0 = 0.f, sb1 = 0.f;
+  float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
   for (int64_t m = r0 + w; m < r1; m += 4) {
+    const int64_t i = m * kHid + 4 * lane;
     const float y0 = dY[2 * m], y1 = dY[2 * m + 1];
     const float q0 = (float)(__bf16)y0, q1 = (float)(__bf16)y1;
-    const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H2 + m * kHid + 4 * lane);
+    const bf16x4 h = *reinterpret_cast<const bf16x4 *>(H2 + i);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       acc[2 * j] += (float)h[j] * q0;
@@ -494,8 +450,26 @@ __global__ void __launch_bounds__(256) k_out_backward_part(const __bf16 *__restr
     }
     sb0 += y0;
     sb1 += y1;
+    float4 g;
+    g.x = q0 * w3[0][0] + q1 * w3[0][1];
+    g.y = q0 * w3[1][0] + q1 * w3[1][1];
+    g.z = q0 * w3[2][0] + q1 * w3[2][1];
+    g.w = q0 * w3[3][0] + q1 * w3[3][1];
+    const float vx = (float)h[0] > 0.f ? g.x : 0.f, vy = (float)h[1] > 0.f ? g.y : 0.f;
+    const float vz = (float)h[2] > 0.f ? g.z : 0.f, vw = (float)h[3] > 0.f ? g.w : 0.f;
+    sx += vx;
+    sy += vy;
+    sz += vz;
+    sw += vw;
+    bf16x4 b;
+    b[0] = (__bf16)vx;
+    b[1] = (__bf16)vy;
+    b[2] = (__bf16)vz;
+    b[3] = (__bf16)vw;
+    *reinterpret_cast<bf16x4 *>(G2 + i) = b;
   }
   for (int i = 0; i < 8; ++i) red[w][lane][i] = acc[i];
+  redr[w][lane] = make_float4(sx, sy, sz, sw);
   if (lane == 0) {
     redb[w][0] = sb0;
     redb[w][1] = sb1;
@@ -505,13 +479,23 @@ __global__ void __launch_bounds__(256) k_out_backward_part(const __bf16 *__restr
     for (int i = 0; i < 8; ++i) {
       float t = red[0][lane][i];
       for (int k = 1; k < 4; ++k) t += red[k][lane][i];
-      part[(int64_t)blockIdx.x * (kHid * kOut) + 8 * lane + i] = t;
+      part3[(int64_t)blockIdx.x * (kHid * kOut) + 8 * lane + i] = t;
     }
     if (lane < kOut) {
       float t = redb[0][lane];
       for (int k = 1; k < 4; ++k) t += redb[k][lane];
       partb[(int64_t)blockIdx.x * kOut + lane] = t;
     }
+  } else if (w == 1) {
+    float4 t = redr[0][lane];
+    for (int k = 1; k < 4; ++k) {
+      const float4 u = redr[k][lane];
+      t.x += u.x;
+      t.y += u.y;
+      t.z += u.z;
+      t.w += u.w;
+    }
+    *reinterpret_cast<float4 *>(partr + (int64_t)blockIdx.x * kHid + 4 * lane) = t;
   }
 }
 
@@ -1026,15 +1010,15 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
   };
   const int64_t rchunk = (M + kColChunks - 1) / kColChunks;
   if (!st) {
-    // layer 3: dW3 = H2^T dY, db3 = colsum dY (one pass over the rows)
+    // layer 3: dW3 = H2^T dY, db3 = colsum dY; dH2 = (dY W3^T) masked by
+    // H2 > 0, in BF16, and db2 = its column sums (one pass over the rows)
     float *part3 = part, *partb = part + (size_t)kColChunks * kHid * kOut;
-    k_out_backward_part<<<kColChunks, 256, 0, s>>>((const __bf16 *)H2, dY, M, rchunk, part3, partb);
+    float *partr = partb + (size_t)kColChunks * kOut;
+    k_out_relu_back<<<kColChunks, 256, 0, s>>>((const __bf16 *)H2, dY, (const __bf16 *)w->W3, M,
+                                               rchunk, part3, partb, G2b, partr);
     k_col_merge<<<kHid * kOut, 64, 0, s>>>(part3, kColChunks, kHid * kOut, gr->dW3);
     k_col_merge<<<kOut, 64, 0, s>>>(partb, kColChunks, kOut, gr->db3);
-    // dH2 = (dY W3^T) masked by H2 > 0, in BF16, and db2 = its column sums
-    k_relu_back_colsum<<<kColChunks, 256, 0, s>>>(dY, (const __bf16 *)w->W3, (const __bf16 *)H2, M,
-                                                  rchunk, G2b, part);
-    k_col_merge<<<kHid, 64, 0, s>>>(part, kColChunks, kHid, gr->db2);
+    k_col_merge<<<kHid, 64, 0, s>>>(partr, kColChunks, kHid, gr->db2);
     st = dW((const __bf16 *)H1, kHid, G2b, kHid, gr->dW2);
   }
   if (!st) {
