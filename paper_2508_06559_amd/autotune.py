@@ -14,10 +14,11 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 from . import CfrState, Plan, paper_params, _torch
 
-DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = (
-    (256, 0), (512, 0), (1024, 0),
-    (1024, 4096), (1024, 8192), (1024, 16384), (512, 8192),
-)
+# threads per workgroup x root-run length (0: one root per segment; a run
+# also stops at the workgroup's thread count and at its LDS budget)
+BLOCKS: Tuple[int, ...] = (256, 512, 1024)
+SEG_NODES: Tuple[int, ...] = (0, 2048, 4096, 8192, 16384, 32768)
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((b, g) for b in BLOCKS for g in SEG_NODES)
 
 
 def time_plan(states: Sequence[CfrState], block: int, seg_nodes: int, iters: int) -> float:
@@ -39,6 +40,9 @@ def autotune(rounds_states: List[Sequence[CfrState]], candidates=DEFAULT_CANDIDA
     """rounds_states[k] = the states one plan of round k covers."""
     result = {"candidates": [list(c) for c in candidates], "iters_timed": iters, "rounds": []}
     for k, states in enumerate(rounds_states):
+        if not states:  # every tree of the round is streamed: no plan to tune
+            result["rounds"].append({"slot": k, "best": None, "timings": []})
+            continue
         timings = []
         for block, seg in candidates:
             ms = time_plan(states, block, seg, iters)
@@ -55,4 +59,4 @@ def autotune(rounds_states: List[Sequence[CfrState]], candidates=DEFAULT_CANDIDA
 
 def params_from(result: Dict) -> List:
     return [paper_params(block=r["best"]["block"], seg_nodes=r["best"]["seg_nodes"])
-            for r in result["rounds"]]
+            if r["best"] is not None else paper_params() for r in result["rounds"]]

@@ -91,6 +91,39 @@ def test_batched_streamed_rounds_equal_per_round_schedules(which):
     b.free()
 
 
+def test_autotune_keeps_fastest_and_results():
+    """The autotuner times every candidate of every round, keeps the
+    fastest, and the batch solved with its schedule equals the deals solved
+    one by one (every segment schedule gives the same bits)."""
+    pa = require_gpu()
+    import torch
+    from paper_2508_06559_amd import autotune
+    probs = problems([1, 2, 3, 5])
+    b = pa.BatchSolver(probs, 4, 200, dtype=pa.PASUR_F32)
+    cands = ((256, 0), (1024, 0), (1024, 4096), (512, 2048))
+    res = autotune.autotune(b.round_states(), candidates=cands, iters=3)
+    assert len(res["rounds"]) == 2
+    for r in res["rounds"]:
+        assert len(r["timings"]) == len(cands)
+        assert r["best"] == min(r["timings"], key=lambda x: x["ms_per_iter"])
+        assert all(t["ms_per_iter"] > 0 for t in r["timings"])
+    b.set_params(autotune.params_from(res))
+    for k, r in enumerate(res["rounds"]):
+        assert (b.params[k].block, b.params[k].seg_nodes) == (r["best"]["block"],
+                                                             r["best"]["seg_nodes"])
+    b.solve()
+    torch.cuda.synchronize()
+    for (deck, roots), sv in zip(probs, b.deals):
+        ref = pa.SubgameSolver(deck, 4, roots, dtype=pa.PASUR_F32)
+        ref.solve(200)
+        torch.cuda.synchronize()
+        for x, y in zip(state_arrays(sv.rounds), state_arrays(ref.rounds)):
+            assert np.array_equal(x, y)
+        ref.free()
+    assert len(autotune.DEFAULT_CANDIDATES) == 18
+    b.free()
+
+
 def test_graph_replays_match_eager():
     pa = require_gpu()
     import torch
