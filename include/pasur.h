@@ -491,6 +491,14 @@ int pasur_sgd_step(float *w, const float *g, uint16_t *w_bf16, int64_t n, float 
 /* Adam on an FP32 master array; refreshes its BF16 copy when w_bf16 != NULL. */
 int pasur_adam_step(float *w, const float *g, float *m, float *v, uint16_t *w_bf16, int64_t n,
                     float lr, float beta1, float beta2, float eps, int64_t step, void *stream);
+/* Adam over 1..8 FP32 master arrays in one launch, the same arithmetic per
+ * element as pasur_adam_step: array t has n[t] elements at w[t], g[t], m[t],
+ * v[t] and a BF16 copy at w_bf16[t] (w_bf16 or an entry NULL: none).  The
+ * pointer arrays are host memory, the arrays they name device memory. */
+int pasur_adam_step_multi(int count, float *const w[], const float *const g[], float *const m[],
+                          float *const v[], uint16_t *const w_bf16[], const int64_t n[],
+                          float lr, float beta1, float beta2, float eps, int64_t step,
+                          void *stream);
 /* Feature rows (BF16 [n][192]) of FGT nodes of `level`: the nodes d_edges[i]
  * (device) or, with d_edges NULL, all n = n[level] nodes in order.  `gt` must
  * be the game tree `fgt` was unfolded from.  Columns: 0..51 Alex's hand,

@@ -109,6 +109,8 @@ def lib():
         L.pasur_mlp_loss.argtypes = [vp, vp, vp, vp, i64, i64, C.c_float, vp, vp, vp]
         L.pasur_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
                                       C.c_float, i64, vp]
+        L.pasur_adam_step_multi.argtypes = [i32, vp, vp, vp, vp, vp, vp, C.c_float, C.c_float,
+                                            C.c_float, C.c_float, i64, vp]
         L.pasur_edge_features.argtypes = [vp, vp, i32, vp, i64, vp, vp]
         L.pasur_sample_parents.argtypes = [vp, i32, C.c_uint64, C.c_double, vp, vp,
                                            C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
@@ -504,6 +506,16 @@ def mlp_loss(Y, tsig, tval, seg, n_par, n_rows, value_weight, dY, loss, stream=N
 def adam_step(w, g, m, v, wb, lr, b1, b2, eps, step, stream=None):
     _check(lib().pasur_adam_step(_p(w), _p(g), _p(m), _p(v), _p(wb), w.numel(), lr, b1, b2, eps,
                                  step, _stream(stream)), "pasur_adam_step")
+
+
+def adam_step_multi(ws, gs, ms, vs, wbs, lr, b1, b2, eps, step, stream=None):
+    """pasur_adam_step_multi: one launch over the arrays of the lists (wbs
+    entries may be None)."""
+    k = len(ws)
+    arr = lambda ts: (C.c_void_p * k)(*[None if t is None else t.data_ptr() for t in ts])
+    n = (C.c_int64 * k)(*[t.numel() for t in ws])
+    _check(lib().pasur_adam_step_multi(k, arr(ws), arr(gs), arr(ms), arr(vs), arr(wbs), n, lr, b1,
+                                       b2, eps, step, _stream(stream)), "pasur_adam_step_multi")
 
 
 def edge_features(gt: GameTree, fgt: UnfoldedTree, level: int, edges, n: int, X, stream=None):

@@ -609,11 +609,11 @@ __global__ void k_loss(int64_t n_par, const int32_t *__restrict__ seg, const flo
   loss[2 * p + 1] = lv * inv_r;
 }
 
-__global__ void k_adam(int64_t n, float *__restrict__ w, const float *__restrict__ g,
-                       float *__restrict__ m, float *__restrict__ v, __bf16 *__restrict__ wb,
-                       float lr, float b1, float b2, float eps, float c1, float c2) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// One Adam element: moments, master weight and its BF16 copy.
+__device__ __forceinline__ void adam_elem(int64_t i, float *__restrict__ w,
+                                          const float *__restrict__ g, float *__restrict__ m,
+                                          float *__restrict__ v, __bf16 *__restrict__ wb, float lr,
+                                          float b1, float b2, float eps, float c1, float c2) {
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.f - b1) * gi;
   const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -622,6 +622,36 @@ __global__ void k_adam(int64_t n, float *__restrict__ w, const float *__restrict
   const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   w[i] = wi;
   if (wb) wb[i] = (__bf16)wi;
+}
+
+__global__ void k_adam(int64_t n, float *__restrict__ w, const float *__restrict__ g,
+                       float *__restrict__ m, float *__restrict__ v, __bf16 *__restrict__ wb,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  adam_elem(i, w, g, m, v, wb, lr, b1, b2, eps, c1, c2);
+}
+
+// Up to kAdamMax arrays in one launch: array t covers flat elements
+// off[t] .. off[t+1]-1.
+constexpr int kAdamMax = 8;
+struct AdamSet {
+  int count;
+  int64_t off[kAdamMax + 1];
+  float *w[kAdamMax];
+  const float *g[kAdamMax];
+  float *m[kAdamMax];
+  float *v[kAdamMax];
+  __bf16 *wb[kAdamMax];
+};
+
+__global__ void k_adam_multi(AdamSet a, float lr, float b1, float b2, float eps, float c1,
+                             float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.off[a.count]) return;
+  int t = 0;
+  while (t + 1 < a.count && i >= a.off[t + 1]) ++t;
+  adam_elem(i - a.off[t], a.w[t], a.g[t], a.m[t], a.v[t], a.wb[t], lr, b1, b2, eps, c1, c2);
 }
 
 __global__ void k_sgd(int64_t n, float *__restrict__ w, const float *__restrict__ g,
@@ -1075,6 +1105,38 @@ extern "C" int pasur_adam_step(float *w, const float *g, float *m, float *v, uin
   const float c2 = 1.f - std::pow(beta2, (float)step);
   k_adam<<<blocks(n), 256, 0, (hipStream_t)stream>>>(n, w, g, m, v, (__bf16 *)w_bf16, lr, beta1,
                                                      beta2, eps, c1, c2);
+  PASUR_TRY_HIP(hipGetLastError());
+  return PASUR_OK;
+}
+
+extern "C" int pasur_adam_step_multi(int count, float *const w[], const float *const g[],
+                                     float *const m[], float *const v[], uint16_t *const w_bf16[],
+                                     const int64_t n[], float lr, float beta1, float beta2,
+                                     float eps, int64_t step, void *stream) {
+  if (count < 1 || count > kAdamMax || !w || !g || !m || !v || !n || step < 1) {
+    set_error("bad multi-array Adam arguments (1..%d arrays)", kAdamMax);
+    return PASUR_E_INVAL;
+  }
+  AdamSet a;
+  std::memset(&a, 0, sizeof(a));
+  a.count = count;
+  for (int t = 0; t < count; ++t) {
+    if (!w[t] || !g[t] || !m[t] || !v[t] || n[t] < 0) {
+      set_error("bad Adam array %d", t);
+      return PASUR_E_INVAL;
+    }
+    a.off[t + 1] = a.off[t] + n[t];
+    a.w[t] = w[t];
+    a.g[t] = g[t];
+    a.m[t] = m[t];
+    a.v[t] = v[t];
+    a.wb[t] = w_bf16 ? (__bf16 *)w_bf16[t] : nullptr;
+  }
+  if (a.off[count] == 0) return PASUR_OK;
+  const float c1 = 1.f - std::pow(beta1, (float)step);
+  const float c2 = 1.f - std::pow(beta2, (float)step);
+  k_adam_multi<<<blocks(a.off[count]), 256, 0, (hipStream_t)stream>>>(a, lr, beta1, beta2, eps, c1,
+                                                                        c2);
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
 }

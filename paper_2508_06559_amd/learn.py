@@ -21,7 +21,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import (FGT_PARENT, INFOSET_MLP, INFOSET_WIDTH, PASUR_F32, PASUR_F64, MlpGrads, MlpWeights,
-               CfrState, adam_step, average_strategy, infoset_rows,
+               CfrState, adam_step_multi, average_strategy, infoset_rows,
                cfr_init, cfr_iterate, cfr_warm_init, edge_features, gather_f32, leaf_utilities,
                mlp_backward, mlp_forward, mlp_infer, mlp_loss, paper_params, round_values, sample_parents,
                shift_i32, mlp_transpose, warm_start_round as _warm_start_round,
@@ -139,9 +139,8 @@ class WarmStartMLP:
         mlp_loss(b["Y"], u.tsig, u.tval, u.seg, u.n_par, u.n_rows, value_weight, b["dY"], loss)
         mlp_backward(w, u.X, b["H1"], b["H2"], b["dY"], u.n_rows, self.grads())
         self.step += 1
-        for k in range(6):
-            adam_step(self.master[k], self.g[k], self.m[k], self.v[k], self.bf.get(k), lr,
-                      betas[0], betas[1], eps, self.step)
+        adam_step_multi(self.master, self.g, self.m, self.v, [self.bf.get(k) for k in range(6)], lr,
+                        betas[0], betas[1], eps, self.step)
         self._version += 1
         return loss
 

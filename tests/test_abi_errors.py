@@ -128,6 +128,19 @@ def test_mlp_checks(lib):
                    C.c_int64, vp]
     expect(lib, ad(DUMMY, DUMMY, DUMMY, DUMMY, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None),
            E_INVAL, ["Adam"])
+    am = lib.pasur_adam_step_multi
+    am.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float,
+                   C.c_int64, vp]
+    ptrs = (vp * 9)(*([DUMMY] * 9))
+    ns = (C.c_int64 * 9)(*([4] * 9))
+    for count in (0, 9):
+        expect(lib, am(count, ptrs, ptrs, ptrs, ptrs, None, ns, 1e-3, 0.9, 0.999, 1e-8, 1, None),
+               E_INVAL, ["1..8 arrays"])
+    holes = (vp * 2)(DUMMY, None)
+    expect(lib, am(2, ptrs, ptrs, holes, ptrs, None, ns, 1e-3, 0.9, 0.999, 1e-8, 1, None),
+           E_INVAL, ["array 1"])
+    expect(lib, am(2, ptrs, ptrs, ptrs, ptrs, None, ns, 1e-3, 0.9, 0.999, 1e-8, 0, None),
+           E_INVAL, ["1..8 arrays"])
 
 
 def test_selfplay_checks(lib):

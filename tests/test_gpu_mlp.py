@@ -289,3 +289,31 @@ def test_mlp_infer_full_size_sampled():
     (_, _, Yo), (_, _, bY) = forward_bounds(W, X[idx].astype(np.float64))
     Yi = to_np(Y)[idx].astype(np.float64)
     assert np.all(np.abs(Yi - Yo) <= bY)
+
+
+def test_adam_multi_equals_per_array_steps():
+    """One multi-array Adam launch gives every array exactly what its own
+    pasur_adam_step call gives (moments, master weights, BF16 copies),
+    arrays of uneven sizes, one without a BF16 copy."""
+    pa = require_gpu()
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(5)
+    sizes = [192 * 256, 256, 7, 256 * 256 + 3]
+    def mk():
+        return [torch.randn(n, generator=g).cuda() for n in sizes]
+    w, gr, m = mk(), mk(), mk()
+    v = [x.abs() for x in mk()]
+    wb = [torch.zeros(n, dtype=torch.int16, device="cuda") for n in sizes]
+    wb[2] = None
+    a = [[t.clone() if t is not None else None for t in ts] for ts in (w, m, v, wb)]
+    b = [[t.clone() if t is not None else None for t in ts] for ts in (w, m, v, wb)]
+    for k in range(len(sizes)):
+        pa.adam_step(a[0][k], gr[k], a[1][k], a[2][k], a[3][k], 1e-3, 0.9, 0.999, 1e-8, 7)
+    pa.adam_step_multi(b[0], gr, b[1], b[2], b[3], 1e-3, 0.9, 0.999, 1e-8, 7)
+    torch.cuda.synchronize()
+    for ta, tb in zip(a, b):
+        for x, y in zip(ta, tb):
+            if x is None:
+                assert y is None
+            else:
+                assert torch.equal(x, y)
