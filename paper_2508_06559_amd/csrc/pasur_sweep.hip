@@ -93,6 +93,9 @@ namespace {
 constexpr int kBlk = 256;
 // Children per tile (a parent's children never straddle two tiles).
 constexpr int kTile = 1024;
+// Largest fan-out from which a level's up sweep takes the per-child form
+// (round 6 of deal 40: level 5 489 -> 473 us; 8 leaves that level out).
+constexpr int kWideKids = 5;
 
 inline unsigned grid_of(int64_t n, int64_t cap = 256 * 32) {
   int64_t g = (n + kBlk - 1) / kBlk;
@@ -852,6 +855,141 @@ __global__ void __launch_bounds__(kBlk)
   }
 }
 
+// The same update for levels whose sibling groups vary widely in size
+// (levels that are not the tail's boundary): only the two sibling sums run
+// one thread per parent, in child order -- the regret-matching sum, then
+// u(h) = sum sigma^t u; sigma^t = x / sum and each child's regret and
+// average-sum updates run one thread per child, so a wave does not wait on
+// the largest group among its 64 parents.  Each child's arithmetic is that
+// of k_sw_up_tile, so the results are the same bits.  The regrets and
+// average sums leave straight from the child threads (coalesced).
+template <class T, bool PAPER>
+__global__ void __launch_bounds__(kBlk)
+    k_sw_up_tile_wide(int64_t n_tile, const int32_t *__restrict__ ts,
+                      const int32_t *__restrict__ tc, UpArgs<T> a, IterK ik, int variant,
+                      int rm_mode, double eps) {
+  __shared__ T sR[kTile], su[kTile], ss[kTile];
+  __shared__ int32_t scb[kTile + 1];
+  __shared__ int16_t sp[kTile];           // a child's parent within the tile
+  __shared__ double sZ[kTile];            // parent: regret-matching sum, then u(h)
+  __shared__ T sopp[kTile], sown[kTile];  // parent: the opponent's and own reach
+  if (PAPER) {
+    variant = PASUR_DCFR;
+    rm_mode = PASUR_RM_FLOOR;
+  }
+  const double sgn = a.mover == 0 ? 1.0 : -1.0;
+  const int tid = threadIdx.x;
+  const bool first = a.sg_first != nullptr;
+  // registers of the next tile
+  TileMeta nm;
+  T pR[kPer], pS[kPer], pu[kPer], pg[kPer], pa[kPer], pb[kPer];
+  int32_t pcb[kPer + 1];
+  auto fetch = [&](int64_t w) {
+    nm = tile_meta(ts, tc, w);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int j = tid + k * kBlk;
+      if (j < nm.nc) {
+        const int64_t q = nm.c0 + j;
+        pR[k] = a.R[q];
+        pS[k] = a.Sb[q];
+        pu[k] = a.u[q];
+        if (first) pg[k] = a.sg_first[q];
+      }
+      if (j < nm.np) {
+        pa[k] = a.ra[nm.h0 + j];
+        pb[k] = a.rb[nm.h0 + j];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k <= kPer; ++k) {
+      const int i = tid + k * kBlk;
+      if (i <= nm.np) pcb[k] = a.cb[nm.h0 + i];
+    }
+  };
+  int64_t w = blockIdx.x;
+  if (w < n_tile) fetch(w);
+  for (; w < n_tile; w += gridDim.x) {
+    const TileMeta m = nm;
+    T ca[kPer], cbb[kPer], cS[kPer];  // cS: child j's average sum, j = tid + k * kBlk
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int j = tid + k * kBlk;
+      if (j < m.nc) {
+        sR[j] = pR[k];
+        cS[k] = pS[k];
+        su[j] = pu[k];
+        if (first) ss[j] = pg[k];
+      }
+      ca[k] = pa[k];
+      cbb[k] = pb[k];
+    }
+#pragma unroll
+    for (int k = 0; k <= kPer; ++k) {
+      const int i = tid + k * kBlk;
+      if (i <= m.np) scb[i] = pcb[k] - m.c0;
+    }
+    __syncthreads();
+    if (w + gridDim.x < n_tile) fetch(w + gridDim.x);
+    // one thread per parent: the child -> parent map, the parent's reaches
+    // and (unless sigma is given) the regret-matching sum in child order
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * kBlk;
+      if (i >= m.np) break;
+      const int32_t b = scb[i], e = scb[i + 1];
+      double sum = 0.0;
+      for (int j = b; j < e; ++j) {
+        sp[j] = (int16_t)i;
+        if (!first) sum += rm_x((double)sR[j], rm_mode, eps);
+      }
+      sZ[i] = sum;
+      sopp[i] = a.mover == 0 ? cbb[k] : ca[k];
+      sown[i] = a.mover == 0 ? ca[k] : cbb[k];
+    }
+    __syncthreads();
+    // one thread per child: sigma^t from the regret and the sum
+    if (!first) {
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * kBlk;
+        if (j >= m.nc) break;
+        const int i = sp[j];
+        const double x = rm_x((double)sR[j], rm_mode, eps);
+        ss[j] = PAPER ? (T)(x / sZ[i]) : (T)sig_from<T>(x, sZ[i], scb[i + 1] - scb[i]);
+      }
+      __syncthreads();
+    }
+    // one thread per parent: u(h) = sum sigma^t u in child order
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * kBlk;
+      if (i >= m.np) break;
+      const int32_t b = scb[i], e = scb[i + 1];
+      double uh = 0.0;
+      for (int j = b; j < e; ++j) uh += (double)ss[j] * (double)su[j];
+      sZ[i] = uh;
+      a.u_par[m.h0 + i] = (T)uh;
+      if (a.vacc) a.vacc[m.h0 + i] += uh;
+    }
+    __syncthreads();
+    // one thread per child: the regret and average-sum updates
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int j = tid + k * kBlk;
+      if (j >= m.nc) break;
+      const int i = sp[j];
+      const double uh = sZ[i], opp = (double)sopp[i], own = (double)sown[i];
+      const double r = sgn * opp * ((double)su[j] - uh);
+      double add = own * (double)ss[j];
+      if (!PAPER && variant == PASUR_CFR_PLUS) add *= ik.avg_t;
+      a.R[m.c0 + j] = (T)regret_update<PAPER>((double)sR[j], r, ik, variant);
+      a.Sb[m.c0 + j] = (T)(ik.avg_w * (double)cS[k] + add);
+    }
+    __syncthreads();  // before the next tile reuses LDS
+  }
+}
+
 // FindUtility, one thread per parent (all parents of the level, or those in
 // `list`): the children in order, as the oracle's loops.
 template <class T, bool PAPER>
@@ -1088,8 +1226,13 @@ int sweep_t(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p, 
       const int64_t nt = x.n_tile[L];
       ProfScope ps(a.act ? PK_UP_BND : PK_UP, L, s, f->n[L], f->n[L - 1],
                    a.act ? x.n_act[x.S] : 0, 0, 1);
+      // wide sibling groups: the per-child form (measured faster where the
+      // largest group reaches kWideKids; slower on the tail boundary, whose
+      // groups are nearly all of two)
+      const bool wide = !a.act && x.kmax[L] >= kWideKids;
       auto kern = a.act ? (pos ? k_sw_up_tile<T, true, true> : k_sw_up_tile<T, false, true>)
-                        : (pos ? k_sw_up_tile<T, true, false> : k_sw_up_tile<T, false, false>);
+                  : wide ? (pos ? k_sw_up_tile_wide<T, true> : k_sw_up_tile_wide<T, false>)
+                         : (pos ? k_sw_up_tile<T, true, false> : k_sw_up_tile<T, false, false>);
       kern<<<grid_of(nt * kBlk), kBlk, 0, s>>>(nt, x.tile[L], x.tile_c[L], a, ik, var, rm, eps);
     } else if (f->n[L - 1] > 0) {
       const int64_t n = f->n[L - 1];

@@ -58,10 +58,13 @@ def solve(pa, deck, start, roots, dtype, iters, sched, params=None):
 
 
 # deals whose trees have non-chain nodes on levels 6 and 7 (so the compact
-# tail has two levels), and one whose level 6 is all chains
+# tail has two levels), one whose level 6 is all chains, and ones with
+# sibling groups of 8 to 22 children (the up sweep's per-child form for wide
+# levels: seeds 1 and 22)
 CASES = [("two-round 1", lambda: (4, synth.two_round_root(1))),
          ("two-round 13", lambda: (4, synth.two_round_root(13))),
          ("two-round 38", lambda: (4, synth.two_round_root(38))),
+         ("two-round 22", lambda: (4, synth.two_round_root(22))),
          ("last-round 2", lambda: (5, synth.last_round_roots(2)))]
 
 
