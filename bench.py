@@ -53,7 +53,7 @@ TRAFFIC = {
                 "bytes": 1.226e12},
     # the full game's dominant streaming kernel (average over its launches)
     "full-game": {"source": "paper_2508_06559_amd/csrc/pasur_sweep.hip",
-                  "sha256": "bf9e950bc9c6c389f7013d15a33cfb35c7e8e098d859225b340c110ee5a88908",
+                  "sha256": "d512a356e55862de35549ff60b0b683365b85538736f209dd30645d6585b11f9",
                   "bytes": 2.134e9},
 }
 
