@@ -64,6 +64,9 @@ struct SweepIndex {
   int32_t *jpos[9];     // level L = S+1..7: active node -> its compact child position
   int32_t *ppar[9];     // level L = S+1..7: active node -> its parent's active index;
                         // level S: -> its parent's index in bp
+  int32_t *ttile[9];    // level L = S+1..8: tiles of the compact children (parent starts,
+  int32_t *ttile_c[9];  // child starts; n_ttile[L] + 1 each), where the largest group fits
+  int64_t n_ttile[9];
   int64_t n_bp;         // boundary parents: level S-1 nodes with an active child
   int32_t *bp;          // their indices (sorted)
   int32_t *bp_tile;     // first bp entry of each tile of level S-1 (n_tile[S-1] + 1)
@@ -81,6 +84,8 @@ void sweep_index_free(SweepIndex *x) {
     dev_free(x->cmap[l]);
     dev_free(x->jpos[l]);
     dev_free(x->ppar[l]);
+    dev_free(x->ttile[l]);
+    dev_free(x->ttile_c[l]);
   }
   dev_free(x->bp);
   dev_free(x->bp_tile);
@@ -178,6 +183,11 @@ __global__ void k_sw_cmap(int64_t n, const int32_t *__restrict__ act, const int3
   }
 }
 
+// compact child position -> its parent's active index
+__global__ void k_sw_cpar(int64_t n, const int32_t *__restrict__ cbc, int32_t *__restrict__ pc) {
+  SW_FOR(i, n) for (int32_t j = cbc[i]; j < cbc[i + 1]; ++j) pc[j] = (int32_t)i;
+}
+
 // active node i of level L: its parent's active index and its compact child
 // position among that parent's children
 __global__ void k_sw_tailpos(int64_t n, const int32_t *__restrict__ act,
@@ -259,6 +269,30 @@ int build_tail(pasur_fgt *f, SweepIndex *x, int S, hipStream_t s) {
     k_sw_cmap<<<grid_of(na), kBlk, 0, s>>>(na, x->act[L - 1], f->child_begin[L - 1], x->cbc[L - 1],
                                            x->cmap[L]);
   }
+  // tiles of the compact levels (every active parent has a child)
+  for (int L = S + 1; L <= 8 && !st; ++L) {
+    const int km = x->kmax[L];
+    const int64_t m = x->m[L], na = x->n_act[L - 1];
+    if (m == 0 || km > kTile / 2) continue;
+    int32_t *pc = nullptr;
+    st = dev_alloc(&pc, m);
+    const int stride = kTile - (km - 1);
+    const int64_t nt = (m + stride - 1) / stride;
+    if (!st) st = dev_alloc(&x->ttile[L], nt + 1);
+    if (!st) st = dev_alloc(&x->ttile_c[L], nt + 1);
+    if (!st) {
+      x->n_ttile[L] = nt;
+      k_sw_cpar<<<grid_of(na), kBlk, 0, s>>>(na, x->cbc[L - 1], pc);
+      k_sw_tiles<<<grid_of(nt + 1), kBlk, 0, s>>>(nt, m, na, stride, pc, x->ttile[L]);
+      k_sw_tile_c<<<grid_of(nt + 1), kBlk, 0, s>>>(nt, x->ttile[L], x->cbc[L - 1], x->ttile_c[L]);
+      const hipError_t e = hipStreamSynchronize(s);  // pc is read by k_sw_tiles
+      if (e != hipSuccess) {
+        set_error("sweep tail tiles: %s", hipGetErrorString(e));
+        st = PASUR_E_HIP;
+      }
+    }
+    dev_free(pc);
+  }
   for (int L = S + 1; L <= 7 && !st; ++L) {
     const int64_t na = x->n_act[L];
     st = dev_alloc(&x->ppar[L], na);
@@ -319,6 +353,8 @@ int build_index(pasur_fgt *f, hipStream_t s) {
     x->kmax[l] = 0;
     x->m[l] = 0;
     x->cbc[l] = x->cmap[l] = x->jpos[l] = x->ppar[l] = nullptr;
+    x->ttile[l] = x->ttile_c[l] = nullptr;
+    x->n_ttile[l] = 0;
   }
   x->S = 0;
   x->n_bp = 0;
@@ -990,6 +1026,121 @@ __global__ void __launch_bounds__(kBlk)
   }
 }
 
+// FindUtility on a level of the compact tail, over LDS-staged tiles of its
+// compact children (the tail's parents are its active nodes, a.cb its
+// compact CSR): as k_sw_up_tile, except that sigma^t comes from the
+// parent's stored regret-matching sum (a.Z, as the tail's down sweep uses
+// it) instead of a loop over the siblings, the parent's new sum is stored
+// for the next iteration, and the parent's utility goes to its compact
+// position (a.upos).  The operations are those of k_sw_up_parent on the
+// tail, in the same order.  Not for a call's first iteration.
+template <class T, bool PAPER>
+__global__ void __launch_bounds__(kBlk)
+    k_sw_up_tail_tile(int64_t n_tile, const int32_t *__restrict__ ts,
+                      const int32_t *__restrict__ tc, UpArgs<T> a, IterK ik, int variant,
+                      int rm_mode, double eps) {
+  __shared__ T sR[kTile], sS[kTile], su[kTile], ss[kTile];
+  __shared__ int32_t scb[kTile + 1];
+  if (PAPER) {
+    variant = PASUR_DCFR;
+    rm_mode = PASUR_RM_FLOOR;
+  }
+  const double sgn = a.mover == 0 ? 1.0 : -1.0;
+  const int tid = threadIdx.x;
+  // registers of the next tile
+  TileMeta nm;
+  T pR[kPer], pS[kPer], pu[kPer], pa[kPer], pb[kPer];
+  double pz[kPer];
+  int32_t pcb[kPer + 1];
+  auto fetch = [&](int64_t w) {
+    nm = tile_meta(ts, tc, w);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int j = tid + k * kBlk;
+      if (j < nm.nc) {
+        const int64_t q = nm.c0 + j;
+        pR[k] = a.R[q];
+        pS[k] = a.Sb[q];
+        pu[k] = a.u[q];
+      }
+      if (j < nm.np) {
+        pa[k] = a.ra[nm.h0 + j];
+        pb[k] = a.rb[nm.h0 + j];
+        pz[k] = a.Z[nm.h0 + j];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k <= kPer; ++k) {
+      const int i = tid + k * kBlk;
+      if (i <= nm.np) pcb[k] = a.cb[nm.h0 + i];
+    }
+  };
+  int64_t w = blockIdx.x;
+  if (w < n_tile) fetch(w);
+  for (; w < n_tile; w += gridDim.x) {
+    const TileMeta m = nm;
+    T ca[kPer], cbb[kPer];
+    double cz[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int j = tid + k * kBlk;
+      if (j < m.nc) {
+        sR[j] = pR[k];
+        sS[j] = pS[k];
+        su[j] = pu[k];
+      }
+      ca[k] = pa[k];
+      cbb[k] = pb[k];
+      cz[k] = pz[k];
+    }
+#pragma unroll
+    for (int k = 0; k <= kPer; ++k) {
+      const int i = tid + k * kBlk;
+      if (i <= m.np) scb[i] = pcb[k] - m.c0;
+    }
+    __syncthreads();
+    if (w + gridDim.x < n_tile) fetch(w + gridDim.x);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * kBlk;
+      if (i >= m.np) break;
+      const int32_t h = m.h0 + i, b = scb[i], e = scb[i + 1], kk = e - b;
+      // sigma^t from the stored sum and u(h) = sum sigma^t u, in child order
+      const double Zh = cz[k];
+      double uh = 0.0;
+      for (int j = b; j < e; ++j) {
+        const T sj = (T)sig_of<T>(sR[j], Zh, rm_mode, eps);
+        ss[j] = sj;
+        uh += (double)sj * (double)su[j];
+      }
+      const double opp = a.mover == 0 ? (double)cbb[k] : (double)ca[k];
+      const double own = a.mover == 0 ? (double)ca[k] : (double)cbb[k];
+      double sum = 0.0;
+      for (int j = b; j < e; ++j) {
+        const double r = sgn * opp * ((double)su[j] - uh);
+        const T Rs = (T)regret_update<PAPER>((double)sR[j], r, ik, variant);
+        sR[j] = Rs;
+        sum += rm_x((double)Rs, rm_mode, eps);
+        double add = own * (double)ss[j];
+        if (!PAPER && variant == PASUR_CFR_PLUS) add *= ik.avg_t;
+        sS[j] = (T)(ik.avg_w * (double)sS[j] + add);
+      }
+      a.u_par[a.upos ? a.upos[h] : h] = (T)uh;
+      a.Z[h] = z_enc(sum, kk);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int j = tid + k * kBlk;
+      if (j < m.nc) {
+        a.R[m.c0 + j] = sR[j];
+        a.Sb[m.c0 + j] = sS[j];
+      }
+    }
+    __syncthreads();  // before the next tile reuses LDS
+  }
+}
+
 // FindUtility, one thread per parent (all parents of the level, or those in
 // `list`): the children in order, as the oracle's loops.
 template <class T, bool PAPER>
@@ -1313,7 +1464,13 @@ int sweep_t(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p, 
       a.rb = tl.rbc[L - 1];
       a.vacc = nullptr;
       ProfScope ps(PK_TAIL_UP, L, s, x.m[L], n, 0, 0, 1);
-      k_sw_up_parent<T, PAPER><<<grid_of(n), kBlk, 0, s>>>(n, nullptr, a, ik, var, rm, eps);
+      if (x.ttile[L]) {
+        const int64_t nt = x.n_ttile[L];
+        auto kern = pos ? k_sw_up_tail_tile<T, true> : k_sw_up_tail_tile<T, false>;
+        kern<<<grid_of(nt * kBlk), kBlk, 0, s>>>(nt, x.ttile[L], x.ttile_c[L], a, ik, var, rm, eps);
+      } else {
+        k_sw_up_parent<T, PAPER><<<grid_of(n), kBlk, 0, s>>>(n, nullptr, a, ik, var, rm, eps);
+      }
     }
     for (int L = S; L >= 1; --L) {
       UpArgs<T> a = up_args(L);
