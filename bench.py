@@ -439,7 +439,8 @@ def bench_full(args):
         e_r = sum(n[1:])
         ms_r = round_ms[5 - r] if len(round_ms) == 6 else None
         rounds.append({"round": r + 1, "nodes": int(sum(n)), "edges": int(e_r),
-                       "schedule": "stream" if sum(n) >= 10_000_000 else "persistent segments",
+                       "schedule": (("stream" if sum(n) >= 9_000_000 else "persistent segments")
+                                    if args.sched == "auto" else args.sched),
                        "dcfr_ms": ms_r,
                        "node_updates_per_s": e_r * iters / (ms_r * 1e-3) if ms_r else None})
     out = {"metric": METRIC, "value": value, "unit": "node-updates/s",

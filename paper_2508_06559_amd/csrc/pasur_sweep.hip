@@ -1530,14 +1530,14 @@ int sweep_t(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p, 
 }  // namespace
 
 bool sweep_pays(const pasur_fgt *f) {
-  // Measured on the full game of deal 40: the persistent segment kernel
-  // runs a round at 6-7e10 node-updates/s once it fills the chip; the
-  // streaming sweeps pay about 15 launches per iteration and overtake it
-  // from about 1e7 nodes (1.2e7: 176 vs 198 us per iteration; 1.5e8: 0.98
-  // vs 2.6 ms; 6.8e8: 3.2 vs 10.7 ms).
+  // Measured on whole games (1000 iterations per round, streaming vs
+  // persistent segments): the streaming sweeps pay about 30 launches per
+  // iteration and overtake the segment kernel between 7.7e6 nodes (137 vs
+  // 112 ms, deal 1 round 5) and 9.7e6 (136 vs 146 ms, deal 1 round 6);
+  // 1.1e7: 133 vs 181 ms; 3.5e7: 231 vs 454 ms; 1.1e8: 442 vs 1372 ms.
   int64_t nodes = 0;
   for (int l = 0; l <= 8; ++l) nodes += f->n[l];
-  return nodes >= (int64_t)10 * 1000 * 1000;
+  return nodes >= (int64_t)9 * 1000 * 1000;
 }
 
 int sweep_iterate(pasur_fgt *f, const pasur_cfr_state *st, const pasur_cfr_params *p,
