@@ -53,7 +53,7 @@ TRAFFIC = {
                 "bytes": 1.226e12},
     # the full game's dominant streaming kernel (average over its launches)
     "full-game": {"source": "paper_2508_06559_amd/csrc/pasur_sweep.hip",
-                  "sha256": "2a6ed1a61a1d3b2005f682601bdefeb5b79b5bb2d9800cda758986719dc27177",
+                  "sha256": "b709966b880899046598e783d0007aaedb0aeb2b4c2c72f3c58875b6926fa956",
                   "bytes": 2.134e9},
 }
 
