@@ -1219,7 +1219,7 @@ def main():
     ap.add_argument("--train-deals", type=int, default=512)
     ap.add_argument("--test-deals", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
-    ap.add_argument("--stream-min-nodes", type=int, default=10_000_000,
+    ap.add_argument("--stream-min-nodes", type=int, default=9_000_000,
                     help="paper-scale: round trees this large run the streaming sweeps "
                          "(0: every round in the batched plan)")
     ap.add_argument("--full-train-games", type=int, default=48,
