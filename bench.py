@@ -1067,8 +1067,8 @@ def bench_mlp(args):
     feature rows (card bits set with probability 1/4, score and level
     columns as the feature layout fills them): --steps timed calls of the
     fused inference (k_mlp_infer) over 2^20 rows, and --steps training steps
-    (forward: two GEMMs and the output layer; loss, backward, Adam) over 2^18 rows in groups of
-    four siblings, each timed with HIP events on the launch stream."""
+    (forward: the fused kernel, which also writes H1 and H2; loss, backward, Adam) over 2^18 rows
+    in groups of four siblings, each timed with HIP events on the launch stream."""
     import torch
     from paper_2508_06559_amd import learn
     import paper_2508_06559_amd as pa

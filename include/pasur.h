@@ -442,8 +442,8 @@ typedef struct {
   const uint16_t *W2; const float *b2; /* [256][256], [256] */
   const uint16_t *W3; const float *b3; /* [256][2], [2] */
   /* Optional (may be NULL): W1 and W2 transposed to [256][192] and [256][256]
-   * (pasur_mlp_transpose), used by pasur_mlp_infer instead of transposing
-   * into scratch on every call. */
+   * (pasur_mlp_transpose), used by pasur_mlp_infer and the fused
+   * pasur_mlp_forward instead of transposing into scratch on every call. */
   const uint16_t *W1t, *W2t;
 } pasur_mlp_weights;
 typedef struct {
@@ -467,7 +467,8 @@ int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M,
 /* Inference only: Y [M][2] (FP32) for M rows of X [M][192] (BF16), the same
  * arithmetic as pasur_mlp_forward (H1, H2 rounded to BF16; FP32 accumulation
  * in another order) in one fused launch that keeps H1 and H2 on chip.  Uses
- * stream-ordered scratch for the transposed weights (~220 KB). */
+ * stream-ordered scratch for the transposed weights (~220 KB) unless w
+ * carries them. */
 int pasur_mlp_infer(const pasur_mlp_weights *w, const uint16_t *X, int64_t M, float *Y,
                     void *stream);
 /* W1t = W1^T [256][192], W2t = W2^T [256][256] (BF16, caller-owned). */

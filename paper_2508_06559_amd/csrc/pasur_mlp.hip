@@ -741,7 +741,11 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 // ---------------------------------------------------------------------------
 // Fused inference: Y = (relu(relu(X W1 + b1) W2 + b2)) W3 + b3 for a tile of
 // 128 rows per workgroup, H1 and H2 kept in LDS (rounded to BF16 as in
-// pasur_mlp_forward).  The MFMA computes each layer transposed, D = W^T A^T:
+// pasur_mlp_forward).  The hidden layer overwrites the input tile in place
+// (every wave has read the tile when the first hidden values are written),
+// so a workgroup holds 70 KB of LDS and two workgroups share a CU: the
+// latency of one's tile load and epilogues hides behind the other's MFMAs.
+// The MFMA computes each layer transposed, D = W^T A^T:
 // the weights (pre-transposed to [out][in], contiguous in K) are the A
 // operand, loaded from global memory (L2-resident, shared by all
 // workgroups) 16 bytes per lane and prefetched one K step ahead; the
@@ -749,11 +753,10 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 // 16x16 result tile then holds four consecutive output features of one row
 // per lane, which store as one 8-byte LDS write.  With W waves, wave w owns
 // output features 256/W consecutive from w*256/W for all 128 rows
-// (256/(16W) x 8 tiles of 16x16x32).
-// The last layer (256 -> 2) is a plain FP32 dot product per (row, output),
-// in feature order.
+// (256/(16W) x 8 tiles of 16x16x32).  The biases and W3 (transposed) are
+// staged in LDS with the input tile, so that no epilogue waits on memory.
 constexpr int IM = 128;                 // rows per workgroup
-constexpr int kInferWaves = 16;         // four waves per SIMD in the one workgroup that fits a CU
+constexpr int kInferWaves = 8;          // two waves per SIMD per workgroup, two workgroups per CU
 constexpr int kInferDepth = 1;          // K steps of weight fragments in flight per wave
 constexpr int XS = kIn + 8, HS = kHid + 8;  // LDS row strides (bf16), 16-byte aligned
 
@@ -844,53 +847,84 @@ __global__ void __launch_bounds__(64 * WAVES) k_mlp_infer(int M, const __bf16 *_
                                                    float *__restrict__ Y, __bf16 *__restrict__ H1,
                                                    __bf16 *__restrict__ H2) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16 *Xs = reinterpret_cast<__bf16 *>(smem);          // [IM][XS]
-  __bf16 *Hs = Xs + IM * XS;                               // [IM][HS]
+  __bf16 *Xs = reinterpret_cast<__bf16 *>(smem);          // [IM][XS], the input tile
+  __bf16 *Hs = Xs;                                         // [IM][HS], in its place
+  float *b1s = reinterpret_cast<float *>(smem + sizeof(__bf16) * IM * HS);  // [kHid]
+  float *b2s = b1s + kHid;                                                   // [kHid]
+  __bf16 *w3s = reinterpret_cast<__bf16 *>(b2s + kHid);    // [kOut][kHid], W3 transposed
   constexpr int NT = 64 * WAVES;         // threads
   constexpr int TA = kHid / 16 / WAVES;  // 16-wide output tiles per wave
   constexpr int TB = IM / 16;            // 16-row tiles per workgroup
+  constexpr int XP = IM * (kIn / 8) / NT;  // 16-byte pieces of the tile per thread
+  static_assert(IM * (kIn / 8) % NT == 0 && NT >= kHid, "tile staging");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * IM;
-  // X tile -> LDS (16-byte pieces; rows past M are zero)
-  for (int e = tid; e < IM * (kIn / 8); e += NT) {
-    const int r = e / (kIn / 8), c = (e % (kIn / 8)) * 8;
-    bf16x8 v;
-    if (m0 + r < M) v = *reinterpret_cast<const bf16x8 *>(X + (int64_t)(m0 + r) * kIn + c);
+  // X tile, biases and W3 -> LDS: every load issued before the first LDS
+  // write (rows past M are zero)
+  bf16x8 xv[XP];
+#pragma unroll
+  for (int i = 0; i < XP; ++i) {
+    const int e = tid + i * NT, r = e / (kIn / 8), c = (e % (kIn / 8)) * 8;
+    if (m0 + r < M) xv[i] = *reinterpret_cast<const bf16x8 *>(X + (int64_t)(m0 + r) * kIn + c);
     else
-      for (int i = 0; i < 8; ++i) v[i] = (__bf16)0.f;
-    *reinterpret_cast<bf16x8 *>(Xs + r * XS + c) = v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xv[i][j] = (__bf16)0.f;
+  }
+  float bv1 = 0.f, bv2 = 0.f;
+  __bf16 wv[kOut];
+  if (tid < kHid) {
+    bv1 = b1[tid];
+    bv2 = b2[tid];
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) wv[o] = W3[tid * kOut + o];
+  }
+  const float bo0 = b3[0], bo1 = b3[1];
+#pragma unroll
+  for (int i = 0; i < XP; ++i) {
+    const int e = tid + i * NT, r = e / (kIn / 8), c = (e % (kIn / 8)) * 8;
+    *reinterpret_cast<bf16x8 *>(Xs + r * XS + c) = xv[i];
+  }
+  if (tid < kHid) {
+    b1s[tid] = bv1;
+    b2s[tid] = bv2;
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) w3s[o * kHid + tid] = wv[o];
   }
   __syncthreads();
   const int n_base = wave * 16 * TA;   // this wave's output features
-  infer_layer<kIn, TA, TB, DEPTH>(W1t, Xs, XS, b1, Hs, n_base, lane);   // H1 in Hs
+  infer_layer<kIn, TA, TB, DEPTH>(W1t, Xs, XS, b1s, Hs, n_base, lane);  // H1 in Hs
   // (layer 2 reads Hs and passes a barrier before it overwrites it)
   if (STORE) store_hidden<NT>(Hs, H1, m0, M, tid);
-  infer_layer<kHid, TA, TB, DEPTH>(W2t, Hs, HS, b2, Hs, n_base, lane);  // H2 in Hs
+  infer_layer<kHid, TA, TB, DEPTH>(W2t, Hs, HS, b2s, Hs, n_base, lane);  // H2 in Hs
   if (STORE) store_hidden<NT>(Hs, H2, m0, M, tid);
   // last layer (256 -> 2) on the matrix cores as well: wave v < IM/16 takes
   // rows 16v..16v+15; the A operand is W3 transposed and padded to 16
-  // outputs (rows 2..15 zero), built from W3 in registers; outputs 0 and 1
-  // of row 16v + (lane & 15) land in elements 0 and 1 of lanes 0..15.
+  // outputs (rows 2..15 zero), read from LDS; outputs 0 and 1 of row
+  // 16v + (lane & 15) land in elements 0 and 1 of lanes 0..15.
   if (wave < IM / 16) {
     const int lr = lane & 15, lk = 8 * (lane >> 4);
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k0 = 0; k0 < kHid; k0 += 32) {
       bf16x8 wa;
+      if (lr < kOut) wa = *reinterpret_cast<const bf16x8 *>(w3s + lr * kHid + k0 + lk);
+      else
 #pragma unroll
-      for (int i = 0; i < 8; ++i) wa[i] = lr < kOut ? W3[(k0 + lk + i) * kOut + lr] : (__bf16)0.f;
+        for (int i = 0; i < 8; ++i) wa[i] = (__bf16)0.f;
       const bf16x8 x = *reinterpret_cast<const bf16x8 *>(Hs + (16 * wave + lr) * HS + k0 + lk);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, x, acc, 0, 0, 0);
     }
     const int m = m0 + 16 * wave + lr;
     if (lane < 16 && m < M) {
-      Y[(int64_t)m * kOut + 0] = acc[0] + b3[0];
-      Y[(int64_t)m * kOut + 1] = acc[1] + b3[1];
+      Y[(int64_t)m * kOut + 0] = acc[0] + bo0;
+      Y[(int64_t)m * kOut + 1] = acc[1] + bo1;
     }
   }
 }
 
-constexpr size_t kInferLds = sizeof(__bf16) * (size_t)IM * (XS + HS);
+static_assert(XS <= HS && kOut == 2, "fused inference layout");
+constexpr size_t kInferLds =
+    sizeof(__bf16) * (size_t)IM * HS + sizeof(float) * 2 * kHid + sizeof(__bf16) * kOut * kHid;
 
 // W [K][N] (row-major) -> Wt [N][K]
 __global__ void k_transpose_bf16(const __bf16 *__restrict__ W, int K, int N, __bf16 *__restrict__ Wt) {

@@ -133,7 +133,9 @@ class WarmStartMLP:
                    betas=(0.9, 0.999), eps=1e-8):
         torch = self.torch
         b = self._buffers(u.n_rows)
-        w = self.weights()
+        # the transposed W1/W2 copies the fused forward reads (made in place,
+        # so that the step allocates nothing for them)
+        w = self.infer_weights()
         mlp_forward(w, u.X, u.n_rows, b["H1"], b["H2"], b["Y"])
         loss = torch.empty((u.n_par, 2), dtype=torch.float32, device="cuda")
         mlp_loss(b["Y"], u.tsig, u.tval, u.seg, u.n_par, u.n_rows, value_weight, b["dY"], loss)
