@@ -346,6 +346,86 @@ __global__ void k_split_sum(const float *__restrict__ part, int splits, int64_t 
   out[i] = s;
 }
 
+// Weight-gradient partials over one chunk of rows: part[z][i][j] = sum over
+// the rows k of chunk z (K steps of 32, ascending) of A[k][i] G[k][j], for
+// the whole NA x 256 gradient (A [M][NA], G [M][256], BF16, row-major,
+// 16-byte aligned).  One workgroup of 16 waves holds the full gradient, so
+// each operand row is read from memory once per product: wave w owns rows
+// (w / 4) NA/4 .. and columns (w % 4) 64 .. as (NA/64) x 4 MFMA 16x16x32
+// tiles.  A K step's slices of A and G go to LDS transposed ([column][k],
+// each k pair one 32-bit word, as the MFMA reads 8 consecutive k per lane);
+// the next step's are loaded into registers during this step's MFMAs.  Rows
+// at or past the chunk's end (or M) read as zero.
+constexpr int kWgThreads = 1024;  // threads per workgroup of k_wgrad
+constexpr int kWgRows = 1024;     // rows per chunk at most 256 chunks
+template <int NA>
+__global__ void __launch_bounds__(kWgThreads) k_wgrad(const __bf16 *__restrict__ A,
+                                                       const __bf16 *__restrict__ G, int M,
+                                                       int kchunk, float *__restrict__ part) {
+  constexpr int NB = kHid;
+  constexpr int CG = (NA + NB) / 8;     // 8-column groups of both operands
+  constexpr int ITEMS = CG * (BK / 2);  // (column group, k pair) staging tasks per K step
+  constexpr int TA = NA / 64, TB = 4;
+  static_assert(NA % 64 == 0 && ITEMS <= kWgThreads, "k_wgrad shape");
+  __shared__ __align__(16) __bf16 T[NA + NB][LDK];  // LDS rows 0..NA-1: A^T; then G^T
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kbeg = blockIdx.x * kchunk, kend = min(M, kbeg + kchunk);
+  // this thread's staging task: rows k0 + 2 kp and k0 + 2 kp + 1 of one
+  // operand's columns 8 cg' .. 8 cg' + 7
+  const bool stager = tid < ITEMS;
+  const int kp = tid % (BK / 2), cg = tid / (BK / 2);
+  const bool on_a = cg < NA / 8;
+  const __bf16 *src = on_a ? A + 8 * cg : G + 8 * (cg - NA / 8);
+  const int64_t ld = on_a ? NA : NB;
+  bf16x8 lo, hi;
+  auto fetch = [&](int k0) {
+    const int r = k0 + 2 * kp;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) lo[j] = hi[j] = (__bf16)0.f;
+    if (stager && r < kend) lo = *reinterpret_cast<const bf16x8 *>(src + (int64_t)r * ld);
+    if (stager && r + 1 < kend) hi = *reinterpret_cast<const bf16x8 *>(src + (int64_t)(r + 1) * ld);
+  };
+  const int wr = wave >> 2, wc = wave & 3;
+  const int ia = wr * (NA / 4), jb = NA + 64 * wc;  // LDS rows of the wave's A and G tiles
+  const int lr = lane & 15, lk = 8 * (lane >> 4);
+  f32x4 acc[TA][TB];
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();  // every wave has read the previous step's fragments
+    if (stager) {
+      const u16x8 l = __builtin_bit_cast(u16x8, lo), h = __builtin_bit_cast(u16x8, hi);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        *reinterpret_cast<uint32_t *>(&T[8 * cg + j][2 * kp]) = (uint32_t)l[j] | ((uint32_t)h[j] << 16);
+    }
+    __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
+    bf16x8 fa[TA], fb[TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a) fa[a] = *reinterpret_cast<const bf16x8 *>(&T[ia + 16 * a + lr][lk]);
+#pragma unroll
+    for (int b = 0; b < TB; ++b) fb[b] = *reinterpret_cast<const bf16x8 *>(&T[jb + 16 * b + lr][lk]);
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  }
+  // the accumulator of tile (a, b) holds rows 4 (lane / 16) .. +3 of column lane % 16
+  float *out = part + (int64_t)blockIdx.x * NA * NB;
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(int64_t)(ia + 16 * a + 4 * (lane >> 4) + r) * NB + 64 * wc + 16 * b + lr] = acc[a][b][r];
+}
+
 // Column sums over the M rows (bias gradients, the output layer's weight
 // gradient) in two deterministic passes: one workgroup per chunk of rows
 // writes its partial sums part[chunk][n]; k_col_merge then adds the
@@ -1060,12 +1140,17 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
   // 2048 rows, up to 128 chunks.
   const int splits = std::min(128, std::max(1, m / 2048));
   const int kchunk = ((m + splits - 1) / splits + BK - 1) / BK * BK;
+  // k_wgrad's chunks (16-byte aligned operands): up to 256 of at least
+  // kWgRows rows each, a multiple of BK
+  const int64_t wsplits0 = std::min<int64_t>(256, (M + kWgRows - 1) / kWgRows);
+  const int wchunk = (int)(((M + wsplits0 - 1) / wsplits0 + BK - 1) / BK * BK);
+  const int wsplits = (int)((M + wchunk - 1) / wchunk);
   __bf16 *G2b = nullptr, *G1b = nullptr;
   float *part = nullptr;
   // split-K partials of the weight gradients, or the row-chunk partials of
   // the bias gradients and of the output layer's weight gradient, or the
   // dH1 product's row-tile partials of db1
-  const size_t part_n = std::max({(size_t)splits * kHid * kHid,
+  const size_t part_n = std::max({(size_t)std::max(splits, wsplits) * kHid * kHid,
                                   (size_t)kColChunks * (kHid * kOut + kOut + kHid),
                                   (size_t)row_tiles(m, kHid) * kHid});
   hipError_t e = hipMallocAsync((void **)&G2b, sizeof(__bf16) * (size_t)m * kHid, s);
@@ -1077,7 +1162,16 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     st = PASUR_E_NOMEM;
   }
   auto dW = [&](const __bf16 *Act, int kin, const __bf16 *G, int nout, float *out) -> int {
-    // out[kin, nout] = Act^T G, reduced over the M rows in `splits` chunks
+    // out[kin, nout] = Act^T G, reduced over the M rows in chunks
+    if (nout == kHid && (kin == kHid || kin == kIn) &&
+        ((reinterpret_cast<uintptr_t>(Act) | reinterpret_cast<uintptr_t>(G)) & 15) == 0) {
+      if (kin == kHid) k_wgrad<kHid><<<wsplits, kWgThreads, 0, s>>>(Act, G, m, wchunk, part);
+      else k_wgrad<kIn><<<wsplits, kWgThreads, 0, s>>>(Act, G, m, wchunk, part);
+      PASUR_TRY_HIP(hipGetLastError());
+      k_split_sum<<<blocks((int64_t)kin * nout, 64), 64, 0, s>>>(part, wsplits, (int64_t)kin * nout, out);
+      PASUR_TRY_HIP(hipGetLastError());
+      return PASUR_OK;
+    }
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.M = kin; g.N = nout; g.K = m;

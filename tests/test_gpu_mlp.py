@@ -73,20 +73,29 @@ def make_problem(seed, n_par=300):
     return X, seg, tsig, tval, W
 
 
-# about 900 rows (one K chunk per weight gradient) and about 6000 (two ragged chunks)
-@pytest.mark.parametrize("n_par", [300, 2000])
-def test_mlp_forward_backward_match_oracle(n_par):
+# about 900 rows (one row chunk per weight gradient, ragged in its last K
+# step) and about 6000 (six chunks, the last ragged); with X 8 bytes off a
+# 16-byte boundary the forward and dW1 take the GEMM path instead of the
+# fused forward and the whole-gradient kernel
+@pytest.mark.parametrize("n_par,x_off", [(300, 0), (2000, 0), (300, 4)])
+def test_mlp_forward_backward_match_oracle(n_par, x_off):
     pa = require_gpu()
     from paper_2508_06559_amd import learn
     import torch
     X, seg, tsig, tval, W = make_problem(3, n_par)
     M = X.shape[0]
+    print(f"[mlp] forward/backward M={M} x_off={x_off}", flush=True)
     model = learn.WarmStartMLP(0)
     model.set_weights(W)
     # the host-side bfloat16 conversion of the binding equals the oracle's
     for k in (0, 2, 4):
         assert np.array_equal(to_np(model.bf[k]).view(np.uint16), omlp.bf16_bits(W[k]))
     dX = bf16_tensor(X)
+    if x_off:
+        buf = torch.zeros(dX.numel() + x_off, dtype=dX.dtype, device="cuda")
+        buf[x_off:] = dX.flatten()
+        dX = buf[x_off:].view(dX.shape)
+        assert dX.data_ptr() % 16 == 2 * x_off
     b = model._buffers(M)
     w = model.weights()
     pa.mlp_forward(w, dX, M, b["H1"], b["H2"], b["Y"])
@@ -233,7 +242,7 @@ def test_forward_output_layer_both_paths():
 
 def test_mlp_backward_full_size():
     """At the size the benchmark trains on (2^18 rows): the weight gradients
-    take 128 K chunks, db1 the 2048 row tiles of the dH1 product, db2, dW3
+    take 256 row chunks of 1024, db1 the 2048 row tiles of the dH1 product, db2, dW3
     and db3 1024 full row chunks.  All six gradients against the oracle's
     backward on the GPU's own activations."""
     pa = require_gpu()
