@@ -439,6 +439,8 @@ __device__ __forceinline__ void col_merge_one(const float *__restrict__ part, in
                                               int n, float *__restrict__ out) {
   const int lane = threadIdx.x;
   float s = 0.f;
+  // eight loads in flight per lane; the sum still runs in chunk order
+#pragma unroll 8
   for (int z = lane; z < chunks; z += 64) s += part[(int64_t)z * N + n];
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
@@ -1007,11 +1009,19 @@ constexpr size_t kInferLds =
     sizeof(__bf16) * (size_t)IM * HS + sizeof(float) * 2 * kHid + sizeof(__bf16) * kOut * kHid;
 
 // W [K][N] (row-major) -> Wt [N][K]
-__global__ void k_transpose_bf16(const __bf16 *__restrict__ W, int K, int N, __bf16 *__restrict__ Wt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K * N) return;
+__device__ __forceinline__ void transpose_elem(const __bf16 *__restrict__ W, int K, int N, int i,
+                                               __bf16 *__restrict__ Wt) {
   const int k = i / N, n = i % N;
   Wt[(int64_t)n * K + k] = W[i];
+}
+
+// W1 [192][256] -> W1t [256][192] and W2 [256][256] -> W2t in one launch
+// (elements 0 .. 192*256-1 of the grid: W1, then W2)
+__global__ void k_transpose_w12(const __bf16 *__restrict__ W1, __bf16 *__restrict__ W1t,
+                                const __bf16 *__restrict__ W2, __bf16 *__restrict__ W2t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kIn * kHid) transpose_elem(W1, kIn, kHid, i, W1t);
+  else if (i < kIn * kHid + kHid * kHid) transpose_elem(W2, kHid, kHid, i - kIn * kHid, W2t);
 }
 
 
@@ -1543,10 +1553,8 @@ extern "C" int pasur_mlp_transpose(const pasur_mlp_weights *w, uint16_t *W1t, ui
     return PASUR_E_INVAL;
   }
   hipStream_t s = (hipStream_t)stream;
-  k_transpose_bf16<<<blocks(kIn * kHid), 256, 0, s>>>((const __bf16 *)w->W1, kIn, kHid,
-                                                      (__bf16 *)W1t);
-  k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid,
-                                                       (__bf16 *)W2t);
+  k_transpose_w12<<<blocks(kIn * kHid + kHid * kHid), 256, 0, s>>>(
+      (const __bf16 *)w->W1, (__bf16 *)W1t, (const __bf16 *)w->W2, (__bf16 *)W2t);
   PASUR_TRY_HIP(hipGetLastError());
   return PASUR_OK;
 }
@@ -1588,9 +1596,8 @@ int fused_forward(const pasur_mlp_weights *w, const uint16_t *X, int64_t M, floa
     }
     W1t = Wt;
     W2t = Wt + (size_t)kIn * kHid;
-    k_transpose_bf16<<<blocks(kIn * kHid), 256, 0, s>>>((const __bf16 *)w->W1, kIn, kHid, Wt);
-    k_transpose_bf16<<<blocks(kHid * kHid), 256, 0, s>>>((const __bf16 *)w->W2, kHid, kHid,
-                                                         Wt + (size_t)kIn * kHid);
+    k_transpose_w12<<<blocks(kIn * kHid + kHid * kHid), 256, 0, s>>>(
+        (const __bf16 *)w->W1, Wt, (const __bf16 *)w->W2, Wt + (size_t)kIn * kHid);
   }
   kern<<<(unsigned)((M + IM - 1) / IM), 64 * kInferWaves, kInferLds, s>>>(
       (int)M, (const __bf16 *)X, W1t, w->b1, W2t, w->b2, (const __bf16 *)w->W3, w->b3, Y,

@@ -74,9 +74,9 @@ def make_problem(seed, n_par=300):
 
 
 # about 900 rows (one row chunk per weight gradient, ragged in its last K
-# step) and about 6000 (six chunks, the last ragged); with X 8 bytes off a
-# 16-byte boundary the forward and dW1 take the GEMM path instead of the
-# fused forward and the whole-gradient kernel
+# step) and about 6000 (six chunks, the last ragged); with X and W2 8 bytes
+# off a 16-byte boundary the forward and dW1 take the GEMM path (element-wise
+# operand loads) instead of the fused forward and the whole-gradient kernel
 @pytest.mark.parametrize("n_par,x_off", [(300, 0), (2000, 0), (300, 4)])
 def test_mlp_forward_backward_match_oracle(n_par, x_off):
     pa = require_gpu()
@@ -98,6 +98,12 @@ def test_mlp_forward_backward_match_oracle(n_par, x_off):
         assert dX.data_ptr() % 16 == 2 * x_off
     b = model._buffers(M)
     w = model.weights()
+    if x_off:
+        w2 = model.bf[2].view(torch.int16)
+        wbuf = torch.zeros(w2.numel() + x_off, dtype=w2.dtype, device="cuda")
+        wbuf[x_off:] = w2.flatten()
+        w.W2 = wbuf[x_off:].data_ptr()
+        assert w.W2 % 16 == 2 * x_off
     pa.mlp_forward(w, dX, M, b["H1"], b["H2"], b["Y"])
     dseg = torch.from_numpy(seg).cuda()
     dts, dtv = torch.from_numpy(tsig).cuda(), torch.from_numpy(tval).cuda()
