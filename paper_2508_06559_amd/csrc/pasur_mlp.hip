@@ -357,7 +357,7 @@ __global__ void k_split_sum(const float *__restrict__ part, int splits, int64_t 
 // the next step's are loaded into registers during this step's MFMAs.  Rows
 // at or past the chunk's end (or M) read as zero.
 constexpr int kWgThreads = 1024;  // threads per workgroup of k_wgrad
-constexpr int kWgRows = 1024;     // rows per chunk at most 256 chunks
+constexpr int kWgRows = 1024;     // fewest rows per chunk (at most 256 chunks)
 template <int NA>
 __global__ void __launch_bounds__(kWgThreads) k_wgrad(const __bf16 *__restrict__ A,
                                                        const __bf16 *__restrict__ G, int M,
