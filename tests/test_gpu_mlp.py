@@ -246,6 +246,37 @@ def test_forward_output_layer_both_paths():
     assert np.all(np.abs(Ya - Yo) <= bY)
 
 
+# one row; 33 rows (one chunk of two K steps, the second ragged); and row
+# counts just past the weight-gradient chunk size (1025 rows: chunks of 544
+# and 481; 4097: four of 832 and one of 769)
+@pytest.mark.parametrize("M", [1, 33, 1025, 4097])
+def test_mlp_backward_edge_sizes(M):
+    pa = require_gpu()
+    from paper_2508_06559_amd import learn
+    import torch
+    print(f"[mlp] backward edge size M={M}", flush=True)
+    rng = np.random.default_rng(100 + M)
+    X = (rng.random((M, omlp.N_IN)) < 0.25).astype(np.float64)
+    X[:, 156:167] = rng.normal(0, 0.5, (M, 11))
+    X = omlp.bf16_round(X)
+    W = omlp.init_weights(rng)
+    W[1] = rng.normal(0, 0.1, 256)
+    W[3] = rng.normal(0, 0.1, 256)
+    W[5] = rng.normal(0, 0.1, 2)
+    W = [np.asarray(w, np.float32).astype(np.float64) for w in W]
+    model = learn.WarmStartMLP(0)
+    model.set_weights(W)
+    dX = bf16_tensor(X)
+    b = model._buffers(M)
+    w = model.weights()
+    pa.mlp_forward(w, dX, M, b["H1"], b["H2"], b["Y"])
+    dY = rng.normal(0, 1e-2, (M, 2)).astype(np.float32)
+    pa.mlp_backward(w, dX, b["H1"], b["H2"], torch.from_numpy(dY).cuda(), M, model.grads())
+    torch.cuda.synchronize()
+    H1g, H2g = from_bf16(b["H1"][:M]), from_bf16(b["H2"][:M])
+    check_gradients(model, W, X, H1g, H2g, dY.astype(np.float64))
+
+
 def test_mlp_backward_full_size():
     """At the size the benchmark trains on (2^18 rows): the weight gradients
     take 256 row chunks of 1024, db1 the 2048 row tiles of the dH1 product, db2, dW3
