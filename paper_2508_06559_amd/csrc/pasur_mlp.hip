@@ -132,9 +132,11 @@ struct TileLoader {
 // tile and column (l % 16) of the B tile, K elements 8*(l/16) .. 8*(l/16)+7;
 // the accumulator holds rows 4*(l/16) .. +3 of column (l % 16).
 // MASK selects the ReLU-backward epilogue at compile time (g.mask set), so
-// the plain products do not carry its registers.
+// the plain products do not carry its registers.  256-wide tiles (the ReLU
+// backward over all columns, so that A is read once) hold 128 accumulators
+// per lane and are capped at two waves per SIMD (no spills).
 template <int TI, int TJ, bool MASK>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+__global__ void __launch_bounds__(256, TJ > 4 ? 2 : 1) k_gemm(GemmArgs g) {
   constexpr int BM = 32 * TI, BN = 32 * TJ;
   __shared__ __align__(16) __bf16 As[BM][LDK];
   __shared__ __align__(16) __bf16 Bs[BN][LDK];
@@ -183,7 +185,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     // (the operand tiles are no longer read) and writes it as 16-byte row
     // pieces, eight lanes per 128-byte run, instead of 2-byte stores.
     constexpr int RH = 8 * TI, CW = 16 * TJ, SS = CW + 8;  // rows per half, columns, stride
-    static_assert(2 * RH * SS <= BM * LDK, "two waves' halves fit one operand tile");
+    static_assert(MASK || 2 * RH * SS <= BM * LDK, "two waves' halves fit one operand tile");
     __bf16 *S = (wave < 2 ? &As[0][0] : &Bs[0][0]) + (wave & 1) * RH * SS;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -219,13 +221,16 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int j = 0; j < TJ; ++j) cs[j] = 0.f;
     if (m0 + BM <= g.M && n0 + BN <= g.N && (g.ldc & 7) == 0 &&
         ((reinterpret_cast<uintptr_t>(g.Cb) | reinterpret_cast<uintptr_t>(g.mask)) & 15) == 0) {
-      // full tile: each wave brings half of its quadrant's mask into LDS with
-      // 16-byte loads, masks its accumulators there in place (each lane its
-      // own elements) and writes the half out as 16-byte row pieces
-      constexpr int RH = 8 * TI, CW = 16 * TJ, SS = CW + 8;
+      // full tile: each wave brings a part (half, or a quarter for 256-wide
+      // tiles) of its quadrant's mask into LDS with 16-byte loads, masks its
+      // accumulators there in place (each lane its own elements) and writes
+      // the part out as 16-byte row pieces
+      constexpr int H = TJ > 4 ? 4 : 2;                        // parts per quadrant
+      constexpr int RH = 16 * TI / H, CW = 16 * TJ, SS = CW + 8;  // rows per part, columns, stride
+      static_assert(2 * RH * SS <= BM * LDK, "two waves' parts fit one operand tile");
       __bf16 *S = (wave < 2 ? &As[0][0] : &Bs[0][0]) + (wave & 1) * RH * SS;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < H; ++h) {
         const int64_t base = (int64_t)(m0 + wm + h * RH) * g.ldc + n0 + wn;
         for (int c = lane; c < RH * CW / 8; c += 64) {
           const int row = c / (CW / 8), col = (c % (CW / 8)) * 8;
@@ -234,13 +239,13 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         }
         __syncthreads();
 #pragma unroll
-        for (int ii = 0; ii < TI / 2; ++ii)
+        for (int ii = 0; ii < TI / H; ++ii)
 #pragma unroll
           for (int j = 0; j < TJ; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int row = ii * 16 + 4 * (lane >> 4) + r, col = j * 16 + (lane & 15);
-              const float v = (float)S[row * SS + col] > 0.f ? acc[h * (TI / 2) + ii][j][r] : 0.f;
+              const float v = (float)S[row * SS + col] > 0.f ? acc[h * (TI / H) + ii][j][r] : 0.f;
               S[row * SS + col] = (__bf16)v;
               cs[j] += v;
             }
@@ -314,7 +319,11 @@ inline int row_tiles(int M, int N) { return (M + (big_tiles(M, N) ? 127 : 63)) /
 int gemm(GemmArgs g, int splits, hipStream_t s);
 
 int gemm(GemmArgs g, int splits, hipStream_t s) {
-  if (big_tiles(g.M, g.N) && splits == 1) {
+  if (g.mask && g.N == 256 && g.M >= 128 && splits == 1) {
+    // the ReLU backward over all 256 columns in one tile: A (dH2) read once
+    dim3 grid(1u, (unsigned)((g.M + 127) / 128), 1u);
+    k_gemm<4, 8, true><<<grid, 256, 0, s>>>(g);
+  } else if (big_tiles(g.M, g.N) && splits == 1) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), (unsigned)splits);
     if (g.mask)
       k_gemm<4, 4, true><<<grid, 256, 0, s>>>(g);
