@@ -476,9 +476,12 @@ int pasur_mlp_transpose(const pasur_mlp_weights *w, uint16_t *W1t, uint16_t *W2t
 /* Gradients of the loss with respect to the weights given dY [M][2] (FP32);
  * dY is rounded to BF16 for its products (db3 sums it in FP32).  H1 and H2 must be 8-byte aligned
  * (PASUR_E_INVAL otherwise).  The weight gradients reduce over the M rows in
- * FP32 partials of row chunks, summed in chunk order (deterministic).  Uses
- * stream-ordered scratch: the two hidden gradients (BF16, [M][256] each) and
- * up to 256 partial 256x256 FP32 gradients. */
+ * FP32 partials of row chunks, summed in chunk order (deterministic).  Its
+ * scratch (the two hidden gradients, BF16 [M][256] each, and up to 256
+ * partial 256x256 FP32 gradients: about 0.33 GB for M = 2^18) is kept per
+ * (device, stream) between calls: allocated stream-ordered when a call needs
+ * more than it holds, held until the process ends.  Calls on one stream
+ * from several host threads at once race on it. */
 int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X, const uint16_t *H1,
                        const uint16_t *H2, const float *dY, int64_t M, pasur_mlp_grads *g,
                        void *stream);

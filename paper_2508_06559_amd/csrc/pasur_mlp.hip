@@ -9,7 +9,9 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <type_traits>
 
 using namespace pasur;
@@ -1141,6 +1143,36 @@ extern "C" int pasur_mlp_forward(const pasur_mlp_weights *w, const uint16_t *X, 
   return PASUR_OK;
 }
 
+namespace {
+// The backward pass's workspace, kept per (device, stream) between calls:
+// stream order finishes one call's use before the next call's kernels run,
+// and a kept block spares every call the stream-ordered allocation and free
+// (each of which holds up the queue).  Grown stream-ordered when a call
+// needs more; held until the process ends.
+std::mutex g_bwd_mu;
+std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_bwd_ws;
+
+int backward_workspace(hipStream_t s, size_t bytes, void **out) {
+  int dev = 0;
+  PASUR_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_bwd_mu);
+  std::pair<void *, size_t> &ws = g_bwd_ws[std::make_pair(dev, s)];
+  if (ws.second < bytes) {
+    if (ws.first) (void)hipFreeAsync(ws.first, s);
+    ws = std::make_pair(nullptr, (size_t)0);
+    void *p = nullptr;
+    const hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess) {
+      set_error("MLP backward workspace (%zu bytes): %s", bytes, hipGetErrorString(e));
+      return PASUR_E_NOMEM;
+    }
+    ws = std::make_pair(p, bytes);
+  }
+  *out = ws.first;
+  return PASUR_OK;
+}
+}  // namespace
+
 extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
                                   const uint16_t *H1, const uint16_t *H2, const float *dY,
                                   int64_t M, pasur_mlp_grads *gr, void *stream) {
@@ -1164,22 +1196,21 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
   const int64_t wsplits0 = std::min<int64_t>(256, (M + kWgRows - 1) / kWgRows);
   const int wchunk = (int)(((M + wsplits0 - 1) / wsplits0 + BK - 1) / BK * BK);
   const int wsplits = (int)((M + wchunk - 1) / wchunk);
-  __bf16 *G2b = nullptr, *G1b = nullptr;
-  float *part = nullptr;
   // split-K partials of the weight gradients, or the row-chunk partials of
   // the bias gradients and of the output layer's weight gradient, or the
   // dH1 product's row-tile partials of db1
   const size_t part_n = std::max({(size_t)std::max(splits, wsplits) * kHid * kHid,
                                   (size_t)kColChunks * (kHid * kOut + kOut + kHid),
                                   (size_t)row_tiles(m, kHid) * kHid});
-  hipError_t e = hipMallocAsync((void **)&G2b, sizeof(__bf16) * (size_t)m * kHid, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&G1b, sizeof(__bf16) * (size_t)m * kHid, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&part, sizeof(float) * part_n, s);
+  // workspace: dH2 and dH1 in BF16, then the partials
+  const size_t gbytes = align_up(sizeof(__bf16) * (size_t)m * kHid, 256);
+  void *ws = nullptr;
+  PASUR_TRY(backward_workspace(s, 2 * gbytes + sizeof(float) * part_n, &ws));
+  __bf16 *G2b = reinterpret_cast<__bf16 *>(ws);
+  __bf16 *G1b = reinterpret_cast<__bf16 *>(reinterpret_cast<char *>(ws) + gbytes);
+  float *part = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + 2 * gbytes);
+  hipError_t e = hipSuccess;
   int st = PASUR_OK;
-  if (e != hipSuccess) {
-    set_error("MLP backward workspace: %s", hipGetErrorString(e));
-    st = PASUR_E_NOMEM;
-  }
   auto dW = [&](const __bf16 *Act, int kin, const __bf16 *G, int nout, float *out) -> int {
     // out[kin, nout] = Act^T G, reduced over the M rows in chunks
     if (nout == kHid && (kin == kHid || kin == kIn) &&
@@ -1240,9 +1271,6 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
       st = PASUR_E_HIP;
     }
   }
-  (void)hipFreeAsync(G2b, s);
-  (void)hipFreeAsync(G1b, s);
-  (void)hipFreeAsync(part, s);
   return st;
 }
 
