@@ -443,34 +443,42 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const __bf16 *__restrict__
 // kColChunks partials of each column.
 constexpr int kColChunks = 1024;
 
-// Second pass of the column sums: one wave per column, lane j adds partials
-// j, j + 64, ... in order, then the lanes combine in a fixed shuffle tree
+// Second pass of the column sums: one workgroup of kMergeThreads per column,
+// thread j adds partials j, j + kMergeThreads, ... in order, then each
+// wave's lanes combine in a fixed shuffle tree and the waves in order
 // (deterministic).
+constexpr int kMergeThreads = 256;
 __device__ __forceinline__ void col_merge_one(const float *__restrict__ part, int chunks, int N,
                                               int n, float *__restrict__ out) {
-  const int lane = threadIdx.x;
+  __shared__ float wsum[kMergeThreads / 64];
+  const int t = threadIdx.x, lane = t & 63;
   float s = 0.f;
-  // eight loads in flight per lane; the sum still runs in chunk order
-#pragma unroll 8
-  for (int z = lane; z < chunks; z += 64) s += part[(int64_t)z * N + n];
+  // four loads in flight per thread; the sum still runs in chunk order
+#pragma unroll 4
+  for (int z = t; z < chunks; z += kMergeThreads) s += part[(int64_t)z * N + n];
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
-  if (lane == 0) out[n] = s;
+  if (lane == 0) wsum[t >> 6] = s;
+  __syncthreads();
+  if (t == 0) {
+    float r = wsum[0];
+#pragma unroll
+    for (int k = 1; k < kMergeThreads / 64; ++k) r += wsum[k];
+    out[n] = r;
+  }
 }
 
-__global__ void __launch_bounds__(64) k_col_merge(const float *__restrict__ part, int chunks, int N,
-                                                  float *__restrict__ out) {
+__global__ void __launch_bounds__(kMergeThreads)
+    k_col_merge(const float *__restrict__ part, int chunks, int N, float *__restrict__ out) {
   col_merge_one(part, chunks, N, blockIdx.x, out);
 }
 
 // Three column merges in one launch (blocks 0..Na-1: the first array, then
 // the second, then the third), each column as k_col_merge sums it.
-__global__ void __launch_bounds__(64) k_col_merge3(int chunks, const float *__restrict__ pa, int Na,
-                                                   float *__restrict__ oa,
-                                                   const float *__restrict__ pb, int Nb,
-                                                   float *__restrict__ ob,
-                                                   const float *__restrict__ pc, int Nc,
-                                                   float *__restrict__ oc) {
+__global__ void __launch_bounds__(kMergeThreads)
+    k_col_merge3(int chunks, const float *__restrict__ pa, int Na, float *__restrict__ oa,
+                 const float *__restrict__ pb, int Nb, float *__restrict__ ob,
+                 const float *__restrict__ pc, int Nc, float *__restrict__ oc) {
   const int n = blockIdx.x;
   if (n < Na) col_merge_one(pa, chunks, Na, n, oa);
   else if (n < Na + Nb) col_merge_one(pb, chunks, Nb, n - Na, ob);
@@ -1243,9 +1251,8 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     float *partr = partb + (size_t)kColChunks * kOut;
     k_out_relu_back<<<kColChunks, 256, 0, s>>>((const __bf16 *)H2, dY, (const __bf16 *)w->W3, M,
                                                rchunk, part3, partb, G2b, partr);
-    k_col_merge3<<<kHid * kOut + kOut + kHid, 64, 0, s>>>(kColChunks, part3, kHid * kOut, gr->dW3,
-                                                          partb, kOut, gr->db3, partr, kHid,
-                                                          gr->db2);
+    k_col_merge3<<<kHid * kOut + kOut + kHid, kMergeThreads, 0, s>>>(
+        kColChunks, part3, kHid * kOut, gr->dW3, partb, kOut, gr->db3, partr, kHid, gr->db2);
     st = dW((const __bf16 *)H1, kHid, G2b, kHid, gr->dW2);
   }
   if (!st) {
@@ -1260,7 +1267,7 @@ extern "C" int pasur_mlp_backward(const pasur_mlp_weights *w, const uint16_t *X,
     g.mask = (const __bf16 *)H1; g.colpart = part;
     st = gemm(g, 1, s);
     if (!st) {
-      k_col_merge<<<kHid, 64, 0, s>>>(part, row_tiles(m, kHid), kHid, gr->db1);
+      k_col_merge<<<kHid, kMergeThreads, 0, s>>>(part, row_tiles(m, kHid), kHid, gr->db1);
       st = dW((const __bf16 *)X, kIn, G1b, kHid, gr->dW1);
     }
   }
