@@ -440,8 +440,10 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const __bf16 *__restrict__
 // Column sums over the M rows (bias gradients, the output layer's weight
 // gradient) in two deterministic passes: one workgroup per chunk of rows
 // writes its partial sums part[chunk][n]; k_col_merge then adds the
-// kColChunks partials of each column.
-constexpr int kColChunks = 1024;
+// kColChunks partials of each column.  2048 chunks: eight 4-wave workgroups
+// per CU, all resident at once (1024 left half the wave slots empty; 4096
+// made the merges longer than the pass got shorter).
+constexpr int kColChunks = 2048;
 
 // Second pass of the column sums: one workgroup of kMergeThreads per column,
 // thread j adds partials j, j + kMergeThreads, ... in order, then each

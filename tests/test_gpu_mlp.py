@@ -280,7 +280,7 @@ def test_mlp_backward_edge_sizes(M):
 def test_mlp_backward_full_size():
     """At the size the benchmark trains on (2^18 rows): the weight gradients
     take 256 row chunks of 1024, db1 the 2048 row tiles of the dH1 product, db2, dW3
-    and db3 1024 full row chunks.  All six gradients against the oracle's
+    and db3 2048 full row chunks.  All six gradients against the oracle's
     backward on the GPU's own activations."""
     pa = require_gpu()
     from paper_2508_06559_amd import learn
