@@ -369,10 +369,10 @@ def bench_full(args):
                               "auto": pa.SCHED_AUTO}[args.sched], args.block)
     round_ms = []
 
-    def step(record_rounds=False):
+    def step(record_rounds=False, on_round=None):
         s = pa.SubgameSolver(deck, 0, roots, dtype=dtype)
         ev = [] if record_rounds else None
-        s.solve(iters, params, round_events=ev)
+        s.solve(iters, params, round_events=ev, on_round=on_round)
         bra, brb, _ = s.exploitability()
         torch.cuda.synchronize()
         if ev is not None:
@@ -383,19 +383,28 @@ def bench_full(args):
         s.free()
         return sizes, ex, V0
 
-    def per_kernel():
-        """Algorithmic bytes, seconds and launches per kernel id over the
-        recorded launches (HIP events on the launch stream)."""
+    def read_records():
+        """The recorded sweep launches as (kernel id, algorithmic bytes,
+        seconds from HIP events on the launch stream); the streaming
+        schedule's per-call set-up (id 8) is not a sweep and is left out."""
         kern, lev, ms, work = pa.profile_read()
+        return [(int(kern[i]), all_launch_bytes(int(kern[i]), int(lev[i]), work[i], T),
+                 float(ms[i]) * 1e-3) for i in range(len(kern)) if int(kern[i]) != 8]
+
+    def per_kernel(recs=None):
+        """Algorithmic bytes, seconds and launches per kernel id."""
         per = {}
-        for i in range(len(kern)):
-            k = int(kern[i])
-            if k == 8:  # the streaming schedule's per-call set-up, not a sweep
-                continue
+        for k, b1, t1 in (read_records() if recs is None else recs):
             b, t, c = per.get(k, (0.0, 0.0, 0))
-            per[k] = (b + all_launch_bytes(k, int(lev[i]), work[i], T), t + float(ms[i]) * 1e-3,
-                      c + 1)
+            per[k] = (b + b1, t + t1, c + 1)
         return per
+
+    # launch records per round in the first warm-up step: the count of
+    # records (sweep launches enqueued, id 8 included) after each round
+    bounds = []
+
+    def mark(r):
+        bounds.append((r, pa.profile_count()))
 
     # Warm-up steps time every sweep launch, which picks the dominant kernel
     # (the largest share of time) and gives the whole-sweep figures; the
@@ -403,11 +412,24 @@ def bench_full(args):
     # warm-up, the timed steps record every launch.
     pa.profile_enable(True)
     per_all = None
+    round_alg = {}
     for w in range(args.warmup):
-        sizes, ex, V0 = step()
+        sizes, ex, V0 = step(on_round=mark if w == 0 else None)
         log(f"[bench] warmup {w + 1}/{args.warmup} done, exploitability {ex:.3e}")
     if args.warmup:
-        per_all = per_kernel()
+        kern, lev, ms, work = pa.profile_read()
+        recs_all = [(int(kern[i]), all_launch_bytes(int(kern[i]), int(lev[i]), work[i], T),
+                     float(ms[i]) * 1e-3) for i in range(len(kern))]
+        prev = 0
+        for r, cnt in bounds:
+            part = [x for x in recs_all[prev:cnt] if x[0] != 8]
+            b = sum(x[1] for x in part)
+            t = sum(x[2] for x in part)
+            lds = sum(x[1] for x in part if x[0] == 2)  # k_cfr_seg, every segment in LDS
+            seg = sum(x[1] for x in part if x[0] in (2, 3))
+            round_alg[r] = (b, t, lds / seg if seg else None)
+            prev = cnt
+        per_all = per_kernel([x for x in recs_all if x[0] != 8])
         dom = max(per_all, key=lambda k: per_all[k][1])
         pa.profile_enable(True)
         pa.profile_select([dom])
@@ -438,11 +460,19 @@ def bench_full(args):
     for r, n in enumerate(sizes):
         e_r = sum(n[1:])
         ms_r = round_ms[5 - r] if len(round_ms) == 6 else None
+        b_r, t_r, lds_r = round_alg.get(r, (0.0, 0.0, None))
         rounds.append({"round": r + 1, "nodes": int(sum(n)), "edges": int(e_r),
                        "schedule": (("stream" if sum(n) >= 9_000_000 else "persistent segments")
                                     if args.sched == "auto" else args.sched),
                        "dcfr_ms": ms_r,
-                       "node_updates_per_s": e_r * iters / (ms_r * 1e-3) if ms_r else None})
+                       "node_updates_per_s": e_r * iters / (ms_r * 1e-3) if ms_r else None,
+                       # algorithmic bytes of the round's sweep launches over
+                       # their summed launch time (first warm-up step)
+                       "alg_GBs": b_r / t_r / 1e9 if t_r else None,
+                       "alg_frac": b_r / t_r / 1e9 / HBM_PEAK_GBS if t_r else None,
+                       # share of the persistent kernel's algorithmic bytes in
+                       # launches that kept every segment's state in LDS
+                       "lds_resident_share": lds_r})
     out = {"metric": METRIC, "value": value, "unit": "node-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",

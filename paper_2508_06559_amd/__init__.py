@@ -634,6 +634,14 @@ def profile_select(kernels):
     _check(lib().pasur_profile_select(mask), "pasur_profile_select")
 
 
+def profile_count() -> int:
+    """Number of sweep launches recorded so far (reads no timings, so it
+    does not wait for the GPU)."""
+    n = C.c_int64()
+    _check(lib().pasur_profile_read(0, None, None, None, None, C.byref(n)), "pasur_profile_read")
+    return n.value
+
+
 def profile_read():
     """Recorded sweep launches: arrays (kernel, level, milliseconds, work)
     with work[i] = (edges, internal nodes, roots, level-7 nodes, iterations)."""

@@ -61,10 +61,12 @@ class SubgameSolver:
         return sum(rr.fgt.edges() for rr in self.rounds)
 
     def solve(self, iters: int, params=None, value_mode: int = V_ITERATE_MEAN,
-              round_events=None):
+              round_events=None, on_round=None):
         """Backward DCFR: ``iters`` iterations per round.  If ``round_events``
         is a list, a (start, end) pair of CUDA events around each round's
-        iterations is appended to it (last round first)."""
+        iterations is appended to it (last round first).  ``on_round(r)``,
+        if given, is called on the host once round r's iterations are
+        enqueued (last round first)."""
         torch = self.torch
         params = params if params is not None else paper_params()
         V = None
@@ -80,6 +82,8 @@ class SubgameSolver:
             if round_events is not None:
                 ev[1].record()
                 round_events.append(ev)
+            if on_round is not None:
+                on_round(rr.round)
             average_strategy(st, self.stream)
             rr.V = torch.empty(rr.fgt.n[0], dtype=torch.float64, device="cuda")
             round_values(st, value_mode, rr.V, self.stream)
