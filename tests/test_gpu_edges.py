@@ -1,8 +1,9 @@
 """Edge cases of the round path, through the C ABI: an empty root list is
 refused, zero iterations leave the state untouched under every schedule,
 averaging before any iteration gives the uniform strategy, the iterate-mean
-value needs at least one iteration, and the smallest subgame (one root of
-the final round) matches the FP64 oracle under every schedule."""
+value needs at least one iteration, the smallest subgame (one root of the
+final round) matches the FP64 oracle under every schedule, and the solver's
+per-round hook sees the rounds in order."""
 import numpy as np
 import pytest
 
@@ -99,3 +100,24 @@ def test_one_root_final_round_matches_oracle(sched):
         assert np.max(np.abs(to_np(st.R[l]) - c.get(oracle.CF_R, l))) <= 1e-9, l
     assert np.max(np.abs(to_np(s.rounds[0].V) - V)) <= 1e-9
     s.free()
+
+
+def test_solve_round_hook_and_profile_count():
+    """SubgameSolver.solve calls on_round once per round, last round first,
+    after the round's iterations are enqueued; the profile's record count
+    (read without waiting for the GPU) grows with every round's sweeps."""
+    pa = require_gpu()
+    deck, roots = synth.two_round_root(1)
+    print("[edges] on_round hook, two-round subgame of deal 1", flush=True)
+    s = pa.SubgameSolver(deck, 4, roots, dtype=pa.PASUR_F32)
+    seen = []
+    pa.profile_enable(True)
+    try:
+        s.solve(5, on_round=lambda r: seen.append((r, pa.profile_count())))
+        total = len(pa.profile_read()[0])
+    finally:
+        pa.profile_enable(False)
+        s.free()
+    assert [r for r, _ in seen] == [5, 4]
+    counts = [c for _, c in seen]
+    assert 0 < counts[0] < counts[1] <= total
